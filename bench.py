@@ -1,0 +1,175 @@
+"""Throughput of PT + isoenergetic cluster moves on one MI355X.
+
+A step is one fused sweep block (sweeps_per_step simulation steps: Metropolis
+sweep, ICM at the cold temperatures, PT) over the whole batch of the workload:
+1024 3D L=8 Gaussian instances, 20 temperatures x 4 replicas (the batched
+3D workload).  Inputs are synthetic and resident in HBM before timing starts.
+
+Prints one JSON line:  value = spin-flip attempts/s over the whole job; also
+ICM moves/s, the same measured with plain per-instance launches, the roofline
+of the fused kernel and the CPU oracle's rate on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# VALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T 32-bit lane-ops/s
+VALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=16)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="3d_L8_gauss_1024inst")
+    ap.add_argument("--sweeps-per-step", type=int, default=256)
+    ap.add_argument("--threads", type=int, default=512)
+    ap.add_argument("--icm-slots", type=int, default=8)
+    ap.add_argument("--graph", type=int, default=1)
+    ap.add_argument("--per-instance-sample", type=int, default=32)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-per-instance", action="store_true")
+    return ap.parse_args()
+
+
+def algorithmic_bytes_per_sweep(spec, N, n_bonds, jbytes):
+    """2 bytes (int8 spin read + write) per attempt plus the couplings once."""
+    S = spec["n_temps"] * spec["n_replicas"]
+    return 2 * S * N + n_bonds * jbytes
+
+
+def cpu_baseline(name, spec, seconds):
+    """The CPU oracle on the host cores, over a bounded sample of the workload."""
+    import concurrent.futures as cf
+
+    import oracle
+    from paper_1501_05630_amd import inputs
+
+    cores = os.cpu_count() or 1
+    cores = min(cores, 16)
+    N = inputs.n_sites(spec["topology"], spec["L"])
+    S = spec["n_temps"] * spec["n_replicas"]
+    # calibrate: sweeps per instance so that the sample takes ~`seconds`
+    J, temps, kc, _ = inputs.workload_instance(name, 0)
+    o = oracle.Sim(spec["topology"], spec["L"], J, temps, spec["n_replicas"], kc,
+                   seed=inputs.MASTER_SEED, instance_key=0, j_scale=spec["j_scale"])
+    o.init_hot()
+    t0 = time.perf_counter()
+    o.run(4)
+    per_sweep = (time.perf_counter() - t0) / 4
+    n_inst = cores
+    sweeps = max(4, int(seconds / max(per_sweep, 1e-9)))
+
+    def job(b):
+        J, temps, kc, _ = inputs.workload_instance(name, b)
+        s = oracle.Sim(spec["topology"], spec["L"], J, temps, spec["n_replicas"], kc,
+                       seed=inputs.MASTER_SEED, instance_key=b, j_scale=spec["j_scale"])
+        s.init_hot()
+        s.run(sweeps)
+        return s.stats()["icm_moves"]
+
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=cores) as ex:
+        moves = sum(ex.map(job, range(n_inst)))
+    dt = time.perf_counter() - t0
+    return {"value": S * N * sweeps * n_inst / dt, "unit": "spin-flip attempts/s", "cores": cores,
+            "kind": "oracle", "icm_moves_per_s": moves / dt,
+            "sample": f"{n_inst} instances x {sweeps} sweeps of {name}, one oracle per thread"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_1501_05630_amd import icm, inputs
+
+    name = args.workload
+    spec = inputs.WORKLOADS[name]
+    n_inst = spec["n_instances"]
+    N = inputs.n_sites(spec["topology"], spec["L"])
+    S = spec["n_temps"] * spec["n_replicas"]
+    ctx = icm.Context(arena_bytes=2 << 30, seed=inputs.MASTER_SEED)
+    hs = []
+    n_bonds = None
+    for b in range(n_inst):
+        J, temps, kc, _ = inputs.workload_instance(name, b)
+        hs.append(ctx.icm_add_instance(spec["topology"], spec["L"], J, temps, spec["n_replicas"], kc,
+                                       instance_key=b, j_scale=spec["j_scale"]))
+        ctx.icm_init_states(hs[-1])
+        if n_bonds is None:
+            n_bonds = {inputs.SQUARE2D: 2 * N, inputs.CUBIC3D: 3 * N,
+                       inputs.CHIMERA: 16 * spec["L"] ** 2 + 8 * spec["L"] * (spec["L"] - 1)}[spec["topology"]]
+            n_moves_per_sweep = kc * spec["n_replicas"] // 2
+    jbytes = 4 if spec["kind"] == "gauss" else 1
+    spsw = args.sweeps_per_step
+    ctx.icm_set_run_config(threads=args.threads, sweeps_per_launch=spsw, use_graph=args.graph,
+                           icm_slots=args.icm_slots)
+    stream = ctx.stream
+    for _ in range(args.warmup):
+        ctx.icm_run(hs, spsw)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        ctx.icm_run(hs, spsw)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    sweeps = spsw * args.steps
+    attempts = S * N * sweeps * n_inst
+    secs = ms / 1e3
+    value = attempts / secs
+    icm_moves = n_moves_per_sweep * sweeps * n_inst
+    launch_ms = ms / args.steps  # one launch of the fused kernel per step
+    bytes_per_launch = algorithmic_bytes_per_sweep(spec, N, n_bonds, jbytes) * spsw * n_inst
+    achieved_gbs = bytes_per_launch / (launch_ms / 1e3) / 1e9
+
+    out = {
+        "metric": "spin-flip attempts/s + ICM moves/s, batched vs per-instance; % HBM roofline",
+        "value": value, "unit": "spin-flip attempts/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": launch_ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if spec["kind"] == "gauss" else "i32",
+        "data": "synthetic (seeded disorder, hot start)",
+        "config": {"workload": name, "instances": n_inst, "topology": inputs.TOPOLOGY_NAMES[spec["topology"]],
+                   "L": spec["L"], "N": N, "temps": spec["n_temps"], "replicas": spec["n_replicas"],
+                   "icm_temps": kc, "sweeps_per_step": spsw, "threads": args.threads,
+                   "graph": bool(args.graph), "parallelism": "single GPU, one workgroup per instance"},
+        "icm_moves_per_s": icm_moves / secs,
+        "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_attempt": algorithmic_bytes_per_sweep(spec, N, n_bonds, jbytes) / (S * N)},
+    }
+    if not args.no_per_instance:
+        sample = hs[: args.per_instance_sample]
+        ctx.icm_set_run_config(use_graph=0)
+        ctx.icm_run_per_instance(sample, spsw)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        ctx.icm_run_per_instance(sample, spsw)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        pms = ev0.elapsed_time(ev1)
+        out["per_instance"] = {"value": S * N * spsw * len(sample) / (pms / 1e3),
+                               "icm_moves_per_s": n_moves_per_sweep * spsw * len(sample) / (pms / 1e3),
+                               "sample": f"{len(sample)} instances, one launch each"}
+        out["batched_over_per_instance"] = value / out["per_instance"]["value"]
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(name, spec, args.cpu_seconds)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,200 @@
+/*
+ * libicm — parallel tempering with isoenergetic cluster moves (ICM) for Ising
+ * spin glasses on one MI355X (gfx950).
+ *
+ * Method: Zhu, Ochoa, Katzgraber, "Efficient Cluster Algorithm for Spin
+ * Glasses in Any Space Dimension" (arXiv:1501.05630).  One simulation step is
+ * the paper's "Isoenergetic cluster algorithm" list: (1) a Metropolis sweep in
+ * every replica, (2a) the spin-reversal flip when more than N/2 sites have
+ * q_i = -1, (2b) one Houdayer cluster move (cluster = connected q = -1 domain of
+ * a random q = -1 site, flipped in both replicas; "Reminder: Houdayer cluster
+ * algorithm" paragraph) at the coldest temperatures, (3) parallel tempering.
+ *
+ * Conventions fixed by this library where the paper is silent:
+ *   - H = -sum over bonds (each once) J_ij s_i s_j.
+ *   - square2d (L even) and cubic3d (L even) are periodic, site
+ *     i = x + L*y (+ L*L*z); chimera is C x C cells of K_{4,4} with open
+ *     boundaries, site i = 8*(row*C + col) + u (u<4 couple vertically, u>=4
+ *     horizontally).  Coupling layouts: [N][2], [N][3], [C*C][24] (see
+ *     icm_instance_desc::couplings).
+ *   - walkers w = h*R + r (h = starting temperature index, r = chain); PT swaps
+ *     move temperature labels between walkers of one chain; ICM pairs chains
+ *     (2p, 2p+1) at the same temperature.
+ *   - the Metropolis sweep updates every colour-0 site, then every colour-1 site
+ *     of a proper 2-colouring (lattices: (x+y[+z]) mod 2; chimera:
+ *     (row+col+[u>=4]) mod 2).
+ *   - random numbers: Philox4x32-10 (Salmon et al., SC'11), key (seed,
+ *     instance_key), counters: Metropolis (i, t, w>>2, 0) word w&3; hot start
+ *     (i, 0, w>>2, 1) word w&3, spin -1 iff bit 31 is set; ICM
+ *     (k*(R/2)+p, t, 0, 2) word 0; PT (k, t, r, 3) word 0.  t is the sweep index.
+ *   - integer couplings (J = j / j_scale): Metropolis accepts dE > 0 iff
+ *     u < min(floor(2^32 exp(-(beta*dE)/j_scale)), 2^32-1); the PT rule uses the
+ *     same form with (beta_k - beta_k+1) and the energy gap.  Energies are exact
+ *     integers in units of 1/j_scale.
+ *   - float couplings: J is rounded to the 2^-32 grid (a no-op for |J| >= 2^-8);
+ *     local fields and energies are exact on that grid; dE > 0 is accepted iff
+ *     u * 2^-32 < exp(-(beta*dE)) evaluated in double; energies are reported in
+ *     units of 2^-32.
+ *
+ * Memory: the caller hands the library one device buffer (the arena, e.g. a
+ * torch uint8 tensor) at icm_create; every device allocation of the library is
+ * carved from it and the library never calls hipMalloc.  The arena must stay
+ * alive until icm_destroy.  Host pointers passed to any call are read or
+ * written before the call returns and are not retained.
+ *
+ * Errors: every call returns ICM_OK (0) or a negative ICM_E_* code; nothing
+ * throws or aborts across this boundary.  A HIP failure returns ICM_E_DEVICE
+ * and poisons the context (every later call returns ICM_E_DEVICE).
+ * icm_last_error() gives a human-readable reason for the last failure.
+ *
+ * Threading: one context per host thread, except icm_submit / icm_poll /
+ * icm_take_result, which may be called from any thread while the serving loop
+ * runs.
+ */
+#ifndef ICM_H
+#define ICM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ICM_OK 0
+#define ICM_E_INVALID -1   /* bad argument or descriptor */
+#define ICM_E_NOMEM -2     /* the arena has no room */
+#define ICM_E_DEVICE -3    /* HIP error; the context is poisoned */
+#define ICM_E_NOTFOUND -4  /* unknown handle or ticket */
+#define ICM_E_BUSY -5      /* serving loop owns the instances / result not ready */
+#define ICM_E_BUFSIZE -6   /* caller buffer too small */
+
+#define ICM_TOPO_SQUARE2D 0
+#define ICM_TOPO_CUBIC3D 1
+#define ICM_TOPO_CHIMERA 2
+
+#define ICM_J_INT8 0 /* couplings int8 j, J = j / j_scale */
+#define ICM_J_F32 1  /* couplings float, rounded to the 2^-32 grid */
+
+#define ICM_FLAG_2A 1            /* step 2a (spin-reversal flip of the 2nd replica) */
+#define ICM_FLAG_PT 2            /* step 3 (parallel tempering) */
+#define ICM_FLAG_RECORD_LABELS 4 /* keep the labels of the last ICM move (parity/debug) */
+#define ICM_FLAG_SKIP_METRO 8    /* diagnostic: a step is ICM (+PT) only */
+
+typedef struct icm_ctx icm_ctx;
+
+/* One disorder instance: graph, couplings, temperature ladder, replicas.
+   Model paragraph of the paper (H, Gaussian disorder) and the Table I
+   parameters (N_T temperatures, ICM on the lowest N_c of them). */
+typedef struct {
+  int32_t topology;      /* ICM_TOPO_* */
+  int32_t L;             /* lattice side (even, >= 2) or chimera cells per side (>= 1) */
+  int32_t jkind;         /* ICM_J_INT8 or ICM_J_F32 */
+  int32_t j_scale;       /* ICM_J_INT8: 1..127 (J = j / j_scale); ignored for F32 */
+  const void* couplings; /* host; square2d [N][2] (+x,+y bonds of site i), cubic3d
+                            [N][3] (+x,+y,+z), chimera [C*C][24]: in-cell bond (u,v),
+                            u<4<=v, at u*4+v-4; bond to the cell below at 16+u (u<4);
+                            bond to the cell on the right at 20+u-4 (u>=4); slots that
+                            would leave the grid must be 0.  F32 values need |J| <= 64. */
+  int32_t n_temps;       /* K >= 1 */
+  const double* temps;   /* host [K], strictly ascending, > 0; k = 0 is the coldest */
+  int32_t n_replicas;    /* R: even, 2 <= R <= 64 */
+  int32_t icm_ntemps;    /* K_c: ICM at the coldest K_c temperatures (0 = off) */
+  uint32_t flags;        /* ICM_FLAG_* */
+  uint32_t instance_key; /* Philox key word 1 (the seed is key word 0) */
+} icm_instance_desc;
+
+typedef struct {
+  uint64_t sweeps;            /* sweeps run since the state was set */
+  uint64_t metro_accepts;     /* accepted single-spin flips */
+  uint64_t icm_moves;         /* cluster moves attempted (including n_minus == 0) */
+  uint64_t icm_nontrivial;    /* moves that flipped a non-empty cluster */
+  uint64_t icm_cluster_sites; /* sum of cluster sizes */
+  uint64_t icm_2a_flips;      /* step-2a spin-reversal flips */
+  uint64_t pt_attempts;       /* PT swap attempts */
+  uint64_t pt_accepts;        /* accepted PT swaps */
+} icm_stats;
+
+/* Launch configuration of icm_run (0 = library default / autotuned). */
+typedef struct {
+  int32_t threads;          /* threads per workgroup: 256, 512 or 1024 */
+  int32_t sweeps_per_launch;/* sweeps fused into one kernel launch */
+  int32_t use_graph;        /* 1: replay launches from a captured hipGraph */
+  int32_t icm_slots;        /* concurrent ICM moves per workgroup (LDS scratch) */
+} icm_run_config;
+
+/* Creates a context on `device`, issuing all work on `hip_stream` (a
+   hipStream_t, NULL = the null stream).  `arena` is a caller-owned device
+   buffer of arena_bytes (>= 1 MiB, 256-byte aligned); `seed` is Philox key
+   word 0 for every instance of the context. */
+int icm_create(icm_ctx** out, int device, void* hip_stream, void* arena, size_t arena_bytes,
+               uint32_t seed);
+int icm_destroy(icm_ctx* ctx);
+
+/* Copies the descriptor (couplings, temperatures) into the arena and returns a
+   handle.  ICM_E_INVALID for a bad descriptor, ICM_E_NOMEM when the arena is
+   full.  The state is all spins up until icm_init_states / icm_set_states. */
+int icm_add_instance(icm_ctx* ctx, const icm_instance_desc* d, int32_t* out_handle);
+int icm_remove_instance(icm_ctx* ctx, int32_t handle);
+/* Arena bytes an instance with this descriptor needs (0 if invalid). */
+size_t icm_instance_bytes(const icm_instance_desc* d);
+
+/* Hot start: every walker draws its spins from Philox; sweep counter = 0. */
+int icm_init_states(icm_ctx* ctx, int32_t handle);
+/* Sets spins [K][R][N] (host, any nonzero int8; < 0 means down) in
+   temperature order, resets temperature labels and gauge, sweep counter =
+   sweep0. */
+int icm_set_states(icm_ctx* ctx, int32_t handle, const int8_t* spins, uint32_t sweep0);
+
+/* Runs n_sweeps simulation steps on every listed instance with batched,
+   fused launches (asynchronous on the context stream). */
+int icm_run(icm_ctx* ctx, const int32_t* handles, int32_t n, uint32_t n_sweeps);
+/* Baseline mode: the same kernels, one instance per launch, no graph. */
+int icm_run_per_instance(icm_ctx* ctx, const int32_t* handles, int32_t n, uint32_t n_sweeps);
+int icm_sync(icm_ctx* ctx);
+int icm_set_run_config(icm_ctx* ctx, const icm_run_config* cfg);
+int icm_get_run_config(icm_ctx* ctx, icm_run_config* cfg);
+
+/* Energies [K][R] in temperature order: raw (int64: units of 1/j_scale, or
+   2^-32 for F32) and/or real (double); either pointer may be NULL.  cap is the
+   number of elements the buffers hold. */
+int icm_read_energies(icm_ctx* ctx, int32_t handle, int64_t* raw, double* real, size_t cap);
+/* Spins [K][R][N] (+1/-1) in temperature order, canonical site order. */
+int icm_read_states(icm_ctx* ctx, int32_t handle, int8_t* out, size_t cap);
+/* Site overlap q = sum_i s_i^(2p) s_i^(2p+1) per (k, pair) [K][R/2] and the
+   link overlap numerator sum over bonds of s_i s_j s'_i s'_j [K][R/2] (Eq. 1
+   of the paper uses q_l = that / N_b).  Either pointer may be NULL. */
+int icm_read_overlaps(icm_ctx* ctx, int32_t handle, int32_t* q_sum, int32_t* ql_sum, size_t cap);
+/* Labels [N] of the last ICM move at temperature k, pair p: minimum site index
+   of the q = -1 component, -1 off the mask; requires ICM_FLAG_RECORD_LABELS.
+   seed = seed site (-1 if no q = -1 site), n_minus = post-2a count. */
+int icm_read_labels(icm_ctx* ctx, int32_t handle, int32_t k, int32_t pair, int32_t* labels,
+                    int32_t* seed, int32_t* n_minus, size_t cap);
+int icm_read_stats(icm_ctx* ctx, int32_t handle, icm_stats* out);
+/* Walker index at (k, r), [K][R] (PT permutation). */
+int icm_read_walkers(icm_ctx* ctx, int32_t handle, int32_t* out, size_t cap);
+uint32_t icm_sweep_index(icm_ctx* ctx, int32_t handle);
+
+/* Serving: a request = descriptor + n_sweeps from a hot start.  The loop
+   admits requests at sweep-block boundaries while the arena has room, keeps
+   their state on the device, runs them batched with whatever else is
+   resident, and retires them when done.  Thread-safe. */
+int icm_serve_start(icm_ctx* ctx, int32_t sweeps_per_block);
+int icm_serve_stop(icm_ctx* ctx);
+int icm_submit(icm_ctx* ctx, const icm_instance_desc* d, uint32_t n_sweeps, uint64_t* ticket);
+/* done = 1 when the result is ready; latency_us = submit-to-retire time. */
+int icm_poll(icm_ctx* ctx, uint64_t ticket, int32_t* done, double* latency_us);
+/* Energies [K][R] raw and states [K][R][N] (either may be NULL); frees the
+   ticket. */
+int icm_take_result(icm_ctx* ctx, uint64_t ticket, int64_t* energies, int8_t* states,
+                    size_t cap_energies, size_t cap_states);
+
+const char* icm_strerror(int code);
+const char* icm_last_error(icm_ctx* ctx);
+/* Bytes of arena in use / total. */
+int icm_arena_usage(icm_ctx* ctx, size_t* used, size_t* total);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

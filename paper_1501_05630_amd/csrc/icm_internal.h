@@ -1,0 +1,87 @@
+// Internal layout shared by the host runtime (icm_runtime.cpp) and the HIP
+// kernels (icm_kernels.hip).  Not part of the public ABI.
+#pragma once
+#include <stdint.h>
+
+#ifndef __HIPCC__
+#define ICM_HD inline
+#else
+#define ICM_HD __host__ __device__ inline
+#endif
+
+namespace icm {
+
+constexpr int kMaxDeg = 6;        // neighbour slots per site (2D uses 4)
+constexpr int kMaxSites = 4096;   // one ICM wave holds up to 64 sites per lane
+constexpr int kMaxTemps = 256;
+constexpr int kMaxReplicas = 64;
+
+// Per-instance statistics block in device memory (u64 counters).
+enum StatSlot {
+  kStatSweeps = 0,
+  kStatMetroAcc,
+  kStatIcmMoves,
+  kStatIcmNontrivial,
+  kStatIcmSites,
+  kStat2a,
+  kStatPtAttempts,
+  kStatPtAccepts,
+  kNumStats
+};
+
+// One work unit (a whole instance) as the fused kernel sees it.  All pointers
+// are device addresses inside the caller's arena.
+struct UnitDesc {
+  uint32_t* spins;          // [Wq][N] words; byte b of word (q, i) = walker 4q+b at site i
+  const uint16_t* nbr;      // [N][deg] neighbour sites (missing chimera slots: i itself)
+  const uint16_t* clist;    // [2][Nc] sites of colour 0, then colour 1
+  const void* coup;         // [N][deg] int8 j or float J (grid-rounded), slot-aligned with nbr
+  const uint32_t* thr;      // int kinds: [K][HM] Metropolis thresholds, index e = s*h
+  const double* beta;       // [K] 1/T_k
+  const float* bl2e;        // [K] float(beta_k * log2(e)) for the fast acceptance filter
+  const uint32_t* ptthr;    // int kinds: [K-1][ptlen] PT thresholds for gap D = 1..ptlen
+  int32_t* tau;             // [Wp] temperature of walker (K for padding walkers)
+  int32_t* at;              // [K][R] walker at temperature k in chain r
+  uint8_t* gauge;           // [Wp] 1 = stored spins are the reversal of the true ones
+  int64_t* energy;          // [Wp] raw energies
+  unsigned long long* stats;// [kNumStats]
+  int32_t* labels;          // [Kc][R/2][N] (RECORD_LABELS only)
+  int32_t* seeds;           // [Kc][R/2] seed site, then [Kc][R/2] n_minus
+  uint32_t* sweep;          // sweep counter t
+  int32_t N, Nc, deg, W, Wq, K, R, Kc, HM, ptlen, jkind, jscale;
+  uint32_t flags, seed, key, pad0;
+};
+
+constexpr uint32_t kFlag2a = 1, kFlagPt = 2, kFlagRecord = 4, kFlagSkipMetro = 8;
+
+ICM_HD uint32_t align16(uint32_t x) { return (x + 15u) & ~15u; }
+
+// Byte offsets of the regions of the fused kernel's LDS image of one unit.
+struct LdsLayout {
+  uint32_t sp, nbr, clist, coup, tau, at, gauge, energy, thr, beta, bl2e, parent, mask, stats,
+      total;
+};
+
+ICM_HD LdsLayout lds_layout(int N, int deg, int Wq, int K, int R, int HM, int jkind, int slots) {
+  LdsLayout L{};
+  uint32_t o = 0;
+  const int Wp = 4 * Wq;
+  L.sp = o;      o = align16(o + 4u * Wq * N);
+  L.nbr = o;     o = align16(o + 2u * N * deg);
+  L.clist = o;   o = align16(o + 2u * N);
+  L.coup = o;    o = align16(o + (jkind ? 4u : 1u) * N * deg);
+  L.tau = o;     o = align16(o + 4u * Wp);
+  L.at = o;      o = align16(o + 4u * K * R);
+  L.gauge = o;   o = align16(o + 4u * Wp);
+  L.energy = o;  o = align16(o + 8u * Wp);
+  L.thr = o;     o = align16(o + (jkind ? 0u : 4u * K * HM));
+  L.beta = o;    o = align16(o + 8u * K);
+  L.bl2e = o;    o = align16(o + 4u * K);
+  L.parent = o;  o = align16(o + 4u * N * slots);
+  L.mask = o;    o = align16(o + 8u * 64 * slots);
+  L.stats = o;   o = align16(o + 8u * kNumStats);
+  L.total = o;
+  return L;
+}
+
+}  // namespace icm

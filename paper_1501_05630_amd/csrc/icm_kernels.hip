@@ -1,0 +1,625 @@
+// HIP kernels for parallel tempering + isoenergetic cluster moves on gfx950.
+//
+// The fused sweep-block kernel runs, for every work unit (one disorder
+// instance with all its temperatures and replicas), n simulation steps of the
+// paper's isoenergetic cluster algorithm (steps 1, 2a, 2b, 3) with the unit
+// resident in LDS:
+//   step 1   checkerboard Metropolis: each thread updates the four walkers of
+//            one quad-word at one site with one Philox block;
+//   step 2a  spin reversal recorded as a per-walker gauge bit;
+//   step 2b  one wavefront per cluster move: q-mask by byte compare, n_minus by
+//            popcount + wave reduction, seed by wave prefix scan, connected
+//            component by union-find with LDS atomicMin hooking and pointer
+//            jumping, exact energy update from the cluster boundary, flip in
+//            both replicas;
+//   step 3   parallel tempering: one lane per chain scans the neighbouring
+//            temperature pairs in ascending order.
+#include <hip/hip_runtime.h>
+
+#include "icm_internal.h"
+
+namespace icm {
+
+// ----------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32->64
+// multiplies by the Philox constants with the key added through xor; the key is
+// bumped by the golden-ratio Weyl increments between rounds.
+// ----------------------------------------------------------------------------
+struct Words4 {
+  uint32_t w[4];
+};
+
+__device__ __forceinline__ Words4 philox4x32_10(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3,
+                                                uint32_t key0, uint32_t key1) {
+#pragma unroll
+  for (int round = 0; round < 10; ++round) {
+    const uint64_t m0 = (uint64_t)0xD2511F53u * x0;
+    const uint64_t m1 = (uint64_t)0xCD9E8D57u * x2;
+    const uint32_t y0 = (uint32_t)(m1 >> 32) ^ x1 ^ key0;
+    const uint32_t y2 = (uint32_t)(m0 >> 32) ^ x3 ^ key1;
+    x1 = (uint32_t)m1;
+    x3 = (uint32_t)m0;
+    x0 = y0;
+    x2 = y2;
+    key0 += 0x9E3779B9u;
+    key1 += 0xBB67AE85u;
+  }
+  Words4 r;
+  r.w[0] = x0; r.w[1] = x1; r.w[2] = x2; r.w[3] = x3;
+  return r;
+}
+
+enum : uint32_t { kStreamMetro = 0, kStreamInit = 1, kStreamIcm = 2, kStreamPt = 3 };
+
+// ----------------------------------------------------------------------------
+// wavefront helpers (wave64)
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+__device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
+
+template <class T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ int wave_exclusive_scan(int v) {
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int y = __shfl_up(x, o, 64);
+    if (lane_id() >= o) x += y;
+  }
+  return x - v;
+}
+
+// Orders this wave's LDS accesses around the call (lanes of one wave exchange
+// data through LDS between ICM phases).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ int spin_of(uint32_t word, int b) {
+  return (int)(int8_t)(uint8_t)(word >> (8 * b));
+}
+
+// ----------------------------------------------------------------------------
+// Metropolis acceptance for float couplings.  dE is exact (2^-32 grid); the
+// decision is u * 2^-32 < exp(-beta dE) in double.  A float estimate settles
+// all but a ~1e-4 band around the boundary: p32 = 2^(-dE * beta log2 e) has a
+// relative error below 2^-18 for every exponent that matters, so with a 2^-14
+// margin the fast accept/reject can only be taken when the double comparison
+// gives the same answer; the band falls back to the double evaluation.
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ bool accept_float(uint32_t u, double dE, double beta, float bl2e) {
+  if (dE <= 0.0) return true;
+  const float p = __builtin_amdgcn_exp2f(-((float)dE * bl2e));
+  const float uf = (float)(u >> 8) * 0x1p-24f;  // exact; true u/2^32 lies in [uf, uf + 2^-24)
+  if (uf > p * (1.0f + 0x1p-14f)) return false;
+  if (uf + 0x1p-24f <= p * (1.0f - 0x1p-14f)) return true;
+  return (double)u * 0x1p-32 < exp(-(beta * dE));
+}
+
+// ----------------------------------------------------------------------------
+// union-find on an LDS parent array (parent[x] <= x; roots satisfy parent[x] == x)
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ int uf_load(int* parent, int x) {
+  return __hip_atomic_load(&parent[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+
+__device__ __forceinline__ int uf_find(int* parent, int x) {
+  int p = uf_load(parent, x);
+  while (p != x) {
+    x = p;
+    p = uf_load(parent, x);
+  }
+  return x;
+}
+
+// Hooks the larger root under the smaller one with atomicMin; when the target
+// stopped being a root meanwhile, continues with the value it pointed to, so
+// no link is ever lost.  Component roots end up at their minimum site index.
+__device__ __forceinline__ void uf_union(int* parent, int a, int b) {
+  while (true) {
+    a = uf_find(parent, a);
+    b = uf_find(parent, b);
+    if (a == b) return;
+    if (a > b) { int t = a; a = b; b = t; }
+    const int old = __hip_atomic_fetch_min(&parent[b], a, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WAVEFRONT);
+    if (old == b) return;
+    b = old;
+  }
+}
+
+template <int JK>
+struct EnergyT;
+template <>
+struct EnergyT<0> { using T = int; };
+template <>
+struct EnergyT<1> { using T = double; };
+
+// ----------------------------------------------------------------------------
+// The fused sweep-block kernel.  JK: 0 = int8 couplings, 1 = float couplings.
+// DEG: neighbour slots (4 for square2d, 6 otherwise).
+// ----------------------------------------------------------------------------
+template <int JK, int DEG>
+__global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __restrict__ units,
+                                                          uint32_t n_sweeps, int icm_slots) {
+  using E_t = typename EnergyT<JK>::T;
+  extern __shared__ __align__(16) unsigned char lds[];
+  const UnitDesc U = units[blockIdx.x];
+  const int N = U.N, Nc = U.Nc, W = U.W, Wq = U.Wq, K = U.K, R = U.R, Kc = U.Kc, HM = U.HM;
+  const int Wp = 4 * Wq;
+  const LdsLayout lay = lds_layout(N, DEG, Wq, K, R, HM, JK, icm_slots);
+
+  uint32_t* sp = (uint32_t*)(lds + lay.sp);
+  uint16_t* nbr = (uint16_t*)(lds + lay.nbr);
+  uint16_t* clist = (uint16_t*)(lds + lay.clist);
+  int8_t* cj = (int8_t*)(lds + lay.coup);
+  float* cf = (float*)(lds + lay.coup);
+  int* tau = (int*)(lds + lay.tau);
+  int* at = (int*)(lds + lay.at);
+  int* gauge = (int*)(lds + lay.gauge);
+  E_t* energy = (E_t*)(lds + lay.energy);
+  uint32_t* thr = (uint32_t*)(lds + lay.thr);
+  double* beta = (double*)(lds + lay.beta);
+  float* bl2e = (float*)(lds + lay.bl2e);
+  int* parent_all = (int*)(lds + lay.parent);
+  unsigned long long* mask_all = (unsigned long long*)(lds + lay.mask);
+  unsigned long long* stats = (unsigned long long*)(lds + lay.stats);
+
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  // ---- load the unit into LDS ----
+  for (int x = tid; x < Wq * N; x += nthr) sp[x] = U.spins[x];
+  for (int x = tid; x < N * DEG; x += nthr) nbr[x] = U.nbr[x];
+  for (int x = tid; x < N; x += nthr) clist[x] = U.clist[x];
+  if (JK) {
+    for (int x = tid; x < N * DEG; x += nthr) cf[x] = ((const float*)U.coup)[x];
+  } else {
+    for (int x = tid; x < N * DEG; x += nthr) cj[x] = ((const int8_t*)U.coup)[x];
+    for (int x = tid; x < K * HM; x += nthr) thr[x] = U.thr[x];
+  }
+  for (int x = tid; x < Wp; x += nthr) {
+    tau[x] = U.tau[x];
+    gauge[x] = U.gauge[x];
+    if (JK) energy[x] = (E_t)((double)U.energy[x] * 0x1p-32);
+    else energy[x] = (E_t)U.energy[x];
+  }
+  for (int x = tid; x < K * R; x += nthr) at[x] = U.at[x];
+  for (int x = tid; x < K; x += nthr) { beta[x] = U.beta[x]; bl2e[x] = U.bl2e[x]; }
+  for (int x = tid; x < kNumStats; x += nthr) stats[x] = 0;
+  __syncthreads();
+
+  const uint32_t t0 = *U.sweep;
+  const uint32_t flags = U.flags, seed = U.seed, key = U.key;
+  const int lane = lane_id(), wave = wave_id(), nwaves = nthr >> 6;
+  unsigned long long metro_acc = 0;  // wave-uniform counter, flushed at the end
+
+  for (uint32_t s = 0; s < n_sweeps; ++s) {
+    const uint32_t t = t0 + s;
+    // ---------------- step 1: Metropolis sweep, colour 0 then colour 1 ----------
+    if (!(flags & kFlagSkipMetro)) {
+      for (int c = 0; c < 2; ++c) {
+        const int nchunk = (Nc + 63) >> 6;
+        const int ntasks = Wq * nchunk;
+        const int tb = (int)(((long long)ntasks * wave) / nwaves);
+        const int te = (int)(((long long)ntasks * (wave + 1)) / nwaves);
+        int cur_q = -1;
+        E_t acc[4] = {0, 0, 0, 0};
+        int tq[4] = {K, K, K, K};
+        int rowb[4] = {0, 0, 0, 0};
+        double bq[4] = {0, 0, 0, 0};
+        float lq[4] = {0, 0, 0, 0};
+        for (int task = tb; task < te; ++task) {
+          const int q = task / nchunk, chunk = task - q * nchunk;
+          if (q != cur_q) {
+            if (cur_q >= 0) {
+#pragma unroll
+              for (int b = 0; b < 4; ++b) {
+                E_t v = wave_sum(acc[b]);
+                if (lane == 0 && v != (E_t)0) atomicAdd(&energy[4 * cur_q + b], v);
+                acc[b] = 0;
+              }
+            }
+            cur_q = q;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+              tq[b] = uniform(4 * q + b < W ? tau[4 * q + b] : K);
+              if (tq[b] < K) {
+                if (JK) { bq[b] = beta[tq[b]]; lq[b] = bl2e[tq[b]]; }
+                else rowb[b] = tq[b] * HM;
+              }
+            }
+          }
+          const int j = chunk * 64 + lane;
+          if (j < Nc) {
+            const int i = clist[c * Nc + j];
+            const uint32_t sw = sp[q * N + i];
+            uint32_t nw[DEG];
+#pragma unroll
+            for (int d = 0; d < DEG; ++d) nw[d] = sp[q * N + nbr[i * DEG + d]];
+            const Words4 u = philox4x32_10((uint32_t)i, t, (uint32_t)q, kStreamMetro, seed, key);
+            uint32_t flip = 0;
+            if (JK) {
+              double Jd[DEG];
+#pragma unroll
+              for (int d = 0; d < DEG; ++d) Jd[d] = (double)cf[i * DEG + d];
+#pragma unroll
+              for (int b = 0; b < 4; ++b) {
+                if (tq[b] >= K) continue;
+                double h = 0.0;
+#pragma unroll
+                for (int d = 0; d < DEG; ++d) h += Jd[d] * (double)spin_of(nw[d], b);
+                const double dE = 2.0 * (double)spin_of(sw, b) * h;
+                if (accept_float(u.w[b], dE, bq[b], lq[b])) {
+                  flip |= 0xFEu << (8 * b);
+                  acc[b] += (E_t)dE;
+                }
+              }
+            } else {
+              int Ji[DEG];
+#pragma unroll
+              for (int d = 0; d < DEG; ++d) Ji[d] = cj[i * DEG + d];
+#pragma unroll
+              for (int b = 0; b < 4; ++b) {
+                if (tq[b] >= K) continue;
+                int h = 0;
+#pragma unroll
+                for (int d = 0; d < DEG; ++d) h += Ji[d] * spin_of(nw[d], b);
+                const int e = spin_of(sw, b) * h;  // dE = 2e
+                if (e <= 0 || u.w[b] < thr[rowb[b] + e]) {
+                  flip |= 0xFEu << (8 * b);
+                  acc[b] += (E_t)(2 * e);
+                }
+              }
+            }
+            if (flip) sp[q * N + i] = sw ^ flip;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+              const unsigned long long bal = __ballot((flip >> (8 * b)) & 0xFEu);
+              metro_acc += (unsigned long long)__popcll(bal);
+            }
+          }
+        }
+        if (cur_q >= 0) {
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            E_t v = wave_sum(acc[b]);
+            if (lane == 0 && v != (E_t)0) atomicAdd(&energy[4 * cur_q + b], v);
+          }
+        }
+        __syncthreads();
+      }
+    }
+
+    // ---------------- steps 2a + 2b: isoenergetic cluster moves ----------------
+    if (Kc > 0) {
+      const int half = R >> 1;
+      const int nmoves = Kc * half;
+      const int slots = icm_slots < nwaves ? icm_slots : nwaves;
+      if (wave < slots) {
+        int* parent = parent_all + wave * N;
+        unsigned long long* maskw = mask_all + wave * 64;
+        const int spl = (N + 63) >> 6;  // sites per lane, lane l owns [l*spl, l*spl+spl)
+        const int i0 = lane * spl;
+        int nown = N - i0;
+        nown = nown < 0 ? 0 : (nown > spl ? spl : nown);
+        const unsigned long long own_mask = nown >= 64 ? ~0ull : ((1ull << nown) - 1ull);
+        const unsigned char* spb = (const unsigned char*)sp;
+        unsigned char* spw = (unsigned char*)sp;
+        for (int mv = wave; mv < nmoves; mv += slots) {
+          const int k = mv / half, p = mv - k * half;
+          const int a = at[k * R + 2 * p], b = at[k * R + 2 * p + 1];
+          const int offa = (a >> 2) * N * 4 + (a & 3), offb = (b >> 2) * N * 4 + (b & 3);
+          const int gx = gauge[a] ^ gauge[b];
+          unsigned long long m = 0;
+          for (int s2 = 0; s2 < nown; ++s2) {
+            const int i = i0 + s2;
+            const int diff = (spb[offa + 4 * i] != spb[offb + 4 * i]) ^ gx;
+            m |= (unsigned long long)diff << s2;
+          }
+          int n = wave_sum((int)__popcll(m));
+          int twoa = 0;
+          if ((flags & kFlag2a) && 2 * n > N) {
+            m = ~m & own_mask;
+            n = N - n;
+            twoa = 1;
+            if (lane == 0) gauge[b] ^= 1;
+          }
+          maskw[lane] = m;
+          int seedsite = -1;
+          int csize = 0;
+          E_t dEa = 0;
+          if (n > 0) {
+            const uint32_t u = philox4x32_10((uint32_t)mv, t, 0u, kStreamIcm, seed, key).w[0];
+            const int idx = (int)(((unsigned long long)u * (unsigned long long)n) >> 32);
+            const int cnt = __popcll(m);
+            const int ex = wave_exclusive_scan(cnt);
+            int cand = -1;
+            if (idx >= ex && idx < ex + cnt) {
+              unsigned long long mm = m;
+              for (int r2 = idx - ex; r2 > 0; --r2) mm &= mm - 1ull;  // drop lowest set bits
+              cand = i0 + (int)__builtin_ctzll(mm);
+            }
+            const unsigned long long owner = __ballot(cand >= 0);
+            seedsite = __shfl(cand, (int)__builtin_ctzll(owner), 64);
+            // union-find over the q = -1 subgraph
+            for (int s2 = 0; s2 < nown; ++s2)
+              if ((m >> s2) & 1ull) parent[i0 + s2] = i0 + s2;
+            wave_sync();
+            for (int s2 = 0; s2 < nown; ++s2) {
+              if (!((m >> s2) & 1ull)) continue;
+              const int i = i0 + s2;
+#pragma unroll
+              for (int d = 0; d < DEG; ++d) {
+                const int jn = nbr[i * DEG + d];
+                if (jn <= i) continue;
+                const int jl = jn / spl, js = jn - jl * spl;
+                if ((maskw[jl] >> js) & 1ull) uf_union(parent, i, jn);
+              }
+            }
+            wave_sync();
+            for (int s2 = 0; s2 < nown; ++s2)
+              if ((m >> s2) & 1ull) {
+                const int r0 = uf_find(parent, i0 + s2);
+                __hip_atomic_store(&parent[i0 + s2], r0, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WAVEFRONT);
+              }
+            wave_sync();
+            const int root = uf_load(parent, seedsite);
+            // energy change of replica a from the bonds that cross the cluster boundary
+            unsigned long long cl = 0;
+            for (int s2 = 0; s2 < nown; ++s2) {
+              if (!((m >> s2) & 1ull)) continue;
+              const int i = i0 + s2;
+              if (uf_load(parent, i) != root) continue;
+              cl |= 1ull << s2;
+              ++csize;
+              const int si = (int)(int8_t)spb[offa + 4 * i];
+#pragma unroll
+              for (int d = 0; d < DEG; ++d) {
+                const int jn = nbr[i * DEG + d];
+                const int jl = jn / spl, js = jn - jl * spl;
+                const bool jin = ((maskw[jl] >> js) & 1ull) && uf_load(parent, jn) == root;
+                if (jin) continue;
+                const int sj = (int)(int8_t)spb[offa + 4 * jn];
+                if (JK) dEa += (E_t)((double)cf[i * DEG + d] * (double)(si * sj));
+                else dEa += (E_t)(cj[i * DEG + d] * si * sj);
+              }
+            }
+            wave_sync();
+            for (int s2 = 0; s2 < nown; ++s2)
+              if ((cl >> s2) & 1ull) {
+                const int i = i0 + s2;
+                spw[offa + 4 * i] ^= 0xFEu;
+                spw[offb + 4 * i] ^= 0xFEu;
+              }
+            dEa = wave_sum(dEa);
+            csize = wave_sum(csize);
+            if (lane == 0) {
+              energy[a] += (E_t)2 * dEa;
+              energy[b] -= (E_t)2 * dEa;
+            }
+          }
+          if (lane == 0) {
+            atomicAdd(&stats[kStatIcmMoves], 1ull);
+            if (twoa) atomicAdd(&stats[kStat2a], 1ull);
+            if (n > 0) {
+              atomicAdd(&stats[kStatIcmNontrivial], 1ull);
+              atomicAdd(&stats[kStatIcmSites], (unsigned long long)csize);
+            }
+          }
+          if ((flags & kFlagRecord) && s + 1 == n_sweeps) {
+            int* lab = U.labels + (size_t)mv * N;
+            for (int s2 = 0; s2 < nown; ++s2) {
+              const int i = i0 + s2;
+              lab[i] = (n > 0 && ((m >> s2) & 1ull)) ? uf_load(parent, i) : -1;
+            }
+            if (lane == 0) {
+              U.seeds[mv] = seedsite;
+              U.seeds[nmoves + mv] = n;
+            }
+          }
+          wave_sync();
+        }
+      }
+      __syncthreads();
+    }
+
+    // ---------------- step 3: parallel tempering ---------------------------------
+    if (flags & kFlagPt) {
+      if (wave == 0) {
+        const int r = lane;
+        int acc_pt = 0;
+        for (int k = 0; r < R && k + 1 < K; ++k) {
+          const int x = at[k * R + r], y = at[(k + 1) * R + r];
+          bool accept;
+          if (JK) {
+            const double D = (double)energy[y] - (double)energy[x];
+            accept = D <= 0.0;
+            if (!accept) {
+              const uint32_t u = philox4x32_10((uint32_t)k, t, (uint32_t)r, kStreamPt, seed, key).w[0];
+              accept = (double)u * 0x1p-32 < exp(-((beta[k] - beta[k + 1]) * D));
+            }
+          } else {
+            const int D = (int)energy[y] - (int)energy[x];
+            accept = D <= 0;
+            if (!accept) {
+              const uint32_t u = philox4x32_10((uint32_t)k, t, (uint32_t)r, kStreamPt, seed, key).w[0];
+              accept = D <= U.ptlen && u < U.ptthr[k * U.ptlen + (D - 1)];
+            }
+          }
+          if (accept) {
+            at[k * R + r] = y;
+            at[(k + 1) * R + r] = x;
+            tau[x] = k + 1;
+            tau[y] = k;
+            ++acc_pt;
+          }
+        }
+        const int tot = wave_sum(acc_pt);
+        if (lane == 0) {
+          stats[kStatPtAttempts] += (unsigned long long)(K - 1) * R;
+          stats[kStatPtAccepts] += (unsigned long long)tot;
+        }
+      }
+      __syncthreads();
+    }
+  }
+
+  // ---- store the unit back ----
+  if (lane == 0 && metro_acc) atomicAdd(&stats[kStatMetroAcc], metro_acc);
+  __syncthreads();
+  for (int x = tid; x < Wq * N; x += nthr) U.spins[x] = sp[x];
+  for (int x = tid; x < Wp; x += nthr) {
+    U.tau[x] = tau[x];
+    U.gauge[x] = (uint8_t)gauge[x];
+    if (JK) U.energy[x] = (int64_t)((double)energy[x] * 0x1p32);
+    else U.energy[x] = (int64_t)energy[x];
+  }
+  for (int x = tid; x < K * R; x += nthr) U.at[x] = at[x];
+  if (tid == 0) {
+    stats[kStatSweeps] = n_sweeps;
+    *U.sweep = t0 + n_sweeps;
+  }
+  __syncthreads();
+  for (int x = tid; x < kNumStats; x += nthr) U.stats[x] += stats[x];
+}
+
+// ----------------------------------------------------------------------------
+// Hot start: spin = -1 iff bit 31 of the walker's INIT word is set.
+// grid: (ceil(Wq*N/256), 1), one thread per quad-word.
+// ----------------------------------------------------------------------------
+__global__ void init_spins_kernel(uint32_t* spins, int N, int Wq, int W, uint32_t seed, uint32_t key) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= Wq * N) return;
+  const int q = x / N, i = x - q * N;
+  const Words4 u = philox4x32_10((uint32_t)i, 0u, (uint32_t)q, kStreamInit, seed, key);
+  uint32_t word = 0;
+  for (int b = 0; b < 4; ++b) {
+    const uint32_t sb = (4 * q + b < W && (u.w[b] >> 31)) ? 0xFFu : 0x01u;
+    word |= sb << (8 * b);
+  }
+  spins[x] = word;
+}
+
+// Scatter of caller states [W][N] (walker-major, walker w = k*R + r) into the
+// quad-word layout.
+__global__ void scatter_spins_kernel(uint32_t* spins, const int8_t* src, int N, int Wq, int W) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= Wq * N) return;
+  const int q = x / N, i = x - q * N;
+  uint32_t word = 0;
+  for (int b = 0; b < 4; ++b) {
+    const int w = 4 * q + b;
+    const uint32_t sb = (w < W && src[(size_t)w * N + i] < 0) ? 0xFFu : 0x01u;
+    word |= sb << (8 * b);
+  }
+  spins[x] = word;
+}
+
+// Energy of every walker from scratch: each bond is seen from both ends, so the
+// slot sum is halved (exact: integer, or float couplings on the 2^-32 grid summed
+// as int64 after scaling).  grid: (Wp), block 256.
+template <int JK>
+__global__ void energy_kernel(const uint32_t* spins, const uint16_t* nbr, const void* coup, int N,
+                              int deg, int64_t* energy) {
+  const int w = blockIdx.x, q = w >> 2, b = w & 3;
+  __shared__ long long part[256];
+  long long acc = 0;
+  for (int i = threadIdx.x; i < N; i += blockDim.x) {
+    const int si = spin_of(spins[(size_t)q * N + i], b);
+    for (int d = 0; d < deg; ++d) {
+      const int j = nbr[i * deg + d];
+      const int sj = spin_of(spins[(size_t)q * N + j], b);
+      long long Jraw;
+      if (JK) Jraw = (long long)((double)((const float*)coup)[i * deg + d] * 0x1p32);
+      else Jraw = ((const int8_t*)coup)[i * deg + d];
+      acc -= Jraw * si * sj;
+    }
+  }
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) energy[w] = part[0] / 2;
+}
+
+}  // namespace icm
+
+// ----------------------------------------------------------------------------
+// launch wrappers used by the host runtime
+// ----------------------------------------------------------------------------
+extern "C" {
+
+int icmk_launch_sweep(const icm::UnitDesc* d_units, int n_units, int jkind, int deg,
+                      uint32_t n_sweeps, int threads, int icm_slots, size_t lds_bytes,
+                      hipStream_t stream) {
+  if (n_units <= 0) return 0;
+  dim3 grid(n_units), block(threads);
+  if (jkind == 0 && deg == 4)
+    hipLaunchKernelGGL((icm::sweep_block_kernel<0, 4>), grid, block, lds_bytes, stream, d_units,
+                       n_sweeps, icm_slots);
+  else if (jkind == 0 && deg == 6)
+    hipLaunchKernelGGL((icm::sweep_block_kernel<0, 6>), grid, block, lds_bytes, stream, d_units,
+                       n_sweeps, icm_slots);
+  else if (jkind == 1 && deg == 4)
+    hipLaunchKernelGGL((icm::sweep_block_kernel<1, 4>), grid, block, lds_bytes, stream, d_units,
+                       n_sweeps, icm_slots);
+  else if (jkind == 1 && deg == 6)
+    hipLaunchKernelGGL((icm::sweep_block_kernel<1, 6>), grid, block, lds_bytes, stream, d_units,
+                       n_sweeps, icm_slots);
+  else
+    return (int)hipErrorInvalidValue;
+  return (int)hipGetLastError();
+}
+
+int icmk_set_lds_limit(size_t bytes) {
+  hipError_t e = hipSuccess;
+  const void* fns[4] = {(const void*)icm::sweep_block_kernel<0, 4>,
+                        (const void*)icm::sweep_block_kernel<0, 6>,
+                        (const void*)icm::sweep_block_kernel<1, 4>,
+                        (const void*)icm::sweep_block_kernel<1, 6>};
+  for (int x = 0; x < 4; ++x) {
+    hipError_t r = hipFuncSetAttribute(fns[x], hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (r != hipSuccess) e = r;
+  }
+  return (int)e;
+}
+
+int icmk_launch_init(uint32_t* spins, int N, int Wq, int W, uint32_t seed, uint32_t key,
+                     hipStream_t stream) {
+  const int n = Wq * N;
+  hipLaunchKernelGGL(icm::init_spins_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, spins, N,
+                     Wq, W, seed, key);
+  return (int)hipGetLastError();
+}
+
+int icmk_launch_scatter(uint32_t* spins, const int8_t* src, int N, int Wq, int W,
+                        hipStream_t stream) {
+  const int n = Wq * N;
+  hipLaunchKernelGGL(icm::scatter_spins_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, spins,
+                     src, N, Wq, W);
+  return (int)hipGetLastError();
+}
+
+int icmk_launch_energy(const uint32_t* spins, const uint16_t* nbr, const void* coup, int N, int deg,
+                       int Wp, int jkind, int64_t* energy, hipStream_t stream) {
+  if (jkind)
+    hipLaunchKernelGGL(icm::energy_kernel<1>, dim3(Wp), dim3(256), 0, stream, spins, nbr, coup, N,
+                       deg, energy);
+  else
+    hipLaunchKernelGGL(icm::energy_kernel<0>, dim3(Wp), dim3(256), 0, stream, spins, nbr, coup, N,
+                       deg, energy);
+  return (int)hipGetLastError();
+}
+
+}  // extern "C"

@@ -1,0 +1,280 @@
+"""GPU parity: the HIP path (through the C-ABI) against the CPU oracle.
+
+Integer couplings: whole trajectories bit-exact (spins, temperature labels,
+energies, statistics, ICM labels).  Float couplings: the same bar is expected
+(exact local fields; the acceptance is decided in double on both sides, with a
+float pre-filter on the GPU whose margin covers its error); the per-temperature
+energy test required for Gaussian disorder (1e-3 absolute and 3 standard
+errors) is also run.
+"""
+import numpy as np
+import pytest
+
+import oracle as orc
+from paper_1501_05630_amd import icm, inputs
+
+pytestmark = pytest.mark.gpu
+SEED = inputs.MASTER_SEED
+ORACLE_FLAGS = icm.FLAG_2A | icm.FLAG_PT | icm.FLAG_SKIP_METRO
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = icm.Context(arena_bytes=1 << 30, seed=SEED)
+    yield c
+    c.close()
+
+
+def make_pair(ctx, top, L, J, temps, R, Kc, flags, key=0, j_scale=1):
+    h = ctx.icm_add_instance(top, L, J, temps, R, Kc, flags=flags, instance_key=key, j_scale=j_scale)
+    o = orc.Sim(top, L, J, temps, R, Kc, flags=flags & ORACLE_FLAGS, seed=SEED, instance_key=key,
+                j_scale=j_scale)
+    return h, o
+
+
+STAT_KEYS = ["metro_accepts", "icm_moves", "icm_nontrivial", "icm_cluster_sites", "icm_2a_flips",
+             "pt_attempts", "pt_accepts"]
+
+
+def assert_same(ctx, h, o, what=""):
+    st = ctx.icm_read_states(h)
+    ref = o.states()
+    if not np.array_equal(st, ref):
+        bad = np.argwhere(st != ref)
+        raise AssertionError(f"{what}: {len(bad)} spins differ, first at {bad[:3].tolist()}")
+    raw, _ = ctx.icm_read_energies(h)
+    assert np.array_equal(raw, o.energies_raw()), f"{what}: energies differ"
+    assert np.array_equal(ctx.icm_read_walkers(h), o.walkers()), f"{what}: PT labels differ"
+    gs, os_ = ctx.icm_read_stats(h), o.stats()
+    for k in STAT_KEYS:
+        assert gs[k] == os_[k], f"{what}: stat {k} {gs[k]} != {os_[k]}"
+    assert ctx.icm_sweep_index(h) == o.sweep()
+
+
+def run_both(ctx, h, o, chunks, what):
+    for n in chunks:
+        ctx.icm_run([h], n)
+        o.run(n)
+        ctx.icm_sync()
+        assert_same(ctx, h, o, f"{what} after +{n}")
+
+
+# ------------------------------------------------------------------ trajectories
+def test_2d_pmJ_L8_trajectory_bit_exact(ctx):
+    J, temps, kc, spec = inputs.workload_instance("2d_L8_pmJ_1inst", 0)
+    h, o = make_pair(ctx, spec["topology"], 8, J, temps, 2, kc, icm.FLAG_2A | icm.FLAG_PT)
+    ctx.icm_init_states(h)
+    o.init_hot()
+    assert_same(ctx, h, o, "hot start")
+    run_both(ctx, h, o, [1, 3, 60, 200], "2d pmJ")
+    ctx.icm_remove_instance(h)
+
+
+def test_metropolis_only_bit_exact(ctx):
+    rng = inputs.make_rng(70, 0)
+    for top, L, kind, sc in [(inputs.SQUARE2D, 8, "pmJ", 1), (inputs.CUBIC3D, 4, "gauss", 1),
+                             (inputs.CHIMERA, 2, "int3", 3)]:
+        J = inputs.make_couplings(kind, top, L, rng)
+        h, o = make_pair(ctx, top, L, J, inputs.geometric_temps(0.3, 2.0, 6), 2, 0, 0, j_scale=sc)
+        ctx.icm_init_states(h)
+        o.init_hot()
+        run_both(ctx, h, o, [1, 20], f"metropolis {kind}")
+        ctx.icm_remove_instance(h)
+
+
+@pytest.mark.parametrize("top,L,kind,sc", [(inputs.SQUARE2D, 8, "pmJ", 1), (inputs.CUBIC3D, 6, "gauss", 1),
+                                           (inputs.CHIMERA, 4, "int3", 3), (inputs.SQUARE2D, 2, "pmJ", 1),
+                                           (inputs.CUBIC3D, 2, "gauss", 1), (inputs.CHIMERA, 1, "int3", 3)])
+@pytest.mark.parametrize("two_a", [True, False])
+def test_icm_only_labels_and_flips_bit_exact(ctx, top, L, kind, sc, two_a):
+    rng = inputs.make_rng(71, L * 10 + top)
+    J = inputs.make_couplings(kind, top, L, rng)
+    temps = inputs.geometric_temps(0.3, 1.5, 4)
+    flags = icm.FLAG_SKIP_METRO | icm.FLAG_RECORD_LABELS | (icm.FLAG_2A if two_a else 0)
+    h, o = make_pair(ctx, top, L, J, temps, 4, 4, flags, key=5, j_scale=sc)
+    N = o.N
+    for trial, frac in enumerate([0.05, 0.3, 0.45, 0.55, 0.8, 0.0, 1.0]):
+        st = np.where(rng.random((4, 4, N)) < 0.5, 1, -1).astype(np.int8)
+        for k in range(4):
+            for r in (1, 3):
+                st[k, r] = np.where(rng.random(N) < frac, -st[k, r - 1], st[k, r - 1])
+        ctx.icm_set_states(h, st, sweep0=trial * 7)
+        o.set_states(st, sweep0=trial * 7)
+        ctx.icm_run([h], 1)
+        o.run(1)
+        ctx.icm_sync()
+        for k in range(4):
+            for p in range(2):
+                lab, seed, nm = ctx.icm_read_labels(h, k, p)
+                rl, rs, rn = o.labels(k, p)
+                assert nm == rn and seed == rs, (trial, k, p, nm, rn, seed, rs)
+                assert np.array_equal(lab, rl), (trial, k, p)
+        assert np.array_equal(ctx.icm_read_states(h), o.states()), trial
+        assert np.array_equal(ctx.icm_read_energies(h)[0], o.energies_raw()), trial
+    ctx.icm_remove_instance(h)
+
+
+def test_3d_gauss_L8_trajectory_bit_exact(ctx):
+    J, temps, kc, spec = inputs.workload_instance("3d_L8_gauss_1024inst", 3)
+    h, o = make_pair(ctx, spec["topology"], 8, J, temps, 4, kc, icm.FLAG_2A | icm.FLAG_PT, key=3)
+    ctx.icm_init_states(h)
+    o.init_hot()
+    run_both(ctx, h, o, [1, 40, 100], "3d gauss")
+    ctx.icm_remove_instance(h)
+
+
+def test_chimera_C12_trajectory_bit_exact(ctx):
+    J, temps, kc, spec = inputs.workload_instance("chimera_C12_int3_512inst", 7)
+    h, o = make_pair(ctx, spec["topology"], 12, J, temps, 2, kc, icm.FLAG_2A | icm.FLAG_PT,
+                     key=7, j_scale=3)
+    ctx.icm_init_states(h)
+    o.init_hot()
+    run_both(ctx, h, o, [1, 30], "chimera C12")
+    ctx.icm_remove_instance(h)
+
+
+@pytest.mark.parametrize("case", [
+    dict(top=inputs.CUBIC3D, L=2, kind="gauss", K=3, R=2, Kc=3),      # N=8 multigraph, W%4=2
+    dict(top=inputs.CHIMERA, L=1, kind="int3", K=5, R=2, Kc=5),       # single cell, open edges
+    dict(top=inputs.SQUARE2D, L=4, kind="pmJ", K=1, R=2, Kc=1),       # one temperature, no PT pair
+    dict(top=inputs.SQUARE2D, L=6, kind="pmJ", K=7, R=6, Kc=7),       # R=6, ragged quads
+    dict(top=inputs.CUBIC3D, L=4, kind="pmJ", K=9, R=2, Kc=0),        # ICM off
+    dict(top=inputs.SQUARE2D, L=64, kind="pmJ", K=4, R=2, Kc=4),      # N=4096 (largest resident)
+    dict(top=inputs.CHIMERA, L=5, kind="gauss", K=5, R=4, Kc=2),      # float chimera
+])
+def test_edge_cases_bit_exact(ctx, case):
+    rng = inputs.make_rng(72, case["L"] * 100 + case["K"])
+    J = inputs.make_couplings(case["kind"], case["top"], case["L"], rng)
+    sc = 3 if case["kind"] == "int3" else 1
+    temps = inputs.geometric_temps(0.25, 1.8, case["K"]) if case["K"] > 1 else np.array([0.6])
+    h, o = make_pair(ctx, case["top"], case["L"], J, temps, case["R"], case["Kc"],
+                     icm.FLAG_2A | icm.FLAG_PT, key=11, j_scale=sc)
+    ctx.icm_init_states(h)
+    o.init_hot()
+    run_both(ctx, h, o, [1, 25], str(case))
+    ctx.icm_remove_instance(h)
+
+
+def test_batched_per_instance_and_graph_agree(ctx):
+    rng = inputs.make_rng(73, 0)
+    specs = [(inputs.SQUARE2D, 8, "pmJ", 1, 16, 2), (inputs.CUBIC3D, 4, "gauss", 1, 10, 4),
+             (inputs.CHIMERA, 3, "int3", 3, 12, 2), (inputs.CUBIC3D, 6, "gauss", 1, 8, 4)]
+    made = []
+    for x, (top, L, kind, sc, K, R) in enumerate(specs * 2):
+        J = inputs.make_couplings(kind, top, L, rng)
+        temps = inputs.geometric_temps(0.2, 2.0, K)
+        made.append((top, L, J, temps, R, inputs.icm_cutoff(temps), sc, x))
+
+    def run(mode):
+        hs = []
+        for (top, L, J, temps, R, kc, sc, x) in made:
+            h = ctx.icm_add_instance(top, L, J, temps, R, kc, instance_key=x, j_scale=sc)
+            ctx.icm_init_states(h)
+            hs.append(h)
+        if mode == "batched":
+            ctx.icm_set_run_config(sweeps_per_launch=16, use_graph=0)
+            ctx.icm_run(hs, 80)
+        elif mode == "graph":
+            ctx.icm_set_run_config(sweeps_per_launch=16, use_graph=1)
+            ctx.icm_run(hs, 48)
+            ctx.icm_run(hs, 32)
+        else:
+            ctx.icm_set_run_config(sweeps_per_launch=16, use_graph=0)
+            ctx.icm_run_per_instance(hs, 80)
+        ctx.icm_sync()
+        out = [(ctx.icm_read_states(h), ctx.icm_read_energies(h)[0]) for h in hs]
+        for h in hs:
+            ctx.icm_remove_instance(h)
+        return out
+
+    a, b, c = run("batched"), run("per_instance"), run("graph")
+    ctx.icm_set_run_config(sweeps_per_launch=256, use_graph=0)
+    for x in range(len(made)):
+        for y in (b, c):
+            assert np.array_equal(a[x][0], y[x][0]) and np.array_equal(a[x][1], y[x][1]), x
+
+
+@pytest.mark.parametrize("threads,slots", [(256, 1), (512, 3), (1024, 8), (1024, 16)])
+def test_launch_shape_does_not_change_results(ctx, threads, slots):
+    J, temps, kc, spec = inputs.workload_instance("3d_L8_gauss_1024inst", 1)
+    h, o = make_pair(ctx, spec["topology"], 8, J, temps, 4, kc, icm.FLAG_2A | icm.FLAG_PT, key=1)
+    ctx.icm_set_run_config(threads=threads, icm_slots=slots, sweeps_per_launch=7)
+    ctx.icm_init_states(h)
+    o.init_hot()
+    run_both(ctx, h, o, [20], f"threads={threads} slots={slots}")
+    ctx.icm_set_run_config(threads=512, icm_slots=8, sweeps_per_launch=256)
+    ctx.icm_remove_instance(h)
+
+
+def test_gaussian_energy_per_temperature_statistics(ctx):
+    # Paired GPU-vs-oracle test of the per-temperature mean energy per spin for
+    # Gaussian disorder: |mean difference| <= 1e-3 and <= 3 standard errors.
+    n_inst, sweeps, burn = 12, 1500, 300
+    temps = inputs.geometric_temps(0.5, 2.0, 8)
+    diffs = []
+    for b in range(n_inst):
+        J = inputs.gaussian_couplings(inputs.CUBIC3D, 4, inputs.make_rng(74, b))
+        h, o = make_pair(ctx, inputs.CUBIC3D, 4, J, temps, 2, 4, icm.FLAG_2A | icm.FLAG_PT, key=b)
+        ctx.icm_init_states(h)
+        o.init_hot()
+        ctx.icm_run([h], burn)
+        o.run(burn)
+        g_acc = np.zeros(8)
+        for _ in range(sweeps // 50):
+            ctx.icm_run([h], 50)
+            _, real = ctx.icm_read_energies(h)
+            g_acc += real.mean(axis=1)
+        o_acc = np.zeros(8)
+        for _ in range(sweeps // 50):
+            o.run(50)
+            o_acc += o.energies().mean(axis=1)
+        diffs.append((g_acc - o_acc) / (sweeps // 50) / 64.0)
+        ctx.icm_remove_instance(h)
+    d = np.array(diffs)
+    mean, se = d.mean(axis=0), d.std(axis=0, ddof=1) / np.sqrt(n_inst) + 1e-15
+    assert np.all(np.abs(mean) <= 1e-3)
+    assert np.all(np.abs(mean) <= 3 * se + 1e-12)
+
+
+# ---------------------------------------------------------- full-size workloads
+def _full_size(ctx, name, n_inst, sweeps, sample):
+    hs, Js = [], []
+    for b in range(n_inst):
+        J, temps, kc, spec = inputs.workload_instance(name, b)
+        hs.append(ctx.icm_add_instance(spec["topology"], spec["L"], J, temps, spec["n_replicas"], kc,
+                                       instance_key=b, j_scale=spec["j_scale"]))
+        Js.append(J)
+        ctx.icm_init_states(hs[-1])
+    ctx.icm_set_run_config(threads=512, sweeps_per_launch=sweeps)
+    ctx.icm_run(hs, sweeps)
+    ctx.icm_sync()
+    for b in sample:
+        J, temps, kc, spec = inputs.workload_instance(name, b)
+        o = orc.Sim(spec["topology"], spec["L"], J, temps, spec["n_replicas"], kc,
+                    flags=orc.FLAG_2A | orc.FLAG_PT, seed=SEED, instance_key=b, j_scale=spec["j_scale"])
+        o.init_hot()
+        o.run(sweeps)
+        assert_same(ctx, hs[b], o, f"{name} instance {b}")
+    # property at any size: every reported energy equals the energy of the state
+    ref = orc.Sim(spec["topology"], spec["L"], Js[0], temps, spec["n_replicas"], kc,
+                  seed=SEED, j_scale=spec["j_scale"])
+    for b in range(0, n_inst, max(1, n_inst // 64)):
+        o = orc.Sim(spec["topology"], spec["L"], Js[b], temps, spec["n_replicas"], kc,
+                    seed=SEED, j_scale=spec["j_scale"])
+        st = ctx.icm_read_states(hs[b])
+        raw, _ = ctx.icm_read_energies(hs[b])
+        for k in range(st.shape[0]):
+            for r in range(st.shape[1]):
+                assert raw[k, r] == o.energy_raw(st[k, r]), (b, k, r)
+    del ref
+    for h in hs:
+        ctx.icm_remove_instance(h)
+    ctx.icm_set_run_config(sweeps_per_launch=256)
+
+
+def test_full_size_3d_gauss_1024_instances_sampled(ctx):
+    _full_size(ctx, "3d_L8_gauss_1024inst", 1024, 12, [0, 341, 1023])
+
+
+def test_full_size_chimera_512_instances_sampled(ctx):
+    _full_size(ctx, "chimera_C12_int3_512inst", 512, 6, [0, 511])
