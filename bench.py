@@ -37,6 +37,12 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-instance", action="store_true")
+    ap.add_argument("--serve", type=int, default=0,
+                    help="run the serving workload with this many requests instead")
+    ap.add_argument("--serve-sweeps", type=int, default=1 << 13)
+    ap.add_argument("--serve-block", type=int, default=256)
+    ap.add_argument("--serve-load", type=float, default=0.8)
+    ap.add_argument("--arena-mib", type=int, default=1024)
     return ap.parse_args()
 
 
@@ -85,8 +91,95 @@ def cpu_baseline(name, spec, seconds):
             "sample": f"{n_inst} instances x {sweeps} sweeps of {name}, one oracle per thread"}
 
 
+def serve_request(x, rng):
+    """One request of the serving mix: 2D +-J L in {16,32,64}, 3D Gaussian L in
+    {6,8,12}, chimera C in 4..16, uniformly."""
+    from paper_1501_05630_amd import icm, inputs
+    cls = int(rng.integers(0, 3))
+    if cls == 0:
+        L = int(rng.choice([16, 32, 64]))
+        J = inputs.pm_j_couplings(inputs.SQUARE2D, L, rng)
+        temps = inputs.geometric_temps(0.2, 1.6, 16)
+        d = dict(topology=inputs.SQUARE2D, L=L, couplings=J, temps=temps, n_replicas=2, j_scale=1)
+    elif cls == 1:
+        L = int(rng.choice([6, 8, 12]))
+        J = inputs.gaussian_couplings(inputs.CUBIC3D, L, rng)
+        temps = inputs.geometric_temps(0.2, 2.0, 20)
+        d = dict(topology=inputs.CUBIC3D, L=L, couplings=J, temps=temps, n_replicas=4, j_scale=1)
+    else:
+        C = int(rng.integers(4, 17))
+        J = inputs.int_couplings(inputs.CHIMERA, C, rng)
+        temps = inputs.geometric_temps(0.2, 3.0, 30)
+        d = dict(topology=inputs.CHIMERA, L=C, couplings=J, temps=temps, n_replicas=2, j_scale=3)
+    d["icm_ntemps"] = inputs.icm_cutoff(d["temps"])
+    d["instance_key"] = x
+    d["flags"] = icm.FLAG_2A | icm.FLAG_PT
+    N = inputs.n_sites(d["topology"], d["L"])
+    return d, len(d["temps"]) * d["n_replicas"] * N
+
+
+def run_serving(args):
+    """Continuous batching under Poisson arrivals: p50/p99 latency and sweeps/s."""
+    import numpy as np
+
+    from paper_1501_05630_amd import icm, inputs
+    rng = inputs.make_rng(4, 0)
+    reqs = [serve_request(x, rng) for x in range(args.serve)]
+    ctx = icm.Context(arena_bytes=args.arena_mib << 20, seed=inputs.MASTER_SEED)
+    ctx.icm_serve_start(args.serve_block)
+
+    def drain(tickets):
+        lat = []
+        for t, (d, _) in tickets:
+            while True:
+                done, us = ctx.icm_poll(t)
+                if done:
+                    break
+                time.sleep(0.0005)
+            K, R = len(d["temps"]), d["n_replicas"]
+            ctx.icm_take_result(t, K, R, inputs.n_sites(d["topology"], d["L"]))
+            lat.append(us)
+        return lat
+
+    # saturated rate: everything submitted at once
+    n_sat = max(8, args.serve // 4)
+    t0 = time.perf_counter()
+    tickets = [(ctx.icm_submit(args.serve_sweeps, **d), (d, w)) for d, w in reqs[:n_sat]]
+    drain(tickets)
+    sat_rate = n_sat / (time.perf_counter() - t0)
+    # Poisson arrivals at a fraction of the saturated rate
+    rate = args.serve_load * sat_rate
+    gaps = rng.exponential(1.0 / rate, size=args.serve)
+    t0 = time.perf_counter()
+    tickets = []
+    next_t = t0
+    for (d, w), g in zip(reqs, gaps):
+        next_t += g
+        while time.perf_counter() < next_t:
+            time.sleep(0.0002)
+        tickets.append((ctx.icm_submit(args.serve_sweeps, **d), (d, w)))
+    lat = drain(tickets)
+    wall = time.perf_counter() - t0
+    ctx.icm_serve_stop()
+    ctx.close()
+    attempts = sum(w for _, w in reqs) * args.serve_sweeps
+    lat = np.array(lat) / 1e3
+    return {"requests": args.serve, "sweeps_per_request": args.serve_sweeps,
+            "arrival_rate_per_s": rate, "saturated_rate_per_s": sat_rate,
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "sweeps_per_s": args.serve * args.serve_sweeps / wall,
+            "attempts_per_s": attempts / wall, "arena_mib": args.arena_mib}
+
+
 def main():
     args = parse()
+    if args.serve:
+        if args.gpus != 1:
+            print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+            sys.exit(2)
+        print(json.dumps({"metric": "serving: p50/p99 latency and sweeps/s",
+                          "serving": run_serving(args)}), flush=True)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)

@@ -1,0 +1,77 @@
+"""Launch-shape autotuner for the fused sweep-block kernel.
+
+Searches threads per workgroup, concurrent ICM moves per workgroup and sweeps
+per launch for one batch of instances, timing `icm_run` with HIP events on the
+context stream, and caches the winner in a JSON file keyed by the batch's
+shape.  The choice never changes results: every launch shape computes the same
+bits (the random streams are keyed by site, sweep and walker, not by thread).
+"""
+import itertools
+import json
+import os
+
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "icm_autotune.json")
+THREADS = (256, 512, 1024)
+SLOTS = (2, 4, 8, 16)
+SWEEPS = (64, 256)
+
+
+def shape_key(meta, n_instances):
+    """Cache key: topology shape, walkers, ICM temperatures, coupling kind, batch size bucket."""
+    bucket = 1 << max(0, (n_instances - 1).bit_length())
+    return "N{N}_K{K}_R{R}_Kc{Kc}_j{jkind}_b{b}".format(b=bucket, **meta)
+
+
+def _time_run(ctx, handles, sweeps, repeats=2):
+    torch = ctx.torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ctx.icm_run(handles, sweeps)  # warm-up (and graph/unit-table creation)
+    torch.cuda.synchronize()
+    e0.record(ctx.stream)
+    for _ in range(repeats):
+        ctx.icm_run(handles, sweeps)
+    e1.record(ctx.stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / (repeats * sweeps)  # ms per sweep
+
+
+def tune(ctx, handles, cache_path=DEFAULT_CACHE, budget_sweeps=None, verbose=False):
+    """Returns the best config dict for this batch and applies it to ctx.
+
+    Runs each candidate for a few sweeps on the live instances (their state
+    advances; callers tune on a warm-up batch or accept the extra sweeps)."""
+    meta = dict(ctx.meta[handles[0]])
+    key = shape_key({k: meta[k] for k in ("N", "K", "R", "Kc", "jkind")}, len(handles))
+    cache = {}
+    if cache_path and os.path.exists(cache_path):
+        try:
+            with open(cache_path) as f:
+                cache = json.load(f)
+        except (OSError, ValueError):
+            cache = {}
+    if key in cache:
+        best = cache[key]
+        ctx.icm_set_run_config(**best)
+        return best
+    results = []
+    for threads, slots, spl in itertools.product(THREADS, SLOTS, SWEEPS):
+        if slots > threads // 64:
+            continue
+        cfg = dict(threads=threads, icm_slots=slots, sweeps_per_launch=spl, use_graph=1)
+        ctx.icm_set_run_config(**cfg)
+        n = budget_sweeps or spl
+        ms = _time_run(ctx, handles, n)
+        results.append((ms, cfg))
+        if verbose:
+            print(f"autotune {key} {cfg}: {ms * 1e3:.2f} us/sweep", flush=True)
+    results.sort(key=lambda r: r[0])
+    best = results[0][1]
+    cache[key] = best
+    if cache_path:
+        os.makedirs(os.path.dirname(cache_path), exist_ok=True)
+        tmp = cache_path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(cache, f, indent=1, sort_keys=True)
+        os.replace(tmp, cache_path)
+    ctx.icm_set_run_config(**best)
+    return best

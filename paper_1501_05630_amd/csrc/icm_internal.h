@@ -57,19 +57,27 @@ constexpr uint32_t kFlag2a = 1, kFlagPt = 2, kFlagRecord = 4, kFlagSkipMetro = 8
 ICM_HD uint32_t align16(uint32_t x) { return (x + 15u) & ~15u; }
 
 // Byte offsets of the regions of the fused kernel's LDS image of one unit.
+// Spins are bit-packed in LDS: word (g, i) holds walkers 32g..32g+31 at site i,
+// bit set = spin down.
 struct LdsLayout {
-  uint32_t sp, nbr, clist, coup, tau, at, gauge, energy, thr, beta, bl2e, parent, mask, stats,
-      total;
+  uint32_t sp, nbr, clist, coup, tau, at, gauge, energy, thr, beta, bl2e, ptu, parent, mask,
+      stats, total;
 };
 
-ICM_HD LdsLayout lds_layout(int N, int deg, int Wq, int K, int R, int HM, int jkind, int slots) {
+ICM_HD int bit_words(int Wq) { return (4 * Wq + 31) / 32; }
+
+// tables = 1: neighbour table, colour lists and couplings are copied into LDS;
+// tables = 0: they are read from global memory (for units too large otherwise).
+ICM_HD LdsLayout lds_layout(int N, int deg, int Wq, int K, int R, int HM, int jkind, int slots,
+                            int tables) {
   LdsLayout L{};
   uint32_t o = 0;
   const int Wp = 4 * Wq;
-  L.sp = o;      o = align16(o + 4u * Wq * N);
-  L.nbr = o;     o = align16(o + 2u * N * deg);
-  L.clist = o;   o = align16(o + 2u * N);
-  L.coup = o;    o = align16(o + (jkind ? 4u : 1u) * N * deg);
+  const uint32_t tn = tables ? (uint32_t)N : 0u;
+  L.sp = o;      o = align16(o + 4u * bit_words(Wq) * N);
+  L.nbr = o;     o = align16(o + 2u * tn * deg);
+  L.clist = o;   o = align16(o + 2u * tn);
+  L.coup = o;    o = align16(o + (jkind ? 4u : 1u) * tn * deg);
   L.tau = o;     o = align16(o + 4u * Wp);
   L.at = o;      o = align16(o + 4u * K * R);
   L.gauge = o;   o = align16(o + 4u * Wp);
@@ -77,6 +85,7 @@ ICM_HD LdsLayout lds_layout(int N, int deg, int Wq, int K, int R, int HM, int jk
   L.thr = o;     o = align16(o + (jkind ? 0u : 4u * K * HM));
   L.beta = o;    o = align16(o + 8u * K);
   L.bl2e = o;    o = align16(o + 4u * K);
+  L.ptu = o;     o = align16(o + 4u * (K > 1 ? K - 1 : 1) * R);
   L.parent = o;  o = align16(o + 4u * N * slots);
   L.mask = o;    o = align16(o + 8u * 64 * slots);
   L.stats = o;   o = align16(o + 8u * kNumStats);

@@ -3,12 +3,12 @@
 // The fused sweep-block kernel runs, for every work unit (one disorder
 // instance with all its temperatures and replicas), n simulation steps of the
 // paper's isoenergetic cluster algorithm (steps 1, 2a, 2b, 3) with the unit
-// resident in LDS:
+// resident in LDS (spins bit-packed, 32 walkers per word):
 //   step 1   checkerboard Metropolis: each thread updates the four walkers of
-//            one quad-word at one site with one Philox block;
+//            one Philox quad at one site with one Philox block;
 //   step 2a  spin reversal recorded as a per-walker gauge bit;
-//   step 2b  one wavefront per cluster move: q-mask by byte compare, n_minus by
-//            popcount + wave reduction, seed by wave prefix scan, connected
+//   step 2b  one wavefront per cluster move: q-mask by bit compare, n_minus by
+//            popcount + DPP wave reduction, seed by wave prefix scan, connected
 //            component by union-find with LDS atomicMin hooking and pointer
 //            jumping, exact energy update from the cluster boundary, flip in
 //            both replicas;
@@ -57,11 +57,45 @@ enum : uint32_t { kStreamMetro = 0, kStreamInit = 1, kStreamIcm = 2, kStreamPt =
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 __device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
 
-template <class T>
-__device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+// Sum over the 64 lanes of a wave (all lanes active), returned to every lane.
+// DPP: butterfly inside each quad, then half-row and row mirrors give every
+// lane its 16-lane row sum; the four row sums are read back with readlane.
+__device__ __forceinline__ int dpp_row_sum(int v) {
+  v += __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+  v += __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+  v += __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false);  // row_half_mirror
+  v += __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, false);  // row_mirror
   return v;
+}
+
+__device__ __forceinline__ int wave_sum(int v) {
+  v = dpp_row_sum(v);
+  return __builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16) +
+         __builtin_amdgcn_readlane(v, 32) + __builtin_amdgcn_readlane(v, 48);
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Exact for values on a common fixed grid (every partial sum is representable).
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_d<0xB1>(v);
+  v += dpp_d<0x4E>(v);
+  v += dpp_d<0x141>(v);
+  v += dpp_d<0x140>(v);
+  return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
 }
 
 __device__ __forceinline__ int wave_exclusive_scan(int v) {
@@ -84,8 +118,11 @@ __device__ __forceinline__ void wave_sync() {
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-__device__ __forceinline__ int spin_of(uint32_t word, int b) {
-  return (int)(int8_t)(uint8_t)(word >> (8 * b));
+__device__ __forceinline__ double uniform_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll));
+  const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
 // ----------------------------------------------------------------------------
@@ -144,25 +181,34 @@ struct EnergyT<0> { using T = int; };
 template <>
 struct EnergyT<1> { using T = double; };
 
+__device__ __forceinline__ uint32_t bit_of(uint32_t word, int pos) { return (word >> pos) & 1u; }
+
+// Spin (+1/-1) of byte b of an int8 quad word.
+__device__ __forceinline__ int spin_of(uint32_t word, int b) {
+  return (int)(int8_t)(uint8_t)(word >> (8 * b));
+}
+
 // ----------------------------------------------------------------------------
 // The fused sweep-block kernel.  JK: 0 = int8 couplings, 1 = float couplings.
-// DEG: neighbour slots (4 for square2d, 6 otherwise).
+// DEG: neighbour slots (4 for square2d, 6 otherwise).  One workgroup runs one
+// unit; its spins live bit-packed in LDS for the whole block of sweeps.
 // ----------------------------------------------------------------------------
-template <int JK, int DEG>
+template <int JK, int DEG, int TL>
 __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __restrict__ units,
                                                           uint32_t n_sweeps, int icm_slots) {
   using E_t = typename EnergyT<JK>::T;
   extern __shared__ __align__(16) unsigned char lds[];
   const UnitDesc U = units[blockIdx.x];
   const int N = U.N, Nc = U.Nc, W = U.W, Wq = U.Wq, K = U.K, R = U.R, Kc = U.Kc, HM = U.HM;
-  const int Wp = 4 * Wq;
-  const LdsLayout lay = lds_layout(N, DEG, Wq, K, R, HM, JK, icm_slots);
+  const int Wp = 4 * Wq, G = bit_words(Wq);
+  const LdsLayout lay = lds_layout(N, DEG, Wq, K, R, HM, JK, icm_slots, TL);
 
   uint32_t* sp = (uint32_t*)(lds + lay.sp);
-  uint16_t* nbr = (uint16_t*)(lds + lay.nbr);
-  uint16_t* clist = (uint16_t*)(lds + lay.clist);
-  int8_t* cj = (int8_t*)(lds + lay.coup);
-  float* cf = (float*)(lds + lay.coup);
+  // TL: tables in LDS; otherwise read-only global memory (cached in L1/L2)
+  const uint16_t* nbr = TL ? (const uint16_t*)(lds + lay.nbr) : U.nbr;
+  const uint16_t* clist = TL ? (const uint16_t*)(lds + lay.clist) : U.clist;
+  const int8_t* cj = TL ? (const int8_t*)(lds + lay.coup) : (const int8_t*)U.coup;
+  const float* cf = TL ? (const float*)(lds + lay.coup) : (const float*)U.coup;
   int* tau = (int*)(lds + lay.tau);
   int* at = (int*)(lds + lay.at);
   int* gauge = (int*)(lds + lay.gauge);
@@ -170,21 +216,41 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
   uint32_t* thr = (uint32_t*)(lds + lay.thr);
   double* beta = (double*)(lds + lay.beta);
   float* bl2e = (float*)(lds + lay.bl2e);
+  uint32_t* ptu = (uint32_t*)(lds + lay.ptu);
   int* parent_all = (int*)(lds + lay.parent);
   unsigned long long* mask_all = (unsigned long long*)(lds + lay.mask);
   unsigned long long* stats = (unsigned long long*)(lds + lay.stats);
 
   const int tid = threadIdx.x, nthr = blockDim.x;
-  // ---- load the unit into LDS ----
-  for (int x = tid; x < Wq * N; x += nthr) sp[x] = U.spins[x];
-  for (int x = tid; x < N * DEG; x += nthr) nbr[x] = U.nbr[x];
-  for (int x = tid; x < N; x += nthr) clist[x] = U.clist[x];
-  if (JK) {
-    for (int x = tid; x < N * DEG; x += nthr) cf[x] = ((const float*)U.coup)[x];
-  } else {
-    for (int x = tid; x < N * DEG; x += nthr) cj[x] = ((const int8_t*)U.coup)[x];
-    for (int x = tid; x < K * HM; x += nthr) thr[x] = U.thr[x];
+  // ---- load the unit into LDS; int8 quad words -> bit-packed words ----
+  for (int x = tid; x < G * N; x += nthr) {
+    const int g = x / N, i = x - g * N;
+    uint32_t bits = 0;
+    for (int qq = 0; qq < 8; ++qq) {
+      const int q = 8 * g + qq;
+      if (q >= Wq) break;
+      const uint32_t w = U.spins[(size_t)q * N + i];
+      // byte 0x01 = up, 0xFF = down: bit 7 of each byte is the down flag
+      const uint32_t d = (w >> 7) & 0x01010101u;
+      bits |= ((d & 1u) | ((d >> 7) & 2u) | ((d >> 14) & 4u) | ((d >> 21) & 8u)) << (4 * qq);
+    }
+    sp[x] = bits;
   }
+  if (TL) {
+    uint16_t* nbr_w = (uint16_t*)(lds + lay.nbr);
+    uint16_t* clist_w = (uint16_t*)(lds + lay.clist);
+    for (int x = tid; x < N * DEG; x += nthr) nbr_w[x] = U.nbr[x];
+    for (int x = tid; x < N; x += nthr) clist_w[x] = U.clist[x];
+    if (JK) {
+      float* cf_w = (float*)(lds + lay.coup);
+      for (int x = tid; x < N * DEG; x += nthr) cf_w[x] = ((const float*)U.coup)[x];
+    } else {
+      int8_t* cj_w = (int8_t*)(lds + lay.coup);
+      for (int x = tid; x < N * DEG; x += nthr) cj_w[x] = ((const int8_t*)U.coup)[x];
+    }
+  }
+  if (!JK)
+    for (int x = tid; x < K * HM; x += nthr) thr[x] = U.thr[x];
   for (int x = tid; x < Wp; x += nthr) {
     tau[x] = U.tau[x];
     gauge[x] = U.gauge[x];
@@ -222,8 +288,8 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
             if (cur_q >= 0) {
 #pragma unroll
               for (int b = 0; b < 4; ++b) {
-                E_t v = wave_sum(acc[b]);
-                if (lane == 0 && v != (E_t)0) atomicAdd(&energy[4 * cur_q + b], v);
+                const E_t v = wave_sum(acc[b]);
+                if (lane == b && v != (E_t)0) atomicAdd(&energy[4 * cur_q + b], v);
                 acc[b] = 0;
               }
             }
@@ -232,71 +298,87 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
             for (int b = 0; b < 4; ++b) {
               tq[b] = uniform(4 * q + b < W ? tau[4 * q + b] : K);
               if (tq[b] < K) {
-                if (JK) { bq[b] = beta[tq[b]]; lq[b] = bl2e[tq[b]]; }
-                else rowb[b] = tq[b] * HM;
+                if (JK) {
+                  bq[b] = uniform_d(beta[tq[b]]);
+                  lq[b] = __int_as_float(uniform(__float_as_int(bl2e[tq[b]])));
+                } else {
+                  rowb[b] = tq[b] * HM;
+                }
               }
             }
           }
           const int j = chunk * 64 + lane;
           if (j < Nc) {
+            const int g = q >> 3, sh = 4 * (q & 7);
+            uint32_t* row = sp + g * N;
             const int i = clist[c * Nc + j];
-            const uint32_t sw = sp[q * N + i];
+            const uint32_t own = row[i] >> sh;
             uint32_t nw[DEG];
 #pragma unroll
-            for (int d = 0; d < DEG; ++d) nw[d] = sp[q * N + nbr[i * DEG + d]];
+            for (int d = 0; d < DEG; ++d) nw[d] = row[nbr[i * DEG + d]] >> sh;
             const Words4 u = philox4x32_10((uint32_t)i, t, (uint32_t)q, kStreamMetro, seed, key);
             uint32_t flip = 0;
             if (JK) {
+              // h = sum_d J_d s_d with s_d = 1 - 2 bit_d: h = sum J - 2 sum_d J_d bit_d (exact)
               double Jd[DEG];
+              double Jsum = 0.0;
 #pragma unroll
-              for (int d = 0; d < DEG; ++d) Jd[d] = (double)cf[i * DEG + d];
+              for (int d = 0; d < DEG; ++d) { Jd[d] = (double)cf[i * DEG + d]; Jsum += Jd[d]; }
 #pragma unroll
               for (int b = 0; b < 4; ++b) {
                 if (tq[b] >= K) continue;
-                double h = 0.0;
+                double m = 0.0;
 #pragma unroll
-                for (int d = 0; d < DEG; ++d) h += Jd[d] * (double)spin_of(nw[d], b);
-                const double dE = 2.0 * (double)spin_of(sw, b) * h;
+                for (int d = 0; d < DEG; ++d) m += Jd[d] * (double)bit_of(nw[d], b);
+                const double h = Jsum - 2.0 * m;
+                const double dE = bit_of(own, b) ? -2.0 * h : 2.0 * h;
                 if (accept_float(u.w[b], dE, bq[b], lq[b])) {
-                  flip |= 0xFEu << (8 * b);
+                  flip |= 1u << b;
                   acc[b] += (E_t)dE;
                 }
               }
             } else {
               int Ji[DEG];
+              int Jsum = 0;
 #pragma unroll
-              for (int d = 0; d < DEG; ++d) Ji[d] = cj[i * DEG + d];
+              for (int d = 0; d < DEG; ++d) { Ji[d] = cj[i * DEG + d]; Jsum += Ji[d]; }
 #pragma unroll
               for (int b = 0; b < 4; ++b) {
                 if (tq[b] >= K) continue;
-                int h = 0;
+                int m = 0;
 #pragma unroll
-                for (int d = 0; d < DEG; ++d) h += Ji[d] * spin_of(nw[d], b);
-                const int e = spin_of(sw, b) * h;  // dE = 2e
+                for (int d = 0; d < DEG; ++d) m += Ji[d] * (int)bit_of(nw[d], b);
+                const int h = Jsum - 2 * m;
+                const int e = bit_of(own, b) ? -h : h;  // dE = 2e
                 if (e <= 0 || u.w[b] < thr[rowb[b] + e]) {
-                  flip |= 0xFEu << (8 * b);
+                  flip |= 1u << b;
                   acc[b] += (E_t)(2 * e);
                 }
               }
             }
-            if (flip) sp[q * N + i] = sw ^ flip;
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-              const unsigned long long bal = __ballot((flip >> (8 * b)) & 0xFEu);
-              metro_acc += (unsigned long long)__popcll(bal);
-            }
+            if (flip) atomicXor(&row[i], flip << sh);
+            metro_acc += (unsigned long long)__popcll(__ballot(flip & 1u)) +
+                         (unsigned long long)__popcll(__ballot(flip & 2u)) +
+                         (unsigned long long)__popcll(__ballot(flip & 4u)) +
+                         (unsigned long long)__popcll(__ballot(flip & 8u));
           }
         }
         if (cur_q >= 0) {
 #pragma unroll
           for (int b = 0; b < 4; ++b) {
-            E_t v = wave_sum(acc[b]);
-            if (lane == 0 && v != (E_t)0) atomicAdd(&energy[4 * cur_q + b], v);
+            const E_t v = wave_sum(acc[b]);
+            if (lane == b && v != (E_t)0) atomicAdd(&energy[4 * cur_q + b], v);
           }
         }
         __syncthreads();
       }
     }
+    // PT random numbers do not depend on the state: draw them now, in parallel.
+    if (flags & kFlagPt)
+      for (int x = tid; x < (K - 1) * R; x += nthr) {
+        const int k = x / R, r = x - k * R;
+        ptu[x] = philox4x32_10((uint32_t)k, t, (uint32_t)r, kStreamPt, seed, key).w[0];
+      }
 
     // ---------------- steps 2a + 2b: isoenergetic cluster moves ----------------
     if (Kc > 0) {
@@ -311,17 +393,17 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
         int nown = N - i0;
         nown = nown < 0 ? 0 : (nown > spl ? spl : nown);
         const unsigned long long own_mask = nown >= 64 ? ~0ull : ((1ull << nown) - 1ull);
-        const unsigned char* spb = (const unsigned char*)sp;
-        unsigned char* spw = (unsigned char*)sp;
         for (int mv = wave; mv < nmoves; mv += slots) {
           const int k = mv / half, p = mv - k * half;
           const int a = at[k * R + 2 * p], b = at[k * R + 2 * p + 1];
-          const int offa = (a >> 2) * N * 4 + (a & 3), offb = (b >> 2) * N * 4 + (b & 3);
-          const int gx = gauge[a] ^ gauge[b];
+          uint32_t* rowa = sp + (a >> 5) * N;
+          uint32_t* rowb = sp + (b >> 5) * N;
+          const int pa = a & 31, pb = b & 31;
+          const uint32_t gx = (uint32_t)(gauge[a] ^ gauge[b]);
           unsigned long long m = 0;
           for (int s2 = 0; s2 < nown; ++s2) {
             const int i = i0 + s2;
-            const int diff = (spb[offa + 4 * i] != spb[offb + 4 * i]) ^ gx;
+            const uint32_t diff = bit_of(rowa[i], pa) ^ bit_of(rowb[i], pb) ^ gx;
             m |= (unsigned long long)diff << s2;
           }
           int n = wave_sum((int)__popcll(m));
@@ -353,9 +435,8 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
             for (int s2 = 0; s2 < nown; ++s2)
               if ((m >> s2) & 1ull) parent[i0 + s2] = i0 + s2;
             wave_sync();
-            for (int s2 = 0; s2 < nown; ++s2) {
-              if (!((m >> s2) & 1ull)) continue;
-              const int i = i0 + s2;
+            for (unsigned long long mm = m; mm; mm &= mm - 1ull) {
+              const int i = i0 + (int)__builtin_ctzll(mm);
 #pragma unroll
               for (int d = 0; d < DEG; ++d) {
                 const int jn = nbr[i * DEG + d];
@@ -365,41 +446,43 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
               }
             }
             wave_sync();
-            for (int s2 = 0; s2 < nown; ++s2)
-              if ((m >> s2) & 1ull) {
-                const int r0 = uf_find(parent, i0 + s2);
-                __hip_atomic_store(&parent[i0 + s2], r0, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_WAVEFRONT);
-              }
+            for (unsigned long long mm = m; mm; mm &= mm - 1ull) {
+              const int i = i0 + (int)__builtin_ctzll(mm);
+              const int r0 = uf_find(parent, i);
+              __hip_atomic_store(&parent[i], r0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+            }
             wave_sync();
             const int root = uf_load(parent, seedsite);
             // energy change of replica a from the bonds that cross the cluster boundary
             unsigned long long cl = 0;
-            for (int s2 = 0; s2 < nown; ++s2) {
-              if (!((m >> s2) & 1ull)) continue;
+            for (unsigned long long mm = m; mm; mm &= mm - 1ull) {
+              const int s2 = (int)__builtin_ctzll(mm);
               const int i = i0 + s2;
               if (uf_load(parent, i) != root) continue;
               cl |= 1ull << s2;
               ++csize;
-              const int si = (int)(int8_t)spb[offa + 4 * i];
+              const int si = 1 - 2 * (int)bit_of(rowa[i], pa);
 #pragma unroll
               for (int d = 0; d < DEG; ++d) {
                 const int jn = nbr[i * DEG + d];
                 const int jl = jn / spl, js = jn - jl * spl;
                 const bool jin = ((maskw[jl] >> js) & 1ull) && uf_load(parent, jn) == root;
                 if (jin) continue;
-                const int sj = (int)(int8_t)spb[offa + 4 * jn];
+                const int sj = 1 - 2 * (int)bit_of(rowa[jn], pa);
                 if (JK) dEa += (E_t)((double)cf[i * DEG + d] * (double)(si * sj));
                 else dEa += (E_t)(cj[i * DEG + d] * si * sj);
               }
             }
             wave_sync();
-            for (int s2 = 0; s2 < nown; ++s2)
-              if ((cl >> s2) & 1ull) {
-                const int i = i0 + s2;
-                spw[offa + 4 * i] ^= 0xFEu;
-                spw[offb + 4 * i] ^= 0xFEu;
+            for (unsigned long long mm = cl; mm; mm &= mm - 1ull) {
+              const int i = i0 + (int)__builtin_ctzll(mm);
+              if (rowa == rowb) {
+                atomicXor(&rowa[i], (1u << pa) | (1u << pb));
+              } else {
+                atomicXor(&rowa[i], 1u << pa);
+                atomicXor(&rowb[i], 1u << pb);
               }
+            }
             dEa = wave_sum(dEa);
             csize = wave_sum(csize);
             if (lane == 0) {
@@ -429,8 +512,8 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
           wave_sync();
         }
       }
-      __syncthreads();
     }
+    __syncthreads();
 
     // ---------------- step 3: parallel tempering ---------------------------------
     if (flags & kFlagPt) {
@@ -440,20 +523,13 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
         for (int k = 0; r < R && k + 1 < K; ++k) {
           const int x = at[k * R + r], y = at[(k + 1) * R + r];
           bool accept;
+          const uint32_t u = ptu[k * R + r];
           if (JK) {
             const double D = (double)energy[y] - (double)energy[x];
-            accept = D <= 0.0;
-            if (!accept) {
-              const uint32_t u = philox4x32_10((uint32_t)k, t, (uint32_t)r, kStreamPt, seed, key).w[0];
-              accept = (double)u * 0x1p-32 < exp(-((beta[k] - beta[k + 1]) * D));
-            }
+            accept = D <= 0.0 || (double)u * 0x1p-32 < exp(-((beta[k] - beta[k + 1]) * D));
           } else {
             const int D = (int)energy[y] - (int)energy[x];
-            accept = D <= 0;
-            if (!accept) {
-              const uint32_t u = philox4x32_10((uint32_t)k, t, (uint32_t)r, kStreamPt, seed, key).w[0];
-              accept = D <= U.ptlen && u < U.ptthr[k * U.ptlen + (D - 1)];
-            }
+            accept = D <= 0 || (D <= U.ptlen && u < U.ptthr[k * U.ptlen + (D - 1)]);
           }
           if (accept) {
             at[k * R + r] = y;
@@ -473,10 +549,17 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
     }
   }
 
-  // ---- store the unit back ----
+  // ---- store the unit back (bit-packed -> int8 quad words) ----
   if (lane == 0 && metro_acc) atomicAdd(&stats[kStatMetroAcc], metro_acc);
   __syncthreads();
-  for (int x = tid; x < Wq * N; x += nthr) U.spins[x] = sp[x];
+  for (int x = tid; x < Wq * N; x += nthr) {
+    const int q = x / N, i = x - q * N;
+    const uint32_t nib = (sp[(q >> 3) * N + i] >> (4 * (q & 7))) & 0xFu;
+    uint32_t w = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) w |= (((nib >> b) & 1u) ? 0xFFu : 0x01u) << (8 * b);
+    U.spins[x] = w;
+  }
   for (int x = tid; x < Wp; x += nthr) {
     U.tau[x] = tau[x];
     U.gauge[x] = (uint8_t)gauge[x];
@@ -560,35 +643,39 @@ __global__ void energy_kernel(const uint32_t* spins, const uint16_t* nbr, const 
 // ----------------------------------------------------------------------------
 extern "C" {
 
-int icmk_launch_sweep(const icm::UnitDesc* d_units, int n_units, int jkind, int deg,
+int icmk_launch_sweep(const icm::UnitDesc* d_units, int n_units, int jkind, int deg, int tables,
                       uint32_t n_sweeps, int threads, int icm_slots, size_t lds_bytes,
                       hipStream_t stream) {
   if (n_units <= 0) return 0;
   dim3 grid(n_units), block(threads);
-  if (jkind == 0 && deg == 4)
-    hipLaunchKernelGGL((icm::sweep_block_kernel<0, 4>), grid, block, lds_bytes, stream, d_units,
-                       n_sweeps, icm_slots);
-  else if (jkind == 0 && deg == 6)
-    hipLaunchKernelGGL((icm::sweep_block_kernel<0, 6>), grid, block, lds_bytes, stream, d_units,
-                       n_sweeps, icm_slots);
-  else if (jkind == 1 && deg == 4)
-    hipLaunchKernelGGL((icm::sweep_block_kernel<1, 4>), grid, block, lds_bytes, stream, d_units,
-                       n_sweeps, icm_slots);
-  else if (jkind == 1 && deg == 6)
-    hipLaunchKernelGGL((icm::sweep_block_kernel<1, 6>), grid, block, lds_bytes, stream, d_units,
-                       n_sweeps, icm_slots);
-  else
-    return (int)hipErrorInvalidValue;
+#define ICM_LAUNCH(JK, DEG, TL)                                                            \
+  hipLaunchKernelGGL((icm::sweep_block_kernel<JK, DEG, TL>), grid, block, lds_bytes, stream, \
+                     d_units, n_sweeps, icm_slots)
+  const int sel = (jkind ? 4 : 0) + (deg == 6 ? 2 : 0) + (tables ? 1 : 0);
+  switch (sel) {
+    case 0: ICM_LAUNCH(0, 4, 0); break;
+    case 1: ICM_LAUNCH(0, 4, 1); break;
+    case 2: ICM_LAUNCH(0, 6, 0); break;
+    case 3: ICM_LAUNCH(0, 6, 1); break;
+    case 4: ICM_LAUNCH(1, 4, 0); break;
+    case 5: ICM_LAUNCH(1, 4, 1); break;
+    case 6: ICM_LAUNCH(1, 6, 0); break;
+    case 7: ICM_LAUNCH(1, 6, 1); break;
+    default: return (int)hipErrorInvalidValue;
+  }
+#undef ICM_LAUNCH
+  if (deg != 4 && deg != 6) return (int)hipErrorInvalidValue;
   return (int)hipGetLastError();
 }
 
 int icmk_set_lds_limit(size_t bytes) {
   hipError_t e = hipSuccess;
-  const void* fns[4] = {(const void*)icm::sweep_block_kernel<0, 4>,
-                        (const void*)icm::sweep_block_kernel<0, 6>,
-                        (const void*)icm::sweep_block_kernel<1, 4>,
-                        (const void*)icm::sweep_block_kernel<1, 6>};
-  for (int x = 0; x < 4; ++x) {
+  const void* fns[8] = {
+      (const void*)icm::sweep_block_kernel<0, 4, 0>, (const void*)icm::sweep_block_kernel<0, 4, 1>,
+      (const void*)icm::sweep_block_kernel<0, 6, 0>, (const void*)icm::sweep_block_kernel<0, 6, 1>,
+      (const void*)icm::sweep_block_kernel<1, 4, 0>, (const void*)icm::sweep_block_kernel<1, 4, 1>,
+      (const void*)icm::sweep_block_kernel<1, 6, 0>, (const void*)icm::sweep_block_kernel<1, 6, 1>};
+  for (int x = 0; x < 8; ++x) {
     hipError_t r = hipFuncSetAttribute(fns[x], hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (r != hipSuccess) e = r;
   }

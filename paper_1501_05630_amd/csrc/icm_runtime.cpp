@@ -24,7 +24,7 @@
 #include "icm_internal.h"
 
 extern "C" {
-int icmk_launch_sweep(const icm::UnitDesc* d_units, int n_units, int jkind, int deg,
+int icmk_launch_sweep(const icm::UnitDesc* d_units, int n_units, int jkind, int deg, int tables,
                       uint32_t n_sweeps, int threads, int icm_slots, size_t lds_bytes,
                       hipStream_t stream);
 int icmk_set_lds_limit(size_t bytes);
@@ -225,8 +225,8 @@ struct Instance {
   // device regions
   std::vector<void*> blocks;  // everything this instance owns in the arena
   UnitDesc unit{};
-  size_t lds_bytes_at(int slots) const {
-    return icm::lds_layout(N, deg, Wq, K, R, HM, jkind, slots).total;
+  size_t lds_bytes_at(int slots, int tables) const {
+    return icm::lds_layout(N, deg, Wq, K, R, HM, jkind, slots, tables).total;
   }
 };
 
@@ -246,7 +246,7 @@ struct icm_ctx {
   std::map<int32_t, std::unique_ptr<Instance>> instances;
   int32_t next_handle = 1;
   size_t lds_limit = 65536;
-  icm_run_config cfg{512, 256, 0, 8};
+  icm_run_config cfg{512, 256, 0, 8, 0};
   // unit tables cached per (handle list)
   std::map<std::vector<int32_t>, UnitDesc*> unit_tables;
   // captured graphs per (handle list, sweeps per launch, launches)
@@ -281,6 +281,7 @@ struct Request {
   uint32_t n_sweeps = 0, done_sweeps = 0;
   int32_t handle = -1;
   bool done = false;
+  int error = ICM_OK;
   std::chrono::steady_clock::time_point t_submit, t_done;
   std::vector<int64_t> energies;
   std::vector<int8_t> states;
@@ -646,15 +647,24 @@ std::vector<Group> group_handles(icm_ctx* c, const int32_t* handles, int n) {
   return g;
 }
 
-int effective_slots(icm_ctx* c, const std::vector<int32_t>& hs, int threads, int want, size_t& lds) {
-  int slots = std::max(1, std::min(want, threads / 64));
-  for (;;) {
-    lds = 0;
-    for (int32_t h : hs) lds = std::max(lds, find(c, h)->lds_bytes_at(slots));
-    if (lds <= c->lds_limit || slots == 1) break;
-    --slots;
+// Picks the ICM slot count and where the tables live so that the largest unit
+// of the group fits the LDS limit: tables in LDS with as many slots as asked,
+// else fewer slots, else tables in global memory.
+int effective_slots(icm_ctx* c, const std::vector<int32_t>& hs, int threads, int want, size_t& lds,
+                    int& tables) {
+  const int top = std::max(1, std::min(want, threads / 64));
+  const int first = c->cfg.table_placement == 2 ? 0 : 1;
+  const int last = c->cfg.table_placement == 1 ? 1 : 0;
+  for (tables = first; tables >= last; --tables) {
+    for (int slots = top; slots >= 1; --slots) {
+      lds = 0;
+      for (int32_t h : hs) lds = std::max(lds, find(c, h)->lds_bytes_at(slots, tables));
+      if (lds <= c->lds_limit) return slots;
+      if (tables && slots <= std::min(top, 4)) break;  // prefer global tables over < 4 slots
+    }
   }
-  return slots;
+  tables = 0;
+  return 1;
 }
 
 int unit_table(icm_ctx* c, const std::vector<int32_t>& hs, UnitDesc** out) {
@@ -674,7 +684,8 @@ int unit_table(icm_ctx* c, const std::vector<int32_t>& hs, UnitDesc** out) {
 int launch_group(icm_ctx* c, const Group& g, uint32_t n_sweeps, bool per_instance) {
   const int threads = c->cfg.threads;
   size_t lds = 0;
-  const int slots = effective_slots(c, g.handles, threads, c->cfg.icm_slots, lds);
+  int tables = 1;
+  const int slots = effective_slots(c, g.handles, threads, c->cfg.icm_slots, lds, tables);
   if (lds > c->lds_limit)
     return fail(c, ICM_E_INVALID, "instance needs %zu bytes of LDS, the device allows %zu", lds, c->lds_limit);
   const uint32_t spl = c->cfg.sweeps_per_launch > 0 ? (uint32_t)c->cfg.sweeps_per_launch : n_sweeps;
@@ -686,7 +697,7 @@ int launch_group(icm_ctx* c, const Group& g, uint32_t n_sweeps, bool per_instanc
       if (rc) return rc;
       for (uint32_t done = 0; done < n_sweeps; done += spl) {
         const uint32_t n = std::min(spl, n_sweeps - done);
-        KERNEL_OK(c, icmk_launch_sweep(d, 1, g.jkind, g.deg, n, threads, slots, lds, c->stream));
+        KERNEL_OK(c, icmk_launch_sweep(d, 1, g.jkind, g.deg, tables, n, threads, slots, lds, c->stream));
       }
     }
     return ICM_OK;
@@ -696,7 +707,7 @@ int launch_group(icm_ctx* c, const Group& g, uint32_t n_sweeps, bool per_instanc
   if (rc) return rc;
   const uint32_t full = n_sweeps / spl, rest = n_sweeps % spl;
   if (c->cfg.use_graph && full > 1) {
-    icm_ctx::GraphKey key{g.handles, spl, full, threads, slots};
+    icm_ctx::GraphKey key{g.handles, spl, full, threads, slots + 64 * tables};
     auto it = c->graphs.find(key);
     if (it == c->graphs.end()) {
       // Capture on a private stream (the context stream may be the legacy null
@@ -707,8 +718,8 @@ int launch_group(icm_ctx* c, const Group& g, uint32_t n_sweeps, bool per_instanc
       hipGraph_t graph;
       HIP_OK(c, hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
       for (uint32_t x = 0; x < full; ++x) {
-        int e = icmk_launch_sweep(d, (int)g.handles.size(), g.jkind, g.deg, spl, threads, slots, lds,
-                                  c->capture_stream);
+        int e = icmk_launch_sweep(d, (int)g.handles.size(), g.jkind, g.deg, tables, spl, threads,
+                                  slots, lds, c->capture_stream);
         if (e) {
           hipGraph_t dummy;
           (void)hipStreamEndCapture(c->capture_stream, &dummy);
@@ -724,10 +735,10 @@ int launch_group(icm_ctx* c, const Group& g, uint32_t n_sweeps, bool per_instanc
     HIP_OK(c, hipGraphLaunch(it->second, c->stream));
   } else {
     for (uint32_t x = 0; x < full; ++x)
-      KERNEL_OK(c, icmk_launch_sweep(d, (int)g.handles.size(), g.jkind, g.deg, spl, threads, slots, lds, c->stream));
+      KERNEL_OK(c, icmk_launch_sweep(d, (int)g.handles.size(), g.jkind, g.deg, tables, spl, threads, slots, lds, c->stream));
   }
   if (rest)
-    KERNEL_OK(c, icmk_launch_sweep(d, (int)g.handles.size(), g.jkind, g.deg, rest, threads, slots, lds, c->stream));
+    KERNEL_OK(c, icmk_launch_sweep(d, (int)g.handles.size(), g.jkind, g.deg, tables, rest, threads, slots, lds, c->stream));
   return ICM_OK;
 }
 
@@ -940,6 +951,9 @@ int icm_set_run_config(icm_ctx* c, const icm_run_config* cfg) {
   n.use_graph = cfg->use_graph ? 1 : 0;
   if (cfg->icm_slots < 0 || cfg->icm_slots > 16) return fail(c, ICM_E_INVALID, "icm_slots must be 0..16");
   if (cfg->icm_slots) n.icm_slots = cfg->icm_slots;
+  if (cfg->table_placement < 0 || cfg->table_placement > 2)
+    return fail(c, ICM_E_INVALID, "table_placement must be 0, 1 or 2");
+  n.table_placement = cfg->table_placement;
   c->cfg = n;
   return ICM_OK;
 }
@@ -1092,15 +1106,26 @@ void serve_loop(icm_ctx* c) {
       std::unique_lock<std::mutex> lk(c->mu);
       if (active.empty())
         c->cv.wait_for(lk, std::chrono::milliseconds(2), [&] { return !c->queue.empty() || !c->serving; });
-      if (!c->serving && active.empty() && c->queue.empty()) break;
+      if (!c->serving && active.empty()) {
+        // stopping: whatever is still queued is returned unrun
+        for (auto& r : c->queue) {
+          r->error = ICM_E_BUSY;
+          r->done = true;
+          r->t_done = std::chrono::steady_clock::now();
+        }
+        c->queue.clear();
+        break;
+      }
       // admission: as many queued requests as the arena holds, in arrival order
       while (!c->queue.empty() && !c->poisoned) {
         std::shared_ptr<Request> r = c->queue.front();
         int32_t h = -1;
         int rc = add_instance_impl(c, &r->desc, &h);
-        if (rc == ICM_E_NOMEM) { c->poisoned = false; break; }
+        if (rc == ICM_E_NOMEM && !active.empty()) break;  // wait for a retirement
         c->queue.pop_front();
-        if (rc != ICM_OK || icm_init_states(c, h) != ICM_OK) {
+        if (rc == ICM_OK) rc = icm_init_states(c, h);
+        if (rc != ICM_OK) {  // invalid, or larger than the whole arena
+          r->error = rc;
           r->done = true;
           r->t_done = std::chrono::steady_clock::now();
           continue;
@@ -1124,7 +1149,11 @@ void serve_loop(icm_ctx* c) {
         hipStreamSynchronize(c->stream) != hipSuccess) {
       c->poisoned = true;
       std::lock_guard<std::mutex> lk(c->mu);
-      for (auto& r : active) { r->done = true; r->t_done = std::chrono::steady_clock::now(); }
+      for (auto& r : active) {
+        r->error = ICM_E_DEVICE;
+        r->done = true;
+        r->t_done = std::chrono::steady_clock::now();
+      }
       active.clear();
       break;
     }
@@ -1223,9 +1252,10 @@ int icm_take_result(icm_ctx* c, uint64_t ticket, int64_t* energies, int8_t* stat
   if (it == c->requests.end()) return ICM_E_NOTFOUND;
   Request& r = *it->second;
   if (!r.done) return ICM_E_BUSY;
-  if (r.energies.empty()) {  // the request failed (invalid or device error)
+  if (r.error != ICM_OK || r.energies.empty()) {  // the request failed
+    const int e = r.error != ICM_OK ? r.error : ICM_E_DEVICE;
     c->requests.erase(it);
-    return c->poisoned ? ICM_E_DEVICE : ICM_E_INVALID;
+    return e;
   }
   if ((energies && cap_e < r.energies.size()) || (states && cap_s < r.states.size())) return ICM_E_BUFSIZE;
   if (energies) std::memcpy(energies, r.energies.data(), r.energies.size() * 8);

@@ -40,7 +40,7 @@ class Stats(ctypes.Structure):
 
 class RunConfig(ctypes.Structure):
     _fields_ = [("threads", _I32), ("sweeps_per_launch", _I32), ("use_graph", _I32),
-                ("icm_slots", _I32)]
+                ("icm_slots", _I32), ("table_placement", _I32)]
 
 
 EXPORTS = {
@@ -195,15 +195,17 @@ class Context:
     def icm_sync(self):
         _check(self.h, self._lib.icm_sync(self.h), "icm_sync")
 
-    def icm_set_run_config(self, threads=0, sweeps_per_launch=0, use_graph=0, icm_slots=0):
-        cfg = RunConfig(threads, sweeps_per_launch, use_graph, icm_slots)
+    def icm_set_run_config(self, threads=0, sweeps_per_launch=0, use_graph=0, icm_slots=0,
+                           table_placement=0):
+        cfg = RunConfig(threads, sweeps_per_launch, use_graph, icm_slots, table_placement)
         _check(self.h, self._lib.icm_set_run_config(self.h, ctypes.byref(cfg)), "icm_set_run_config")
 
     def icm_get_run_config(self):
         cfg = RunConfig()
         _check(self.h, self._lib.icm_get_run_config(self.h, ctypes.byref(cfg)), "icm_get_run_config")
         return dict(threads=cfg.threads, sweeps_per_launch=cfg.sweeps_per_launch,
-                    use_graph=cfg.use_graph, icm_slots=cfg.icm_slots)
+                    use_graph=cfg.use_graph, icm_slots=cfg.icm_slots,
+                    table_placement=cfg.table_placement)
 
     # -- readout ---------------------------------------------------------------
     def icm_read_energies(self, h):

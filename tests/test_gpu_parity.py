@@ -194,15 +194,31 @@ def test_batched_per_instance_and_graph_agree(ctx):
             assert np.array_equal(a[x][0], y[x][0]) and np.array_equal(a[x][1], y[x][1]), x
 
 
-@pytest.mark.parametrize("threads,slots", [(256, 1), (512, 3), (1024, 8), (1024, 16)])
-def test_launch_shape_does_not_change_results(ctx, threads, slots):
-    J, temps, kc, spec = inputs.workload_instance("3d_L8_gauss_1024inst", 1)
-    h, o = make_pair(ctx, spec["topology"], 8, J, temps, 4, kc, icm.FLAG_2A | icm.FLAG_PT, key=1)
-    ctx.icm_set_run_config(threads=threads, icm_slots=slots, sweeps_per_launch=7)
+@pytest.mark.parametrize("threads,slots,tables", [(256, 1, 1), (512, 3, 2), (1024, 8, 1),
+                                                  (1024, 16, 2), (512, 8, 2)])
+@pytest.mark.parametrize("name", ["3d_L8_gauss_1024inst", "chimera_C12_int3_512inst"])
+def test_launch_shape_does_not_change_results(ctx, threads, slots, tables, name):
+    J, temps, kc, spec = inputs.workload_instance(name, 1)
+    h, o = make_pair(ctx, spec["topology"], spec["L"], J, temps, spec["n_replicas"], kc,
+                     icm.FLAG_2A | icm.FLAG_PT, key=1, j_scale=spec["j_scale"])
+    ctx.icm_set_run_config(threads=threads, icm_slots=slots, sweeps_per_launch=7,
+                           table_placement=tables)
     ctx.icm_init_states(h)
     o.init_hot()
-    run_both(ctx, h, o, [20], f"threads={threads} slots={slots}")
-    ctx.icm_set_run_config(threads=512, icm_slots=8, sweeps_per_launch=256)
+    run_both(ctx, h, o, [20], f"threads={threads} slots={slots} tables={tables}")
+    ctx.icm_set_run_config(threads=512, icm_slots=8, sweeps_per_launch=256, table_placement=0)
+    ctx.icm_remove_instance(h)
+
+
+def test_large_3d_L16_runs_with_tables_in_global_memory(ctx):
+    # 4096 sites x 96 walkers: the spins fit LDS bit-packed, the tables do not.
+    J = inputs.gaussian_couplings(inputs.CUBIC3D, 16, inputs.make_rng(75, 0))
+    temps = inputs.geometric_temps(0.2, 2.0, 24)
+    h, o = make_pair(ctx, inputs.CUBIC3D, 16, J, temps, 4, inputs.icm_cutoff(temps),
+                     icm.FLAG_2A | icm.FLAG_PT, key=2)
+    ctx.icm_init_states(h)
+    o.init_hot()
+    run_both(ctx, h, o, [1, 4], "3d L16")
     ctx.icm_remove_instance(h)
 
 

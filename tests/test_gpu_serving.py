@@ -1,0 +1,114 @@
+"""Serving: continuous batching of thermalization requests (icm_submit / icm_poll /
+icm_take_result).  Requests of mixed topology and size arrive while others are
+running; a request's result is bit-identical whether it ran alone or in the mix,
+and equal to the oracle's trajectory of the same request."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle as orc
+from paper_1501_05630_amd import icm, inputs
+
+pytestmark = pytest.mark.gpu
+SEED = inputs.MASTER_SEED
+
+
+def requests(n, rng):
+    out = []
+    for x in range(n):
+        kind = x % 3
+        if kind == 0:
+            L = [8, 16][x % 2]
+            J = inputs.pm_j_couplings(inputs.SQUARE2D, L, rng)
+            temps = inputs.geometric_temps(0.2, 1.6, 8)
+            d = dict(topology=inputs.SQUARE2D, L=L, couplings=J, temps=temps, n_replicas=2,
+                     icm_ntemps=inputs.icm_cutoff(temps), j_scale=1)
+        elif kind == 1:
+            L = [4, 6][x % 2]
+            J = inputs.gaussian_couplings(inputs.CUBIC3D, L, rng)
+            temps = inputs.geometric_temps(0.2, 2.0, 6)
+            d = dict(topology=inputs.CUBIC3D, L=L, couplings=J, temps=temps, n_replicas=4,
+                     icm_ntemps=inputs.icm_cutoff(temps), j_scale=1)
+        else:
+            C = [2, 4][x % 2]
+            J = inputs.int_couplings(inputs.CHIMERA, C, rng)
+            temps = inputs.geometric_temps(0.2, 3.0, 10)
+            d = dict(topology=inputs.CHIMERA, L=C, couplings=J, temps=temps, n_replicas=2,
+                     icm_ntemps=inputs.icm_cutoff(temps), j_scale=3)
+        d["instance_key"] = 1000 + x
+        d["flags"] = icm.FLAG_2A | icm.FLAG_PT
+        out.append(d)
+    return out
+
+
+def shape(d):
+    N = inputs.n_sites(d["topology"], d["L"])
+    return len(d["temps"]), d["n_replicas"], N
+
+
+def serve(reqs, sweeps, arena_bytes, block, stagger_s=0.0):
+    ctx = icm.Context(arena_bytes=arena_bytes, seed=SEED)
+    ctx.icm_serve_start(block)
+    tickets = []
+    for d in reqs:
+        tickets.append(ctx.icm_submit(sweeps, **d))
+        if stagger_s:
+            time.sleep(stagger_s)
+    results, lat = [], []
+    deadline = time.time() + 120
+    for t, d in zip(tickets, reqs):
+        while True:
+            done, us = ctx.icm_poll(t)
+            if done:
+                break
+            assert time.time() < deadline, "serving did not finish in time"
+            time.sleep(0.001)
+        lat.append(us)
+        results.append(ctx.icm_take_result(t, *shape(d)))
+    ctx.icm_serve_stop()
+    ctx.close()
+    return results, lat
+
+
+def test_alone_equals_mix_and_oracle():
+    rng = inputs.make_rng(80, 0)
+    reqs = requests(9, rng)
+    sweeps = 96
+    # tiny arena: only a few requests fit at once, the rest queue for admission
+    mixed, lat = serve(reqs, sweeps, arena_bytes=2 << 20, block=32, stagger_s=0.002)
+    alone = [serve([d], sweeps, arena_bytes=64 << 20, block=32)[0][0] for d in reqs[:4]]
+    for x in range(4):
+        assert np.array_equal(mixed[x][0], alone[x][0]), x
+        assert np.array_equal(mixed[x][1], alone[x][1]), x
+    for x in (0, 1, 2):
+        d = reqs[x]
+        o = orc.Sim(d["topology"], d["L"], d["couplings"], d["temps"], d["n_replicas"],
+                    d["icm_ntemps"], flags=orc.FLAG_2A | orc.FLAG_PT, seed=SEED,
+                    instance_key=d["instance_key"], j_scale=d["j_scale"])
+        o.init_hot()
+        o.run(sweeps)
+        assert np.array_equal(mixed[x][1], o.states()), x
+        assert np.array_equal(mixed[x][0], o.energies_raw()), x
+    assert all(v > 0 for v in lat)
+
+
+def test_request_larger_than_the_arena_fails_cleanly():
+    rng = inputs.make_rng(81, 0)
+    d = requests(1, rng)[0]
+    d["L"], d["couplings"] = 64, inputs.pm_j_couplings(inputs.SQUARE2D, 64, rng)
+    d["temps"] = inputs.geometric_temps(0.2, 1.6, 32)
+    d["icm_ntemps"] = inputs.icm_cutoff(d["temps"])
+    d["n_replicas"] = 16  # 512 walkers x 4096 sites: more than the 1 MiB arena
+    ctx = icm.Context(arena_bytes=1 << 20, seed=SEED)
+    ctx.icm_serve_start(16)
+    t = ctx.icm_submit(16, **d)
+    deadline = time.time() + 30
+    while not ctx.icm_poll(t)[0]:
+        assert time.time() < deadline
+        time.sleep(0.001)
+    with pytest.raises(icm.IcmError) as e:
+        ctx.icm_take_result(t, *shape(d))
+    assert e.value.code == icm.ICM_E_NOMEM
+    ctx.icm_serve_stop()
+    ctx.close()
