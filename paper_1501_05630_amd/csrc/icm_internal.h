@@ -60,16 +60,19 @@ ICM_HD uint32_t align16(uint32_t x) { return (x + 15u) & ~15u; }
 // Spins are bit-packed in LDS: word (g, i) holds walkers 32g..32g+31 at site i,
 // bit set = spin down.
 struct LdsLayout {
-  uint32_t sp, nbr, clist, coup, tau, at, gauge, energy, thr, beta, bl2e, ptu, parent, mask,
-      stats, total;
+  uint32_t sp, nbr, clist, coup, tau, at, gauge, energy, thr, beta, bl2e, ptu, queue, visited,
+      parent, mask, stats, total;
 };
 
 ICM_HD int bit_words(int Wq) { return (4 * Wq + 31) / 32; }
 
 // tables = 1: neighbour table, colour lists and couplings are copied into LDS;
 // tables = 0: they are read from global memory (for units too large otherwise).
+// Per ICM slot (one wave working on one move): the BFS queue [N] u16, the
+// visited bitset [N/32] u32, the mask words [64] u64, and, when labels are
+// recorded, the union-find parent array [N] int.
 ICM_HD LdsLayout lds_layout(int N, int deg, int Wq, int K, int R, int HM, int jkind, int slots,
-                            int tables) {
+                            int tables, int record) {
   LdsLayout L{};
   uint32_t o = 0;
   const int Wp = 4 * Wq;
@@ -86,7 +89,9 @@ ICM_HD LdsLayout lds_layout(int N, int deg, int Wq, int K, int R, int HM, int jk
   L.beta = o;    o = align16(o + 8u * K);
   L.bl2e = o;    o = align16(o + 4u * K);
   L.ptu = o;     o = align16(o + 4u * (K > 1 ? K - 1 : 1) * R);
-  L.parent = o;  o = align16(o + 4u * N * slots);
+  L.queue = o;   o = align16(o + 2u * N * slots);
+  L.visited = o; o = align16(o + 4u * ((N + 31) / 32) * slots);
+  L.parent = o;  o = align16(o + (record ? 4u * N * slots : 0u));
   L.mask = o;    o = align16(o + 8u * 64 * slots);
   L.stats = o;   o = align16(o + 8u * kNumStats);
   L.total = o;

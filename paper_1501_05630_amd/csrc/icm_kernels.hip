@@ -8,10 +8,12 @@
 //            one Philox quad at one site with one Philox block;
 //   step 2a  spin reversal recorded as a per-walker gauge bit;
 //   step 2b  one wavefront per cluster move: q-mask by bit compare, n_minus by
-//            popcount + DPP wave reduction, seed by wave prefix scan, connected
-//            component by union-find with LDS atomicMin hooking and pointer
-//            jumping, exact energy update from the cluster boundary, flip in
-//            both replicas;
+//            popcount + DPP wave reduction, seed by ballot counts, the seed's
+//            cluster grown breadth-first with the frontier compacted by ballot +
+//            mbcnt, flipped in both replicas, the energy updated exactly from the
+//            bonds that leave the cluster; for the label readout the full
+//            component labelling by union-find (LDS atomicMin hooking, pointer
+//            jumping);
 //   step 3   parallel tempering: one lane per chain scans the neighbouring
 //            temperature pairs in ascending order.
 #include <hip/hip_runtime.h>
@@ -201,7 +203,8 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
   const UnitDesc U = units[blockIdx.x];
   const int N = U.N, Nc = U.Nc, W = U.W, Wq = U.Wq, K = U.K, R = U.R, Kc = U.Kc, HM = U.HM;
   const int Wp = 4 * Wq, G = bit_words(Wq);
-  const LdsLayout lay = lds_layout(N, DEG, Wq, K, R, HM, JK, icm_slots, TL);
+  const LdsLayout lay = lds_layout(N, DEG, Wq, K, R, HM, JK, icm_slots, TL,
+                                   (U.flags & kFlagRecord) ? 1 : 0);
 
   uint32_t* sp = (uint32_t*)(lds + lay.sp);
   // TL: tables in LDS; otherwise read-only global memory (cached in L1/L2)
@@ -217,7 +220,6 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
   double* beta = (double*)(lds + lay.beta);
   float* bl2e = (float*)(lds + lay.bl2e);
   uint32_t* ptu = (uint32_t*)(lds + lay.ptu);
-  int* parent_all = (int*)(lds + lay.parent);
   unsigned long long* mask_all = (unsigned long long*)(lds + lay.mask);
   unsigned long long* stats = (unsigned long long*)(lds + lay.stats);
 
@@ -381,17 +383,21 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
       }
 
     // ---------------- steps 2a + 2b: isoenergetic cluster moves ----------------
+    // One wave per move (temperature k, chain pair p).  Site i is owned by lane
+    // i % 64 as bit i / 64 of the lane's mask word, so ascending site order is
+    // (bit, lane) order.
     if (Kc > 0) {
       const int half = R >> 1;
       const int nmoves = Kc * half;
       const int slots = icm_slots < nwaves ? icm_slots : nwaves;
       if (wave < slots) {
-        int* parent = parent_all + wave * N;
+        const int spl = (N + 63) >> 6;  // mask bits per lane
+        const int nvis = (N + 31) >> 5;
+        uint16_t* queue = (uint16_t*)(lds + lay.queue) + wave * N;
+        uint32_t* visited = (uint32_t*)(lds + lay.visited) + wave * nvis;
+        int* parent = (int*)(lds + lay.parent) + wave * N;
         unsigned long long* maskw = mask_all + wave * 64;
-        const int spl = (N + 63) >> 6;  // sites per lane, lane l owns [l*spl, l*spl+spl)
-        const int i0 = lane * spl;
-        int nown = N - i0;
-        nown = nown < 0 ? 0 : (nown > spl ? spl : nown);
+        int nown = N > lane ? (N - lane + 63) >> 6 : 0;  // sites owned by this lane
         const unsigned long long own_mask = nown >= 64 ? ~0ull : ((1ull << nown) - 1ull);
         for (int mv = wave; mv < nmoves; mv += slots) {
           const int k = mv / half, p = mv - k * half;
@@ -400,15 +406,16 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
           uint32_t* rowb = sp + (b >> 5) * N;
           const int pa = a & 31, pb = b & 31;
           const uint32_t gx = (uint32_t)(gauge[a] ^ gauge[b]);
+          // site overlap q_i = -1  <=>  the two replicas differ at i
           unsigned long long m = 0;
           for (int s2 = 0; s2 < nown; ++s2) {
-            const int i = i0 + s2;
+            const int i = s2 * 64 + lane;
             const uint32_t diff = bit_of(rowa[i], pa) ^ bit_of(rowb[i], pb) ^ gx;
             m |= (unsigned long long)diff << s2;
           }
           int n = wave_sum((int)__popcll(m));
           int twoa = 0;
-          if ((flags & kFlag2a) && 2 * n > N) {
+          if ((flags & kFlag2a) && 2 * n > N) {  // step 2a: reverse the second replica
             m = ~m & own_mask;
             n = N - n;
             twoa = 1;
@@ -419,63 +426,105 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
           int csize = 0;
           E_t dEa = 0;
           if (n > 0) {
+            // step 2b: the idx-th q = -1 site in ascending order seeds the cluster.
+            // Ballot s gives the mask bits of sites 64s..64s+63, i.e. mask words
+            // 2s and 2s+1; visited starts as the complement of the mask, so a
+            // claim succeeds exactly on an unvisited q = -1 site.
             const uint32_t u = philox4x32_10((uint32_t)mv, t, 0u, kStreamIcm, seed, key).w[0];
-            const int idx = (int)(((unsigned long long)u * (unsigned long long)n) >> 32);
-            const int cnt = __popcll(m);
-            const int ex = wave_exclusive_scan(cnt);
-            int cand = -1;
-            if (idx >= ex && idx < ex + cnt) {
-              unsigned long long mm = m;
-              for (int r2 = idx - ex; r2 > 0; --r2) mm &= mm - 1ull;  // drop lowest set bits
-              cand = i0 + (int)__builtin_ctzll(mm);
+            int rem = (int)(((unsigned long long)u * (unsigned long long)n) >> 32);
+            for (int s2 = 0; s2 < spl; ++s2) {
+              unsigned long long bal = __ballot((m >> s2) & 1ull);
+              if (lane == 0) {
+                visited[2 * s2] = ~(uint32_t)bal;
+                if (2 * s2 + 1 < nvis) visited[2 * s2 + 1] = ~(uint32_t)(bal >> 32);
+              }
+              const int c2 = __popcll(bal);
+              if (rem >= 0 && rem < c2) {
+                for (; rem > 0; --rem) bal &= bal - 1ull;
+                seedsite = s2 * 64 + (int)__builtin_ctzll(bal);
+                rem = -1;
+              } else if (rem >= 0) {
+                rem -= c2;
+              }
             }
-            const unsigned long long owner = __ballot(cand >= 0);
-            seedsite = __shfl(cand, (int)__builtin_ctzll(owner), 64);
-            // union-find over the q = -1 subgraph
-            for (int s2 = 0; s2 < nown; ++s2)
-              if ((m >> s2) & 1ull) parent[i0 + s2] = i0 + s2;
-            wave_sync();
-            for (unsigned long long mm = m; mm; mm &= mm - 1ull) {
-              const int i = i0 + (int)__builtin_ctzll(mm);
+            seedsite = uniform(seedsite);
+            if ((flags & kFlagRecord) && s + 1 == n_sweeps) {
+              // full labelling for the readout: union-find over the q = -1 subgraph,
+              // roots hooked towards the smaller index, then path compression
+              for (int s2 = 0; s2 < nown; ++s2)
+                if ((m >> s2) & 1ull) parent[s2 * 64 + lane] = s2 * 64 + lane;
+              wave_sync();
+              for (unsigned long long mm = m; mm; mm &= mm - 1ull) {
+                const int i = (int)__builtin_ctzll(mm) * 64 + lane;
 #pragma unroll
-              for (int d = 0; d < DEG; ++d) {
-                const int jn = nbr[i * DEG + d];
-                if (jn <= i) continue;
-                const int jl = jn / spl, js = jn - jl * spl;
-                if ((maskw[jl] >> js) & 1ull) uf_union(parent, i, jn);
+                for (int d = 0; d < DEG; ++d) {
+                  const int jn = nbr[i * DEG + d];
+                  if (jn > i && ((maskw[jn & 63] >> (jn >> 6)) & 1ull)) uf_union(parent, i, jn);
+                }
+              }
+              wave_sync();
+              for (unsigned long long mm = m; mm; mm &= mm - 1ull) {
+                const int i = (int)__builtin_ctzll(mm) * 64 + lane;
+                const int r0 = uf_find(parent, i);
+                __hip_atomic_store(&parent[i], r0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
               }
             }
             wave_sync();
-            for (unsigned long long mm = m; mm; mm &= mm - 1ull) {
-              const int i = i0 + (int)__builtin_ctzll(mm);
-              const int r0 = uf_find(parent, i);
-              __hip_atomic_store(&parent[i], r0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+            if (lane == 0) {
+              visited[seedsite >> 5] |= 1u << (seedsite & 31);
+              queue[0] = (uint16_t)seedsite;
             }
             wave_sync();
-            const int root = uf_load(parent, seedsite);
-            // energy change of replica a from the bonds that cross the cluster boundary
-            unsigned long long cl = 0;
-            for (unsigned long long mm = m; mm; mm &= mm - 1ull) {
-              const int s2 = (int)__builtin_ctzll(mm);
-              const int i = i0 + s2;
-              if (uf_load(parent, i) != root) continue;
-              cl |= 1ull << s2;
-              ++csize;
-              const int si = 1 - 2 * (int)bit_of(rowa[i], pa);
+            // grow the seed's cluster breadth-first; the frontier is compacted with
+            // ballot + mbcnt
+            int head = 0, tail = 1;
+            while (head < tail) {
+              const int cnt = (tail - head) < 64 ? (tail - head) : 64;
+              const bool act = lane < cnt;
+              int jn[DEG];
+              bool claim[DEG];
+              if (act) {
+                const int i = queue[head + lane];
+#pragma unroll
+                for (int d = 0; d < DEG; ++d) jn[d] = nbr[i * DEG + d];
+#pragma unroll
+                for (int d = 0; d < DEG; ++d) {
+                  const uint32_t bitm = 1u << (jn[d] & 31);
+                  claim[d] = !(atomicOr(&visited[jn[d] >> 5], bitm) & bitm);
+                }
+              } else {
+#pragma unroll
+                for (int d = 0; d < DEG; ++d) { jn[d] = 0; claim[d] = false; }
+              }
+              head += cnt;
 #pragma unroll
               for (int d = 0; d < DEG; ++d) {
-                const int jn = nbr[i * DEG + d];
-                const int jl = jn / spl, js = jn - jl * spl;
-                const bool jin = ((maskw[jl] >> js) & 1ull) && uf_load(parent, jn) == root;
-                if (jin) continue;
-                const int sj = 1 - 2 * (int)bit_of(rowa[jn], pa);
-                if (JK) dEa += (E_t)((double)cf[i * DEG + d] * (double)(si * sj));
-                else dEa += (E_t)(cj[i * DEG + d] * si * sj);
+                const unsigned long long bal = __ballot(claim[d]);
+                const int pos = tail + (int)__builtin_amdgcn_mbcnt_hi(
+                                           (uint32_t)(bal >> 32),
+                                           __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+                if (claim[d]) queue[pos] = (uint16_t)jn[d];
+                tail += __popcll(bal);
               }
+              wave_sync();
             }
-            wave_sync();
-            for (unsigned long long mm = cl; mm; mm &= mm - 1ull) {
-              const int i = i0 + (int)__builtin_ctzll(mm);
+            csize = tail;
+            // every q = -1 neighbour of the cluster is in it, so the bonds that
+            // leave the cluster are exactly those to q = +1 sites: their energy
+            // in replica a changes sign (pre-flip spins), then the cluster flips
+            // in both replicas
+            for (int x = lane; x < tail; x += 64) {
+              const int i = queue[x];
+              const uint32_t bi = bit_of(rowa[i], pa);
+#pragma unroll
+              for (int d = 0; d < DEG; ++d) {
+                const int j2 = nbr[i * DEG + d];
+                if (!((maskw[j2 & 63] >> (j2 >> 6)) & 1ull)) {
+                  const int sgn = (bi ^ bit_of(rowa[j2], pa)) ? -1 : 1;  // s_a,i s_a,j
+                  if (JK) dEa += (E_t)((double)cf[i * DEG + d] * (double)sgn);
+                  else dEa += (E_t)(cj[i * DEG + d] * sgn);
+                }
+              }
               if (rowa == rowb) {
                 atomicXor(&rowa[i], (1u << pa) | (1u << pb));
               } else {
@@ -484,7 +533,6 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
               }
             }
             dEa = wave_sum(dEa);
-            csize = wave_sum(csize);
             if (lane == 0) {
               energy[a] += (E_t)2 * dEa;
               energy[b] -= (E_t)2 * dEa;
@@ -501,7 +549,7 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
           if ((flags & kFlagRecord) && s + 1 == n_sweeps) {
             int* lab = U.labels + (size_t)mv * N;
             for (int s2 = 0; s2 < nown; ++s2) {
-              const int i = i0 + s2;
+              const int i = s2 * 64 + lane;
               lab[i] = (n > 0 && ((m >> s2) & 1ull)) ? uf_load(parent, i) : -1;
             }
             if (lane == 0) {

@@ -226,7 +226,8 @@ struct Instance {
   std::vector<void*> blocks;  // everything this instance owns in the arena
   UnitDesc unit{};
   size_t lds_bytes_at(int slots, int tables) const {
-    return icm::lds_layout(N, deg, Wq, K, R, HM, jkind, slots, tables).total;
+    return icm::lds_layout(N, deg, Wq, K, R, HM, jkind, slots, tables,
+                           (flags & ICM_FLAG_RECORD_LABELS) ? 1 : 0).total;
   }
 };
 
