@@ -120,7 +120,8 @@ typedef struct {
   int32_t threads;          /* threads per workgroup: 256, 512 or 1024 */
   int32_t sweeps_per_launch;/* sweeps fused into one kernel launch */
   int32_t use_graph;        /* 1: replay launches from a captured hipGraph */
-  int32_t icm_slots;        /* concurrent ICM moves per workgroup (LDS scratch) */
+  int32_t icm_slots;        /* ICM moves in flight per workgroup, 1..64 (LDS scratch);
+                               up to 4 per wavefront, in lane groups */
   int32_t table_placement;  /* 0: automatic, 1: neighbour/coupling tables in LDS,
                                2: tables read from global memory */
 } icm_run_config;

@@ -68,9 +68,9 @@ ICM_HD int bit_words(int Wq) { return (4 * Wq + 31) / 32; }
 
 // tables = 1: neighbour table, colour lists and couplings are copied into LDS;
 // tables = 0: they are read from global memory (for units too large otherwise).
-// Per ICM slot (one wave working on one move): the BFS queue [N] u16, the
-// visited bitset [N/32] u32, the mask words [64] u64, and, when labels are
-// recorded, the union-find parent array [N] int.
+// Per ICM move slot (one move in flight): the BFS queue [N] u16, the visited
+// and q-mask bitsets [N/32] u32 each, and, when labels are recorded, the
+// union-find parent array [N] int.
 ICM_HD LdsLayout lds_layout(int N, int deg, int Wq, int K, int R, int HM, int jkind, int slots,
                             int tables, int record) {
   LdsLayout L{};
@@ -92,7 +92,7 @@ ICM_HD LdsLayout lds_layout(int N, int deg, int Wq, int K, int R, int HM, int jk
   L.queue = o;   o = align16(o + 2u * N * slots);
   L.visited = o; o = align16(o + 4u * ((N + 31) / 32) * slots);
   L.parent = o;  o = align16(o + (record ? 4u * N * slots : 0u));
-  L.mask = o;    o = align16(o + 8u * 64 * slots);
+  L.mask = o;    o = align16(o + 4u * ((N + 31) / 32) * slots);
   L.stats = o;   o = align16(o + 8u * kNumStats);
   L.total = o;
   return L;

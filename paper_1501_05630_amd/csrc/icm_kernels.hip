@@ -220,7 +220,6 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
   double* beta = (double*)(lds + lay.beta);
   float* bl2e = (float*)(lds + lay.bl2e);
   uint32_t* ptu = (uint32_t*)(lds + lay.ptu);
-  unsigned long long* mask_all = (unsigned long long*)(lds + lay.mask);
   unsigned long long* stats = (unsigned long long*)(lds + lay.stats);
 
   const int tid = threadIdx.x, nthr = blockDim.x;
@@ -383,143 +382,185 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
       }
 
     // ---------------- steps 2a + 2b: isoenergetic cluster moves ----------------
-    // One wave per move (temperature k, chain pair p).  Site i is owned by lane
-    // i % 64 as bit i / 64 of the lane's mask word, so ascending site order is
-    // (bit, lane) order.
+    // icm_slots moves are in flight per workgroup: each ICM wave sets up P moves
+    // one after the other with the full wave (mask, 2a, seed), then grows their
+    // clusters concurrently in P lane groups of 64/P lanes, then updates energies
+    // and flips.  Site i is owned by lane i % 64 as bit i / 64 of its mask word,
+    // so ascending site order is (bit, lane) order and ballot s is mask words 2s,
+    // 2s+1.
     if (Kc > 0) {
       const int half = R >> 1;
       const int nmoves = Kc * half;
-      const int slots = icm_slots < nwaves ? icm_slots : nwaves;
-      if (wave < slots) {
+      const int P = icm_slots >= 4 * nwaves ? 4 : (icm_slots >= 2 * nwaves ? 2 : 1);
+      const int iwaves = (icm_slots / P) < nwaves ? (icm_slots / P) : nwaves;
+      if (wave < iwaves) {
         const int spl = (N + 63) >> 6;  // mask bits per lane
         const int nvis = (N + 31) >> 5;
-        uint16_t* queue = (uint16_t*)(lds + lay.queue) + wave * N;
-        uint32_t* visited = (uint32_t*)(lds + lay.visited) + wave * nvis;
-        int* parent = (int*)(lds + lay.parent) + wave * N;
-        unsigned long long* maskw = mask_all + wave * 64;
-        int nown = N > lane ? (N - lane + 63) >> 6 : 0;  // sites owned by this lane
+        const int lpm = 64 / P;         // lanes per move in the BFS
+        const int grp = lane / lpm, li = lane - grp * lpm;
+        const int nown = N > lane ? (N - lane + 63) >> 6 : 0;  // sites owned by this lane
         const unsigned long long own_mask = nown >= 64 ? ~0ull : ((1ull << nown) - 1ull);
-        for (int mv = wave; mv < nmoves; mv += slots) {
-          const int k = mv / half, p = mv - k * half;
-          const int a = at[k * R + 2 * p], b = at[k * R + 2 * p + 1];
-          uint32_t* rowa = sp + (a >> 5) * N;
-          uint32_t* rowb = sp + (b >> 5) * N;
-          const int pa = a & 31, pb = b & 31;
-          const uint32_t gx = (uint32_t)(gauge[a] ^ gauge[b]);
-          // site overlap q_i = -1  <=>  the two replicas differ at i
-          unsigned long long m = 0;
-          for (int s2 = 0; s2 < nown; ++s2) {
-            const int i = s2 * 64 + lane;
-            const uint32_t diff = bit_of(rowa[i], pa) ^ bit_of(rowb[i], pb) ^ gx;
-            m |= (unsigned long long)diff << s2;
-          }
-          int n = wave_sum((int)__popcll(m));
-          int twoa = 0;
-          if ((flags & kFlag2a) && 2 * n > N) {  // step 2a: reverse the second replica
-            m = ~m & own_mask;
-            n = N - n;
-            twoa = 1;
-            if (lane == 0) gauge[b] ^= 1;
-          }
-          maskw[lane] = m;
-          int seedsite = -1;
-          int csize = 0;
-          E_t dEa = 0;
-          if (n > 0) {
-            // step 2b: the idx-th q = -1 site in ascending order seeds the cluster.
-            // Ballot s gives the mask bits of sites 64s..64s+63, i.e. mask words
-            // 2s and 2s+1; visited starts as the complement of the mask, so a
-            // claim succeeds exactly on an unvisited q = -1 site.
-            const uint32_t u = philox4x32_10((uint32_t)mv, t, 0u, kStreamIcm, seed, key).w[0];
-            int rem = (int)(((unsigned long long)u * (unsigned long long)n) >> 32);
-            for (int s2 = 0; s2 < spl; ++s2) {
-              unsigned long long bal = __ballot((m >> s2) & 1ull);
+        const unsigned long long gmask = lpm == 64 ? ~0ull : ((1ull << lpm) - 1ull);
+        const unsigned long long lt_in_grp = (li == 0) ? 0ull : (((1ull << li) - 1ull) << (grp * lpm));
+        for (int mbase = wave * P; mbase < nmoves; mbase += iwaves * P) {
+          // ---- set-up, one move at a time with the full wave ----
+          int mv_g[4], a_g[4], b_g[4], n_g[4];
+#pragma unroll
+          for (int g = 0; g < 4; ++g) {
+            mv_g[g] = -1; a_g[g] = 0; b_g[g] = 0; n_g[g] = 0;
+            if (g >= P || mbase + g >= nmoves) continue;
+            const int mv = mbase + g, slot = wave * P + g;
+            uint16_t* queue = (uint16_t*)(lds + lay.queue) + slot * N;
+            uint32_t* visited = (uint32_t*)(lds + lay.visited) + slot * nvis;
+            uint32_t* mask32 = (uint32_t*)(lds + lay.mask) + slot * nvis;
+            int* parent = (int*)(lds + lay.parent) + slot * N;
+            const int k = mv / half, p = mv - k * half;
+            const int a = at[k * R + 2 * p], b = at[k * R + 2 * p + 1];
+            const uint32_t* rowa = sp + (a >> 5) * N;
+            const uint32_t* rowb = sp + (b >> 5) * N;
+            const int pa = a & 31, pb = b & 31;
+            const uint32_t gx = (uint32_t)(gauge[a] ^ gauge[b]);
+            // site overlap q_i = -1  <=>  the two replicas differ at i
+            unsigned long long m = 0;
+            for (int s2 = 0; s2 < nown; ++s2) {
+              const int i = s2 * 64 + lane;
+              const uint32_t diff = bit_of(rowa[i], pa) ^ bit_of(rowb[i], pb) ^ gx;
+              m |= (unsigned long long)diff << s2;
+            }
+            int n = wave_sum((int)__popcll(m));
+            const bool twoa = (flags & kFlag2a) && 2 * n > N;
+            if (twoa) {  // step 2a: reverse the second replica
+              m = ~m & own_mask;
+              n = N - n;
+              if (lane == 0) gauge[b] ^= 1;
+            }
+            int seedsite = -1;
+            if (n > 0) {
+              // step 2b: the idx-th q = -1 site in ascending order seeds the cluster;
+              // visited starts as the complement of the mask
+              const uint32_t u = philox4x32_10((uint32_t)mv, t, 0u, kStreamIcm, seed, key).w[0];
+              int rem = (int)(((unsigned long long)u * (unsigned long long)n) >> 32);
+              for (int s2 = 0; s2 < spl; ++s2) {
+                unsigned long long bal = __ballot((m >> s2) & 1ull);
+                if (lane == 0) {
+                  mask32[2 * s2] = (uint32_t)bal;
+                  visited[2 * s2] = ~(uint32_t)bal;
+                  if (2 * s2 + 1 < nvis) {
+                    mask32[2 * s2 + 1] = (uint32_t)(bal >> 32);
+                    visited[2 * s2 + 1] = ~(uint32_t)(bal >> 32);
+                  }
+                }
+                const int c2 = __popcll(bal);
+                if (rem >= 0 && rem < c2) {
+                  for (; rem > 0; --rem) bal &= bal - 1ull;
+                  seedsite = s2 * 64 + (int)__builtin_ctzll(bal);
+                  rem = -1;
+                } else if (rem >= 0) {
+                  rem -= c2;
+                }
+              }
+              seedsite = uniform(seedsite);
+              wave_sync();
               if (lane == 0) {
-                visited[2 * s2] = ~(uint32_t)bal;
-                if (2 * s2 + 1 < nvis) visited[2 * s2 + 1] = ~(uint32_t)(bal >> 32);
+                visited[seedsite >> 5] |= 1u << (seedsite & 31);
+                queue[0] = (uint16_t)seedsite;
               }
-              const int c2 = __popcll(bal);
-              if (rem >= 0 && rem < c2) {
-                for (; rem > 0; --rem) bal &= bal - 1ull;
-                seedsite = s2 * 64 + (int)__builtin_ctzll(bal);
-                rem = -1;
-              } else if (rem >= 0) {
-                rem -= c2;
+              if ((flags & kFlagRecord) && s + 1 == n_sweeps) {
+                // full labelling for the readout: union-find over the q = -1
+                // subgraph, roots hooked towards the smaller index, path compression
+                for (int s2 = 0; s2 < nown; ++s2)
+                  if ((m >> s2) & 1ull) parent[s2 * 64 + lane] = s2 * 64 + lane;
+                wave_sync();
+                for (unsigned long long mm = m; mm; mm &= mm - 1ull) {
+                  const int i = (int)__builtin_ctzll(mm) * 64 + lane;
+#pragma unroll
+                  for (int d = 0; d < DEG; ++d) {
+                    const int jn = nbr[i * DEG + d];
+                    if (jn > i && ((mask32[jn >> 5] >> (jn & 31)) & 1u)) uf_union(parent, i, jn);
+                  }
+                }
+                wave_sync();
+                for (unsigned long long mm = m; mm; mm &= mm - 1ull) {
+                  const int i = (int)__builtin_ctzll(mm) * 64 + lane;
+                  const int r0 = uf_find(parent, i);
+                  __hip_atomic_store(&parent[i], r0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+                }
               }
             }
-            seedsite = uniform(seedsite);
             if ((flags & kFlagRecord) && s + 1 == n_sweeps) {
-              // full labelling for the readout: union-find over the q = -1 subgraph,
-              // roots hooked towards the smaller index, then path compression
-              for (int s2 = 0; s2 < nown; ++s2)
-                if ((m >> s2) & 1ull) parent[s2 * 64 + lane] = s2 * 64 + lane;
               wave_sync();
-              for (unsigned long long mm = m; mm; mm &= mm - 1ull) {
-                const int i = (int)__builtin_ctzll(mm) * 64 + lane;
-#pragma unroll
-                for (int d = 0; d < DEG; ++d) {
-                  const int jn = nbr[i * DEG + d];
-                  if (jn > i && ((maskw[jn & 63] >> (jn >> 6)) & 1ull)) uf_union(parent, i, jn);
-                }
+              int* lab = U.labels + (size_t)mv * N;
+              for (int s2 = 0; s2 < nown; ++s2) {
+                const int i = s2 * 64 + lane;
+                lab[i] = (n > 0 && ((m >> s2) & 1ull)) ? uf_load(parent, i) : -1;
               }
-              wave_sync();
-              for (unsigned long long mm = m; mm; mm &= mm - 1ull) {
-                const int i = (int)__builtin_ctzll(mm) * 64 + lane;
-                const int r0 = uf_find(parent, i);
-                __hip_atomic_store(&parent[i], r0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+              if (lane == 0) {
+                U.seeds[mv] = seedsite;
+                U.seeds[nmoves + mv] = n;
               }
             }
-            wave_sync();
             if (lane == 0) {
-              visited[seedsite >> 5] |= 1u << (seedsite & 31);
-              queue[0] = (uint16_t)seedsite;
+              atomicAdd(&stats[kStatIcmMoves], 1ull);
+              if (twoa) atomicAdd(&stats[kStat2a], 1ull);
+              if (n > 0) atomicAdd(&stats[kStatIcmNontrivial], 1ull);
             }
-            wave_sync();
-            // grow the seed's cluster breadth-first; the frontier is compacted with
-            // ballot + mbcnt
-            int head = 0, tail = 1;
-            while (head < tail) {
-              const int cnt = (tail - head) < 64 ? (tail - head) : 64;
-              const bool act = lane < cnt;
-              int jn[DEG];
-              bool claim[DEG];
-              if (act) {
-                const int i = queue[head + lane];
+            mv_g[g] = mv; a_g[g] = a; b_g[g] = b; n_g[g] = n;
+          }
+          wave_sync();
+          // ---- the P clusters grow concurrently, one lane group each ----
+          const int my_mv = grp == 0 ? mv_g[0] : grp == 1 ? mv_g[1] : grp == 2 ? mv_g[2] : mv_g[3];
+          const int my_n = grp == 0 ? n_g[0] : grp == 1 ? n_g[1] : grp == 2 ? n_g[2] : n_g[3];
+          const int my_a = grp == 0 ? a_g[0] : grp == 1 ? a_g[1] : grp == 2 ? a_g[2] : a_g[3];
+          const int my_b = grp == 0 ? b_g[0] : grp == 1 ? b_g[1] : grp == 2 ? b_g[2] : b_g[3];
+          const int slot = wave * P + grp;
+          uint16_t* queue = (uint16_t*)(lds + lay.queue) + slot * N;
+          uint32_t* visited = (uint32_t*)(lds + lay.visited) + slot * nvis;
+          const uint32_t* mask32 = (const uint32_t*)(lds + lay.mask) + slot * nvis;
+          int head = 0, tail = (my_mv >= 0 && my_n > 0) ? 1 : 0;
+          while (__ballot(head < tail)) {
+            const int cnt = (tail - head) < lpm ? (tail - head) : lpm;
+            const bool act = li < cnt;
+            int jn[DEG];
+            bool claim[DEG];
+            if (act) {
+              const int i = queue[head + li];
 #pragma unroll
-                for (int d = 0; d < DEG; ++d) jn[d] = nbr[i * DEG + d];
-#pragma unroll
-                for (int d = 0; d < DEG; ++d) {
-                  const uint32_t bitm = 1u << (jn[d] & 31);
-                  claim[d] = !(atomicOr(&visited[jn[d] >> 5], bitm) & bitm);
-                }
-              } else {
-#pragma unroll
-                for (int d = 0; d < DEG; ++d) { jn[d] = 0; claim[d] = false; }
-              }
-              head += cnt;
+              for (int d = 0; d < DEG; ++d) jn[d] = nbr[i * DEG + d];
 #pragma unroll
               for (int d = 0; d < DEG; ++d) {
-                const unsigned long long bal = __ballot(claim[d]);
-                const int pos = tail + (int)__builtin_amdgcn_mbcnt_hi(
-                                           (uint32_t)(bal >> 32),
-                                           __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-                if (claim[d]) queue[pos] = (uint16_t)jn[d];
-                tail += __popcll(bal);
+                const uint32_t bitm = 1u << (jn[d] & 31);
+                claim[d] = !(atomicOr(&visited[jn[d] >> 5], bitm) & bitm);
               }
-              wave_sync();
+            } else {
+#pragma unroll
+              for (int d = 0; d < DEG; ++d) { jn[d] = 0; claim[d] = false; }
             }
-            csize = tail;
-            // every q = -1 neighbour of the cluster is in it, so the bonds that
-            // leave the cluster are exactly those to q = +1 sites: their energy
-            // in replica a changes sign (pre-flip spins), then the cluster flips
-            // in both replicas
-            for (int x = lane; x < tail; x += 64) {
+            head += cnt > 0 ? cnt : 0;
+#pragma unroll
+            for (int d = 0; d < DEG; ++d) {
+              const unsigned long long bal = __ballot(claim[d]);
+              const unsigned long long gb = (bal >> (grp * lpm)) & gmask;
+              const int pos = tail + __popcll(bal & lt_in_grp);
+              if (claim[d]) queue[pos] = (uint16_t)jn[d];
+              tail += __popcll(gb);
+            }
+            wave_sync();
+          }
+          // ---- bonds leaving the cluster change sign in replica a (every q = -1
+          // neighbour of the cluster is in it, so they are the bonds to q = +1
+          // sites); then the cluster flips in both replicas ----
+          E_t dEa = 0;
+          if (my_mv >= 0) {
+            uint32_t* rowa = sp + (my_a >> 5) * N;
+            uint32_t* rowb = sp + (my_b >> 5) * N;
+            const int pa = my_a & 31, pb = my_b & 31;
+            for (int x = li; x < tail; x += lpm) {
               const int i = queue[x];
               const uint32_t bi = bit_of(rowa[i], pa);
 #pragma unroll
               for (int d = 0; d < DEG; ++d) {
                 const int j2 = nbr[i * DEG + d];
-                if (!((maskw[j2 & 63] >> (j2 >> 6)) & 1ull)) {
+                if (!((mask32[j2 >> 5] >> (j2 & 31)) & 1u)) {
                   const int sgn = (bi ^ bit_of(rowa[j2], pa)) ? -1 : 1;  // s_a,i s_a,j
                   if (JK) dEa += (E_t)((double)cf[i * DEG + d] * (double)sgn);
                   else dEa += (E_t)(cj[i * DEG + d] * sgn);
@@ -532,30 +573,39 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
                 atomicXor(&rowb[i], 1u << pb);
               }
             }
-            dEa = wave_sum(dEa);
-            if (lane == 0) {
-              energy[a] += (E_t)2 * dEa;
-              energy[b] -= (E_t)2 * dEa;
+          }
+          // per-group sums: DPP row sums are 16-lane sums, groups are 1, 2 or 4 rows
+          E_t rows[4];
+          {
+            E_t v = dEa;
+            if (JK) {
+              double dv = (double)v;
+              dv += dpp_d<0xB1>(dv); dv += dpp_d<0x4E>(dv); dv += dpp_d<0x141>(dv); dv += dpp_d<0x140>(dv);
+#pragma unroll
+              for (int r2 = 0; r2 < 4; ++r2) rows[r2] = (E_t)readlane_d(dv, 16 * r2);
+            } else {
+              int iv = (int)v;
+              iv = dpp_row_sum(iv);
+#pragma unroll
+              for (int r2 = 0; r2 < 4; ++r2) rows[r2] = (E_t)__builtin_amdgcn_readlane(iv, 16 * r2);
             }
           }
           if (lane == 0) {
-            atomicAdd(&stats[kStatIcmMoves], 1ull);
-            if (twoa) atomicAdd(&stats[kStat2a], 1ull);
-            if (n > 0) {
-              atomicAdd(&stats[kStatIcmNontrivial], 1ull);
-              atomicAdd(&stats[kStatIcmSites], (unsigned long long)csize);
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+              if (g >= P || mv_g[g] < 0 || n_g[g] == 0) continue;
+              E_t sum = 0;
+              for (int r2 = g * (4 / P); r2 < (g + 1) * (4 / P); ++r2) sum += rows[r2];
+              energy[a_g[g]] += (E_t)2 * sum;
+              energy[b_g[g]] -= (E_t)2 * sum;
             }
           }
-          if ((flags & kFlagRecord) && s + 1 == n_sweeps) {
-            int* lab = U.labels + (size_t)mv * N;
-            for (int s2 = 0; s2 < nown; ++s2) {
-              const int i = s2 * 64 + lane;
-              lab[i] = (n > 0 && ((m >> s2) & 1ull)) ? uf_load(parent, i) : -1;
-            }
-            if (lane == 0) {
-              U.seeds[mv] = seedsite;
-              U.seeds[nmoves + mv] = n;
-            }
+#pragma unroll
+          for (int g = 0; g < 4; ++g) {
+            if (g >= P) continue;
+            const int tg = __builtin_amdgcn_readlane(tail, g * lpm);
+            if (lane == 0 && mv_g[g] >= 0 && n_g[g] > 0)
+              atomicAdd(&stats[kStatIcmSites], (unsigned long long)tg);
           }
           wave_sync();
         }

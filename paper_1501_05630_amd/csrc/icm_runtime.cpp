@@ -247,7 +247,7 @@ struct icm_ctx {
   std::map<int32_t, std::unique_ptr<Instance>> instances;
   int32_t next_handle = 1;
   size_t lds_limit = 65536;
-  icm_run_config cfg{512, 256, 0, 8, 0};
+  icm_run_config cfg{512, 256, 0, 32, 0};
   // unit tables cached per (handle list)
   std::map<std::vector<int32_t>, UnitDesc*> unit_tables;
   // captured graphs per (handle list, sweeps per launch, launches)
@@ -653,7 +653,7 @@ std::vector<Group> group_handles(icm_ctx* c, const int32_t* handles, int n) {
 // else fewer slots, else tables in global memory.
 int effective_slots(icm_ctx* c, const std::vector<int32_t>& hs, int threads, int want, size_t& lds,
                     int& tables) {
-  const int top = std::max(1, std::min(want, threads / 64));
+  const int top = std::max(1, std::min(want, 4 * (threads / 64)));
   const int first = c->cfg.table_placement == 2 ? 0 : 1;
   const int last = c->cfg.table_placement == 1 ? 1 : 0;
   for (tables = first; tables >= last; --tables) {
@@ -950,7 +950,7 @@ int icm_set_run_config(icm_ctx* c, const icm_run_config* cfg) {
   if (cfg->sweeps_per_launch < 0) return fail(c, ICM_E_INVALID, "negative sweeps_per_launch");
   if (cfg->sweeps_per_launch) n.sweeps_per_launch = cfg->sweeps_per_launch;
   n.use_graph = cfg->use_graph ? 1 : 0;
-  if (cfg->icm_slots < 0 || cfg->icm_slots > 16) return fail(c, ICM_E_INVALID, "icm_slots must be 0..16");
+  if (cfg->icm_slots < 0 || cfg->icm_slots > 64) return fail(c, ICM_E_INVALID, "icm_slots must be 0..64");
   if (cfg->icm_slots) n.icm_slots = cfg->icm_slots;
   if (cfg->table_placement < 0 || cfg->table_placement > 2)
     return fail(c, ICM_E_INVALID, "table_placement must be 0, 1 or 2");

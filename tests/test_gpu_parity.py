@@ -195,7 +195,7 @@ def test_batched_per_instance_and_graph_agree(ctx):
 
 
 @pytest.mark.parametrize("threads,slots,tables", [(256, 1, 1), (512, 3, 2), (1024, 8, 1),
-                                                  (1024, 16, 2), (512, 8, 2)])
+                                                  (1024, 16, 2), (512, 8, 2), (512, 32, 1), (256, 16, 2), (512, 20, 1)])
 @pytest.mark.parametrize("name", ["3d_L8_gauss_1024inst", "chimera_C12_int3_512inst"])
 def test_launch_shape_does_not_change_results(ctx, threads, slots, tables, name):
     J, temps, kc, spec = inputs.workload_instance(name, 1)
