@@ -60,8 +60,8 @@ ICM_HD uint32_t align16(uint32_t x) { return (x + 15u) & ~15u; }
 // Spins are bit-packed in LDS: word (g, i) holds walkers 32g..32g+31 at site i,
 // bit set = spin down.
 struct LdsLayout {
-  uint32_t sp, nbr, clist, coup, tau, at, gauge, energy, thr, beta, bl2e, ptu, queue, visited,
-      parent, mask, stats, total;
+  uint32_t sp, nbr, clist, coup, tau, at, gauge, energy, thr, beta, bl2e, ptu, icmu,
+      queue, visited, parent, mask, stats, total;
 };
 
 ICM_HD int bit_words(int Wq) { return (4 * Wq + 31) / 32; }
@@ -72,7 +72,7 @@ ICM_HD int bit_words(int Wq) { return (4 * Wq + 31) / 32; }
 // and q-mask bitsets [N/32] u32 each, and, when labels are recorded, the
 // union-find parent array [N] int.
 ICM_HD LdsLayout lds_layout(int N, int deg, int Wq, int K, int R, int HM, int jkind, int slots,
-                            int tables, int record) {
+                            int tables, int record, int Kc) {
   LdsLayout L{};
   uint32_t o = 0;
   const int Wp = 4 * Wq;
@@ -89,6 +89,7 @@ ICM_HD LdsLayout lds_layout(int N, int deg, int Wq, int K, int R, int HM, int jk
   L.beta = o;    o = align16(o + 8u * K);
   L.bl2e = o;    o = align16(o + 4u * K);
   L.ptu = o;     o = align16(o + 4u * (K > 1 ? K - 1 : 1) * R);
+  L.icmu = o;    o = align16(o + 4u * (Kc > 0 ? Kc * (R / 2) : 1));
   L.queue = o;   o = align16(o + 2u * N * slots);
   L.visited = o; o = align16(o + 4u * ((N + 31) / 32) * slots);
   L.parent = o;  o = align16(o + (record ? 4u * N * slots : 0u));

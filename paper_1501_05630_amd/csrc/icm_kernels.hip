@@ -37,8 +37,9 @@ __device__ __forceinline__ Words4 philox4x32_10(uint32_t x0, uint32_t x1, uint32
   for (int round = 0; round < 10; ++round) {
     const uint64_t m0 = (uint64_t)0xD2511F53u * x0;
     const uint64_t m1 = (uint64_t)0xCD9E8D57u * x2;
-    const uint32_t y0 = (uint32_t)(m1 >> 32) ^ x1 ^ key0;
-    const uint32_t y2 = (uint32_t)(m0 >> 32) ^ x3 ^ key1;
+    // three-way xor in one v_bitop3_b32 (truth table 0x96)
+    const uint32_t y0 = __builtin_amdgcn_bitop3_b32((uint32_t)(m1 >> 32), x1, key0, 0x96);
+    const uint32_t y2 = __builtin_amdgcn_bitop3_b32((uint32_t)(m0 >> 32), x3, key1, 0x96);
     x1 = (uint32_t)m1;
     x3 = (uint32_t)m0;
     x0 = y0;
@@ -135,13 +136,19 @@ __device__ __forceinline__ double uniform_d(double v) {
 // margin the fast accept/reject can only be taken when the double comparison
 // gives the same answer; the band falls back to the double evaluation.
 // ----------------------------------------------------------------------------
+// Out of line: taken for ~1e-4 of the attempts, and inlining it would keep the
+// double exp's constants in registers across the whole sweep loop.
+__device__ __noinline__ bool accept_exact(uint32_t u, double dE, double beta) {
+  return (double)u * 0x1p-32 < exp(-(beta * dE));
+}
+
 __device__ __forceinline__ bool accept_float(uint32_t u, double dE, double beta, float bl2e) {
   if (dE <= 0.0) return true;
   const float p = __builtin_amdgcn_exp2f(-((float)dE * bl2e));
   const float uf = (float)(u >> 8) * 0x1p-24f;  // exact; true u/2^32 lies in [uf, uf + 2^-24)
   if (uf > p * (1.0f + 0x1p-14f)) return false;
   if (uf + 0x1p-24f <= p * (1.0f - 0x1p-14f)) return true;
-  return (double)u * 0x1p-32 < exp(-(beta * dE));
+  return accept_exact(u, dE, beta);
 }
 
 // ----------------------------------------------------------------------------
@@ -204,7 +211,7 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
   const int N = U.N, Nc = U.Nc, W = U.W, Wq = U.Wq, K = U.K, R = U.R, Kc = U.Kc, HM = U.HM;
   const int Wp = 4 * Wq, G = bit_words(Wq);
   const LdsLayout lay = lds_layout(N, DEG, Wq, K, R, HM, JK, icm_slots, TL,
-                                   (U.flags & kFlagRecord) ? 1 : 0);
+                                   (U.flags & kFlagRecord) ? 1 : 0, Kc);
 
   uint32_t* sp = (uint32_t*)(lds + lay.sp);
   // TL: tables in LDS; otherwise read-only global memory (cached in L1/L2)
@@ -220,6 +227,7 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
   double* beta = (double*)(lds + lay.beta);
   float* bl2e = (float*)(lds + lay.bl2e);
   uint32_t* ptu = (uint32_t*)(lds + lay.ptu);
+  uint32_t* icmu = (uint32_t*)(lds + lay.icmu);
   unsigned long long* stats = (unsigned long long*)(lds + lay.stats);
 
   const int tid = threadIdx.x, nthr = blockDim.x;
@@ -270,6 +278,16 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
 
   for (uint32_t s = 0; s < n_sweeps; ++s) {
     const uint32_t t = t0 + s;
+    // The random numbers of PT and ICM do not depend on the state: draw them
+    // now, in parallel; the barriers of the sweep order them before their use.
+    if (flags & kFlagPt)
+      for (int x = tid; x < (K - 1) * R; x += nthr) {
+        const int k = x / R, r = x - k * R;
+        ptu[x] = philox4x32_10((uint32_t)k, t, (uint32_t)r, kStreamPt, seed, key).w[0];
+      }
+    for (int x = tid; x < Kc * (R >> 1); x += nthr)
+      icmu[x] = philox4x32_10((uint32_t)x, t, 0u, kStreamIcm, seed, key).w[0];
+    if (flags & kFlagSkipMetro) __syncthreads();
     // ---------------- step 1: Metropolis sweep, colour 0 then colour 1 ----------
     if (!(flags & kFlagSkipMetro)) {
       for (int c = 0; c < 2; ++c) {
@@ -283,8 +301,8 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
         int rowb[4] = {0, 0, 0, 0};
         double bq[4] = {0, 0, 0, 0};
         float lq[4] = {0, 0, 0, 0};
-        for (int task = tb; task < te; ++task) {
-          const int q = task / nchunk, chunk = task - q * nchunk;
+        int q = tb / nchunk, chunk = tb - q * nchunk;
+        for (int task = tb; task < te; ++task, (++chunk == nchunk ? (chunk = 0, ++q) : 0)) {
           if (q != cur_q) {
             if (cur_q >= 0) {
 #pragma unroll
@@ -374,12 +392,6 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
         __syncthreads();
       }
     }
-    // PT random numbers do not depend on the state: draw them now, in parallel.
-    if (flags & kFlagPt)
-      for (int x = tid; x < (K - 1) * R; x += nthr) {
-        const int k = x / R, r = x - k * R;
-        ptu[x] = philox4x32_10((uint32_t)k, t, (uint32_t)r, kStreamPt, seed, key).w[0];
-      }
 
     // ---------------- steps 2a + 2b: isoenergetic cluster moves ----------------
     // icm_slots moves are in flight per workgroup: each ICM wave sets up P moves
@@ -438,8 +450,7 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
             if (n > 0) {
               // step 2b: the idx-th q = -1 site in ascending order seeds the cluster;
               // visited starts as the complement of the mask
-              const uint32_t u = philox4x32_10((uint32_t)mv, t, 0u, kStreamIcm, seed, key).w[0];
-              int rem = (int)(((unsigned long long)u * (unsigned long long)n) >> 32);
+              int rem = (int)(((unsigned long long)icmu[mv] * (unsigned long long)n) >> 32);
               for (int s2 = 0; s2 < spl; ++s2) {
                 unsigned long long bal = __ballot((m >> s2) & 1ull);
                 if (lane == 0) {

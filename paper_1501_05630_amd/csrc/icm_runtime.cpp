@@ -227,7 +227,7 @@ struct Instance {
   UnitDesc unit{};
   size_t lds_bytes_at(int slots, int tables) const {
     return icm::lds_layout(N, deg, Wq, K, R, HM, jkind, slots, tables,
-                           (flags & ICM_FLAG_RECORD_LABELS) ? 1 : 0).total;
+                           (flags & ICM_FLAG_RECORD_LABELS) ? 1 : 0, Kc).total;
   }
 };
 
@@ -653,6 +653,7 @@ std::vector<Group> group_handles(icm_ctx* c, const int32_t* handles, int n) {
 // else fewer slots, else tables in global memory.
 int effective_slots(icm_ctx* c, const std::vector<int32_t>& hs, int threads, int want, size_t& lds,
                     int& tables) {
+  // a wave carries at most four moves
   const int top = std::max(1, std::min(want, 4 * (threads / 64)));
   const int first = c->cfg.table_placement == 2 ? 0 : 1;
   const int last = c->cfg.table_placement == 1 ? 1 : 0;
