@@ -19,8 +19,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# VALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T 32-bit lane-ops/s
-VALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
+# VALU issue: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-ops/s (one
+# non-packed 32-bit or FP64 operation per lane per cycle)
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
 def parse():
@@ -31,7 +32,7 @@ def parse():
     ap.add_argument("--workload", default="3d_L8_gauss_1024inst")
     ap.add_argument("--sweeps-per-step", type=int, default=256)
     ap.add_argument("--threads", type=int, default=512)
-    ap.add_argument("--icm-slots", type=int, default=8)
+    ap.add_argument("--icm-slots", type=int, default=32)
     ap.add_argument("--graph", type=int, default=1)
     ap.add_argument("--per-instance-sample", type=int, default=32)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -50,6 +51,33 @@ def algorithmic_bytes_per_sweep(spec, N, n_bonds, jbytes):
     """2 bytes (int8 spin read + write) per attempt plus the couplings once."""
     S = spec["n_temps"] * spec["n_replicas"]
     return 2 * S * N + n_bonds * jbytes
+
+
+def algorithmic_ops_per_attempt(deg, kind):
+    """Fewest VALU lane-operations one Metropolis attempt needs: a quarter of a
+    Philox4x32-10 block (10 rounds of two 32x32->64 multiplies and two 3-input
+    xors), one bit extract and one multiply-add per neighbour, the acceptance
+    (Gaussian: sign, scale by beta, exp, uniform conversion, compare; integer
+    couplings: sign, table index, compare) and the flip."""
+    return 10 + 2 * deg + (5 if kind == "gauss" else 3) + 1
+
+
+def algorithmic_ops_per_move(N):
+    """An ICM move forms the overlap at every site (compare, count): 2 N."""
+    return 2 * N
+
+
+def kernel_source_digest():
+    import hashlib
+    with open(os.path.join(ROOT, "paper_1501_05630_amd", "csrc", "icm_kernels.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+# HBM bytes per launch of the fused kernel from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE passes over this bench's default launch, each scaled by what the
+# same counter reads for a plain 256 MiB device copy.  Only valid for the kernel
+# source it was measured on (digest); null otherwise.
+TRAFFIC = {"3d_L8_gauss_1024inst": {"kernel": None, "bytes_per_launch": None}}
 
 
 def cpu_baseline(name, spec, seconds):
@@ -226,8 +254,15 @@ def main():
     value = attempts / secs
     icm_moves = n_moves_per_sweep * sweeps * n_inst
     launch_ms = ms / args.steps  # one launch of the fused kernel per step
+    deg = {inputs.SQUARE2D: 4, inputs.CUBIC3D: 6, inputs.CHIMERA: 6}[spec["topology"]]
+    ops_per_launch = (algorithmic_ops_per_attempt(deg, spec["kind"]) * S * N
+                      + algorithmic_ops_per_move(N) * n_moves_per_sweep) * spsw * n_inst
+    achieved_tops = ops_per_launch / (launch_ms / 1e3) / 1e12
     bytes_per_launch = algorithmic_bytes_per_sweep(spec, N, n_bonds, jbytes) * spsw * n_inst
     achieved_gbs = bytes_per_launch / (launch_ms / 1e3) / 1e9
+    tr = TRAFFIC.get(name, {})
+    traffic = tr.get("bytes_per_launch") if (tr.get("kernel") == kernel_source_digest()
+                                              and spsw == 256 and args.threads == 512) else None
 
     out = {
         "metric": "spin-flip attempts/s + ICM moves/s, batched vs per-instance; % HBM roofline",
@@ -238,11 +273,16 @@ def main():
         "config": {"workload": name, "instances": n_inst, "topology": inputs.TOPOLOGY_NAMES[spec["topology"]],
                    "L": spec["L"], "N": N, "temps": spec["n_temps"], "replicas": spec["n_replicas"],
                    "icm_temps": kc, "sweeps_per_step": spsw, "threads": args.threads,
-                   "graph": bool(args.graph), "parallelism": "single GPU, one workgroup per instance"},
+                   "icm_slots": args.icm_slots, "graph": bool(args.graph),
+                   "parallelism": "single GPU, one workgroup per instance"},
         "icm_moves_per_s": icm_moves / secs,
-        "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": None,
-                     "bytes_per_attempt": algorithmic_bytes_per_sweep(spec, N, n_bonds, jbytes) / (S * N)},
+        "roofline": {"bound": "alu", "achieved": achieved_tops, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
+                     "frac": achieved_tops / VALU_PEAK_TOPS, "traffic": traffic,
+                     "ops_per_attempt": algorithmic_ops_per_attempt(deg, spec["kind"]),
+                     "ops_per_icm_move": algorithmic_ops_per_move(N)},
+        "hbm_effective": {"achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": achieved_gbs / HBM_PEAK_GBS,
+                          "bytes_per_attempt": algorithmic_bytes_per_sweep(spec, N, n_bonds, jbytes) / (S * N)},
     }
     if not args.no_per_instance:
         sample = hs[: args.per_instance_sample]

@@ -12,7 +12,7 @@
 namespace icm {
 
 constexpr int kMaxDeg = 6;        // neighbour slots per site (2D uses 4)
-constexpr int kMaxSites = 4096;   // one ICM wave holds up to 64 sites per lane
+constexpr int kMaxSites = 4096;   // an ICM lane holds at most two 32-site words of a move
 constexpr int kMaxTemps = 256;
 constexpr int kMaxReplicas = 64;
 
@@ -49,7 +49,8 @@ struct UnitDesc {
   int32_t* seeds;           // [Kc][R/2] seed site, then [Kc][R/2] n_minus
   uint32_t* sweep;          // sweep counter t
   int32_t N, Nc, deg, W, Wq, K, R, Kc, HM, ptlen, jkind, jscale;
-  uint32_t flags, seed, key, pad0;
+  uint32_t flags, seed, key;
+  int32_t topo, L, pad0;    // lattice kind (ICM_TOPO_*) and side / cells per side
 };
 
 constexpr uint32_t kFlag2a = 1, kFlagPt = 2, kFlagRecord = 4, kFlagSkipMetro = 8;
@@ -60,23 +61,44 @@ ICM_HD uint32_t align16(uint32_t x) { return (x + 15u) & ~15u; }
 // Spins are bit-packed in LDS: word (g, i) holds walkers 32g..32g+31 at site i,
 // bit set = spin down.
 struct LdsLayout {
-  uint32_t sp, nbr, clist, coup, tau, at, gauge, energy, thr, beta, bl2e, ptu, icmu,
-      queue, visited, parent, mask, stats, total;
+  uint32_t sp, nbr, clist, coup, tau, at, gauge, energy, thr, beta, bl2e, ptu, icmu, terms, slots,
+      parent, stats, total;
 };
+
+// Neighbour relation of the lattice as bit shifts of a site bitset (for the
+// cluster search): term t adds F[i + shift_t] to site i where bit i of mask_t
+// is set.  2D: 8 terms, 3D: 12 (per axis: +1 step, its periodic wrap, -1 step,
+// its wrap); chimera: 4 inter-cell terms, the in-cell K4,4 handled apart.
+constexpr int kMaxTerms = 12;
+
+ICM_HD int site_words(int N) { return (N + 31) / 32; }
+
+// Lanes that share one ICM move (a power of two >= its bitset words, 16..64).
+ICM_HD int icm_lanes_per_move(int N) {
+  const int nw = site_words(N);
+  return nw <= 16 ? 16 : (nw <= 32 ? 32 : 64);
+}
+
+// Per ICM move slot: two frontier buffers with a zero word on each side,
+// the q-mask and cluster words interleaved, replica a's spin words, the move.
+enum SlotInfo { kInMv = 0, kInA, kInB, kInN, kInSeed, kInInts = 8 };
+ICM_HD int slot_words(int N) { return 2 * (site_words(N) + 2) + 3 * site_words(N) + kInInts; }
+ICM_HD int slots_reserved(int N, int slots) {
+  const int p = 64 / icm_lanes_per_move(N);
+  return slots > p ? slots : p;
+}
 
 ICM_HD int bit_words(int Wq) { return (4 * Wq + 31) / 32; }
 
 // tables = 1: neighbour table, colour lists and couplings are copied into LDS;
 // tables = 0: they are read from global memory (for units too large otherwise).
-// Per ICM move slot (one move in flight): the BFS queue [N] u16, the visited
-// and q-mask bitsets [N/32] u32 each, and, when labels are recorded, the
-// union-find parent array [N] int.
 ICM_HD LdsLayout lds_layout(int N, int deg, int Wq, int K, int R, int HM, int jkind, int slots,
                             int tables, int record, int Kc) {
   LdsLayout L{};
   uint32_t o = 0;
   const int Wp = 4 * Wq;
   const uint32_t tn = tables ? (uint32_t)N : 0u;
+  const uint32_t ns = Kc > 0 ? (uint32_t)slots_reserved(N, slots) : 0u;
   L.sp = o;      o = align16(o + 4u * bit_words(Wq) * N);
   L.nbr = o;     o = align16(o + 2u * tn * deg);
   L.clist = o;   o = align16(o + 2u * tn);
@@ -90,10 +112,9 @@ ICM_HD LdsLayout lds_layout(int N, int deg, int Wq, int K, int R, int HM, int jk
   L.bl2e = o;    o = align16(o + 4u * K);
   L.ptu = o;     o = align16(o + 4u * (K > 1 ? K - 1 : 1) * R);
   L.icmu = o;    o = align16(o + 4u * (Kc > 0 ? Kc * (R / 2) : 1));
-  L.queue = o;   o = align16(o + 2u * N * slots);
-  L.visited = o; o = align16(o + 4u * ((N + 31) / 32) * slots);
-  L.parent = o;  o = align16(o + (record ? 4u * N * slots : 0u));
-  L.mask = o;    o = align16(o + 4u * ((N + 31) / 32) * slots);
+  L.terms = o;   o = align16(o + (Kc > 0 ? 4u * kMaxTerms * (1 + site_words(N)) : 0u));
+  L.slots = o;   o = align16(o + 4u * slot_words(N) * ns);
+  L.parent = o;  o = align16(o + (record ? 4u * N * ns : 0u));
   L.stats = o;   o = align16(o + 8u * kNumStats);
   L.total = o;
   return L;

@@ -33,6 +33,10 @@ struct Words4 {
 
 __device__ __forceinline__ Words4 philox4x32_10(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3,
                                                 uint32_t key0, uint32_t key1) {
+  // The round keys are recomputed by scalar adds at every call: opaque to the
+  // optimiser here, so it does not hold all twenty of them in scalar registers
+  // across the sweep loop.
+  asm volatile("" : "+s"(key0), "+s"(key1));
 #pragma unroll
   for (int round = 0; round < 10; ++round) {
     const uint64_t m0 = (uint64_t)0xD2511F53u * x0;
@@ -58,7 +62,8 @@ enum : uint32_t { kStreamMetro = 0, kStreamInit = 1, kStreamIcm = 2, kStreamPt =
 // wavefront helpers (wave64)
 // ----------------------------------------------------------------------------
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
-__device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
+// wave index, known to the compiler as uniform (kept in a scalar register)
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
 // Sum over the 64 lanes of a wave (all lanes active), returned to every lane.
 // DPP: butterfly inside each quad, then half-row and row mirrors give every
@@ -197,6 +202,92 @@ __device__ __forceinline__ int spin_of(uint32_t word, int b) {
   return (int)(int8_t)(uint8_t)(word >> (8 * b));
 }
 
+
+// ----------------------------------------------------------------------------
+// The lattice as bit shifts of a site bitset (bit i of word i / 32 is site i),
+// used to grow clusters a whole frontier at a time.  Term t contributes
+// F[i + shift] to site i wherever its condition holds.  Periodic lattices
+// (index x + L y [+ L^2 z]): per axis of stride sg and coordinate c the +1
+// step (shift sg where c < L-1), its wrap (shift -(L-1) sg where c = L-1), the
+// -1 step (shift -sg where c > 0) and its wrap (shift (L-1) sg where c = 0).
+// Chimera (index 8 (row C + col) + u): u < 4 couples to row +-1, u >= 4 to
+// col +-1, open boundaries; the in-cell K4,4 bonds are applied per byte.
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ int lattice_terms(int topo) {
+  return topo == 0 ? 8 : (topo == 1 ? 12 : 4);
+}
+
+__device__ __forceinline__ int term_shift(int topo, int L, int t) {
+  if (topo == 2) {
+    const int s = (t < 2) ? 8 * L : 8;
+    return (t & 1) ? -s : s;
+  }
+  const int sg = t < 4 ? 1 : (t < 8 ? L : L * L);
+  switch (t & 3) {
+    case 0: return sg;
+    case 1: return -(L - 1) * sg;
+    case 2: return -sg;
+    default: return (L - 1) * sg;
+  }
+}
+
+__device__ __forceinline__ bool term_holds(int topo, int L, int t, int i) {
+  if (topo == 2) {
+    const int cell = i >> 3, u = i & 7, row = cell / L, col = cell - row * L;
+    switch (t) {
+      case 0: return u < 4 && row != L - 1;
+      case 1: return u < 4 && row != 0;
+      case 2: return u >= 4 && col != L - 1;
+      default: return u >= 4 && col != 0;
+    }
+  }
+  const int sg = t < 4 ? 1 : (t < 8 ? L : L * L);
+  const int c = (i / sg) % L;
+  switch (t & 3) {
+    case 0: return c != L - 1;
+    case 1: return c == L - 1;
+    case 2: return c != 0;
+    default: return c == 0;
+  }
+}
+
+// In-cell K4,4 step for four chimera cells (one byte each): a cell's sites
+// u >= 4 are reached when any of its u < 4 is in F, and the other way round.
+__device__ __forceinline__ uint32_t chimera_in_cell(uint32_t f) {
+  uint32_t lo = f & 0x0F0F0F0Fu, hi = (f >> 4) & 0x0F0F0F0Fu;
+  lo |= lo >> 1; lo |= lo >> 2;
+  hi |= hi >> 1; hi |= hi >> 2;
+  return ((lo & 0x01010101u) * 0xF0u) | ((hi & 0x01010101u) * 0x0Fu);
+}
+
+
+// Periodic 8x8x8 lattice, one 32-bit word per lane: word w = 2 z + (y >> 2)
+// holds four x-rows of 8 bits.  x steps rotate within bytes, y steps move
+// bytes and borrow one byte from the other half-plane (lane w ^ 1), z steps
+// are the words two lanes away within the 16-lane row (DPP row rotates wrap
+// at 16 words = 8 planes).  Both directions of every axis are taken, so the
+// result is the full neighbourhood of the frontier.
+__device__ __forceinline__ uint32_t cube8_expand(uint32_t f) {
+  const uint32_t fp = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)f, 0xB1, 0xF, 0xF, false);  // w ^ 1
+  const uint32_t zp = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)f, 0x12E, 0xF, 0xF, false); // row_ror:14
+  const uint32_t zm = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)f, 0x122, 0xF, 0xF, false); // row_ror:2
+  const uint32_t xp = ((f >> 1) & 0x7F7F7F7Fu) | ((f << 7) & 0x80808080u);
+  const uint32_t xm = ((f << 1) & 0xFEFEFEFEu) | ((f >> 7) & 0x01010101u);
+  const uint32_t yp = (f >> 8) | (fp << 24);
+  const uint32_t ym = (f << 8) | (fp >> 24);
+  return xp | xm | yp | ym | zp | zm;
+}
+
+// Bits i..i+31 of a bitset shifted by s (result bit b = F[32 w + b + s]).  F
+// points at word 0 of an array padded with one zero word on each side; the
+// reads are clamped to the padding, which only matters for words where the
+// term's mask is zero.
+__device__ __forceinline__ uint32_t shifted_word(const uint32_t* F, int w, int s, int nw) {
+  int q = w + (s >> 5);
+  q = q < -1 ? -1 : (q > nw - 1 ? nw - 1 : q);
+  return __builtin_amdgcn_alignbit(F[q + 1], F[q], (uint32_t)(s & 31));
+}
+
 // ----------------------------------------------------------------------------
 // The fused sweep-block kernel.  JK: 0 = int8 couplings, 1 = float couplings.
 // DEG: neighbour slots (4 for square2d, 6 otherwise).  One workgroup runs one
@@ -269,6 +360,28 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
   for (int x = tid; x < K * R; x += nthr) at[x] = U.at[x];
   for (int x = tid; x < K; x += nthr) { beta[x] = U.beta[x]; bl2e[x] = U.bl2e[x]; }
   for (int x = tid; x < kNumStats; x += nthr) stats[x] = 0;
+  if (Kc > 0) {
+    // shift program of the lattice and zeroed frontier padding of every slot
+    const int nw = site_words(N), nterm = lattice_terms(U.topo);
+    int* tshift = (int*)(lds + lay.terms);
+    uint32_t* tmask = (uint32_t*)(lds + lay.terms) + kMaxTerms;
+    for (int x = tid; x < nterm; x += nthr) tshift[x] = term_shift(U.topo, U.L, x);
+    for (int x = tid; x < nterm * nw; x += nthr) {
+      const int t = x / nw, w = x - t * nw;
+      uint32_t bits = 0;
+      for (int b = 0; b < 32; ++b) {
+        const int i = 32 * w + b;
+        if (i < N && term_holds(U.topo, U.L, t, i)) bits |= 1u << b;
+      }
+      tmask[x] = bits;
+    }
+    const int ns = slots_reserved(N, icm_slots), sw = slot_words(N);
+    uint32_t* sl0 = (uint32_t*)(lds + lay.slots);
+    for (int x = tid; x < ns; x += nthr) {
+      uint32_t* f = sl0 + x * sw;
+      f[0] = 0; f[nw + 1] = 0; f[nw + 2] = 0; f[2 * nw + 3] = 0;
+    }
+  }
   __syncthreads();
 
   const uint32_t t0 = *U.sweep;
@@ -394,116 +507,151 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
     }
 
     // ---------------- steps 2a + 2b: isoenergetic cluster moves ----------------
-    // icm_slots moves are in flight per workgroup: each ICM wave sets up P moves
-    // one after the other with the full wave (mask, 2a, seed), then grows their
-    // clusters concurrently in P lane groups of 64/P lanes, then updates energies
-    // and flips.  Site i is owned by lane i % 64 as bit i / 64 of its mask word,
-    // so ascending site order is (bit, lane) order and ballot s is mask words 2s,
-    // 2s+1.
+    // A move's sites are a bitset of nw words.  Each ICM wave carries P moves
+    // in lane groups of lpm lanes (lane li of a group owns words li, li + lpm).
+    // Set-up, one move at a time with the full wave: ballots over 64 sites
+    // give the q-mask words (replicas differ) and replica a's spin words,
+    // then 2a, the seed (idx-th q = -1 site in ascending order, found from a
+    // prefix of word popcounts).  Growth: every level expands the frontier of
+    // all P clusters at once through the lattice's shift program, restricted
+    // to q-mask sites not yet in the cluster, until no group's frontier is
+    // left.  Then each lane walks its cluster sites: bonds to q = +1
+    // neighbours change sign in replica a (every q = -1 neighbour of the
+    // cluster is in it), and the site flips in both replicas.
     if (Kc > 0) {
       const int half = R >> 1;
       const int nmoves = Kc * half;
-      const int P = icm_slots >= 4 * nwaves ? 4 : (icm_slots >= 2 * nwaves ? 2 : 1);
-      const int iwaves = (icm_slots / P) < nwaves ? (icm_slots / P) : nwaves;
+      const int nw = site_words(N);
+      const int lpm = icm_lanes_per_move(N), P = 64 / lpm;
+      const int iwaves = (icm_slots / P) < 1 ? 1 : ((icm_slots / P) < nwaves ? (icm_slots / P) : nwaves);
+      const int sw = slot_words(N);
+      const int nterm = lattice_terms(U.topo);
+      const int* tshift = (const int*)(lds + lay.terms);
+      const uint32_t* tmask = (const uint32_t*)(lds + lay.terms) + kMaxTerms;
+      const bool chim = U.topo == 2;
+      const bool cube8 = U.topo == 1 && U.L == 8;  // lpm = 16: one word per lane
+      const bool record = (flags & kFlagRecord) && s + 1 == n_sweeps;
       if (wave < iwaves) {
-        const int spl = (N + 63) >> 6;  // mask bits per lane
-        const int nvis = (N + 31) >> 5;
-        const int lpm = 64 / P;         // lanes per move in the BFS
         const int grp = lane / lpm, li = lane - grp * lpm;
-        const int nown = N > lane ? (N - lane + 63) >> 6 : 0;  // sites owned by this lane
-        const unsigned long long own_mask = nown >= 64 ? ~0ull : ((1ull << nown) - 1ull);
-        const unsigned long long gmask = lpm == 64 ? ~0ull : ((1ull << lpm) - 1ull);
-        const unsigned long long lt_in_grp = (li == 0) ? 0ull : (((1ull << li) - 1ull) << (grp * lpm));
+        uint32_t* gsl = (uint32_t*)(lds + lay.slots) + (wave * P + grp) * sw;  // my group's slot
+        uint32_t* gmc = gsl + 2 * (nw + 2);
+        const uint32_t* gaw = gmc + 2 * nw;
+        const int* ginfo = (const int*)(gaw + nw);
         for (int mbase = wave * P; mbase < nmoves; mbase += iwaves * P) {
           // ---- set-up, one move at a time with the full wave ----
-          int mv_g[4], a_g[4], b_g[4], n_g[4];
-#pragma unroll
-          for (int g = 0; g < 4; ++g) {
-            mv_g[g] = -1; a_g[g] = 0; b_g[g] = 0; n_g[g] = 0;
-            if (g >= P || mbase + g >= nmoves) continue;
+#pragma unroll 1
+          for (int g = 0; g < P; ++g) {
             const int mv = mbase + g, slot = wave * P + g;
-            uint16_t* queue = (uint16_t*)(lds + lay.queue) + slot * N;
-            uint32_t* visited = (uint32_t*)(lds + lay.visited) + slot * nvis;
-            uint32_t* mask32 = (uint32_t*)(lds + lay.mask) + slot * nvis;
-            int* parent = (int*)(lds + lay.parent) + slot * N;
+            uint32_t* sl = (uint32_t*)(lds + lay.slots) + slot * sw;
+            uint32_t* f0 = sl + 1;
+            uint32_t* mc = sl + 2 * (nw + 2);
+            uint32_t* aw = mc + 2 * nw;
+            int* info = (int*)(aw + nw);
+            if (mv >= nmoves) {  // no move in this slot: empty cluster
+              for (int w = lane; w < nw; w += 64) { f0[w] = 0; mc[2 * w + 1] = 0; }
+              if (lane == 0) { info[kInMv] = -1; info[kInN] = 0; }
+              continue;
+            }
             const int k = mv / half, p = mv - k * half;
             const int a = at[k * R + 2 * p], b = at[k * R + 2 * p + 1];
             const uint32_t* rowa = sp + (a >> 5) * N;
             const uint32_t* rowb = sp + (b >> 5) * N;
             const int pa = a & 31, pb = b & 31;
             const uint32_t gx = (uint32_t)(gauge[a] ^ gauge[b]);
-            // site overlap q_i = -1  <=>  the two replicas differ at i
-            unsigned long long m = 0;
-            for (int s2 = 0; s2 < nown; ++s2) {
+            // q_i = -1 <=> the replicas differ at i; 64 sites per ballot
+            int n = 0;
+            for (int s2 = 0; s2 * 64 < N; ++s2) {
               const int i = s2 * 64 + lane;
-              const uint32_t diff = bit_of(rowa[i], pa) ^ bit_of(rowb[i], pb) ^ gx;
-              m |= (unsigned long long)diff << s2;
+              uint32_t qb = 0, ab = 0;
+              if (i < N) {
+                ab = bit_of(rowa[i], pa);
+                qb = ab ^ bit_of(rowb[i], pb) ^ gx;
+              }
+              const unsigned long long bq = __ballot(qb), ba = __ballot(ab);
+              n += __popcll(bq);
+              if (lane == 0) {
+                mc[4 * s2] = (uint32_t)bq;
+                aw[2 * s2] = (uint32_t)ba;
+                if (2 * s2 + 1 < nw) {
+                  mc[4 * s2 + 2] = (uint32_t)(bq >> 32);
+                  aw[2 * s2 + 1] = (uint32_t)(ba >> 32);
+                }
+              }
             }
-            int n = wave_sum((int)__popcll(m));
+            n = uniform(n);
             const bool twoa = (flags & kFlag2a) && 2 * n > N;
-            if (twoa) {  // step 2a: reverse the second replica
-              m = ~m & own_mask;
-              n = N - n;
-              if (lane == 0) gauge[b] ^= 1;
+            wave_sync();
+            // step 2a: reverse the second replica (the q-mask complements);
+            // the cluster and frontier start empty
+            for (int w = lane; w < nw; w += 64) {
+              if (twoa) {
+                const int rem_bits = N - 32 * w;
+                const uint32_t valid = rem_bits >= 32 ? ~0u : ((1u << rem_bits) - 1u);
+                mc[2 * w] = ~mc[2 * w] & valid;
+              }
+              mc[2 * w + 1] = 0;
+              f0[w] = 0;
             }
+            if (twoa) n = N - n;
+            wave_sync();
             int seedsite = -1;
             if (n > 0) {
-              // step 2b: the idx-th q = -1 site in ascending order seeds the cluster;
-              // visited starts as the complement of the mask
+              // step 2b: the idx-th q = -1 site in ascending order seeds the cluster
               int rem = (int)(((unsigned long long)icmu[mv] * (unsigned long long)n) >> 32);
-              for (int s2 = 0; s2 < spl; ++s2) {
-                unsigned long long bal = __ballot((m >> s2) & 1ull);
-                if (lane == 0) {
-                  mask32[2 * s2] = (uint32_t)bal;
-                  visited[2 * s2] = ~(uint32_t)bal;
-                  if (2 * s2 + 1 < nvis) {
-                    mask32[2 * s2 + 1] = (uint32_t)(bal >> 32);
-                    visited[2 * s2 + 1] = ~(uint32_t)(bal >> 32);
+              for (int w0 = 0; w0 < nw; w0 += 64) {
+                const int w = w0 + lane;
+                const uint32_t word = w < nw ? mc[2 * w] : 0u;
+                const int c = __popc(word);
+                const int excl = wave_exclusive_scan(c);
+                const int tot = __builtin_amdgcn_readlane(excl + c, 63);
+                if (rem < tot) {
+                  if (rem >= excl && rem < excl + c) {
+                    uint32_t x = word;
+                    for (int r2 = rem - excl; r2 > 0; --r2) x &= x - 1u;
+                    const int pos = __builtin_ctz(x);
+                    f0[w] = 1u << pos;
+                    mc[2 * w + 1] = 1u << pos;
+                    info[kInSeed] = 32 * w + pos;
                   }
+                  break;
                 }
-                const int c2 = __popcll(bal);
-                if (rem >= 0 && rem < c2) {
-                  for (; rem > 0; --rem) bal &= bal - 1ull;
-                  seedsite = s2 * 64 + (int)__builtin_ctzll(bal);
-                  rem = -1;
-                } else if (rem >= 0) {
-                  rem -= c2;
-                }
+                rem -= tot;
               }
-              seedsite = uniform(seedsite);
               wave_sync();
-              if (lane == 0) {
-                visited[seedsite >> 5] |= 1u << (seedsite & 31);
-                queue[0] = (uint16_t)seedsite;
-              }
-              if ((flags & kFlagRecord) && s + 1 == n_sweeps) {
-                // full labelling for the readout: union-find over the q = -1
-                // subgraph, roots hooked towards the smaller index, path compression
-                for (int s2 = 0; s2 < nown; ++s2)
-                  if ((m >> s2) & 1ull) parent[s2 * 64 + lane] = s2 * 64 + lane;
-                wave_sync();
-                for (unsigned long long mm = m; mm; mm &= mm - 1ull) {
-                  const int i = (int)__builtin_ctzll(mm) * 64 + lane;
-#pragma unroll
-                  for (int d = 0; d < DEG; ++d) {
-                    const int jn = nbr[i * DEG + d];
-                    if (jn > i && ((mask32[jn >> 5] >> (jn & 31)) & 1u)) uf_union(parent, i, jn);
-                  }
-                }
-                wave_sync();
-                for (unsigned long long mm = m; mm; mm &= mm - 1ull) {
-                  const int i = (int)__builtin_ctzll(mm) * 64 + lane;
-                  const int r0 = uf_find(parent, i);
-                  __hip_atomic_store(&parent[i], r0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-                }
-              }
+              seedsite = uniform(info[kInSeed]);
             }
-            if ((flags & kFlagRecord) && s + 1 == n_sweeps) {
-              wave_sync();
+            if (record) {
+              // full labelling for the readout: union-find over the q = -1
+              // subgraph, roots hooked towards the smaller index, path compression
+              int* parent = (int*)(lds + lay.parent) + slot * N;
               int* lab = U.labels + (size_t)mv * N;
+              const int nown = N > lane ? (N - lane + 63) >> 6 : 0;
+              auto inmask = [&](int j) { return (mc[2 * (j >> 5)] >> (j & 31)) & 1u; };
               for (int s2 = 0; s2 < nown; ++s2) {
                 const int i = s2 * 64 + lane;
-                lab[i] = (n > 0 && ((m >> s2) & 1ull)) ? uf_load(parent, i) : -1;
+                if (inmask(i)) parent[i] = i;
+              }
+              wave_sync();
+              for (int s2 = 0; s2 < nown; ++s2) {
+                const int i = s2 * 64 + lane;
+                if (!inmask(i)) continue;
+#pragma unroll
+                for (int d = 0; d < DEG; ++d) {
+                  const int jn = nbr[i * DEG + d];
+                  if (jn > i && inmask(jn)) uf_union(parent, i, jn);
+                }
+              }
+              wave_sync();
+              for (int s2 = 0; s2 < nown; ++s2) {
+                const int i = s2 * 64 + lane;
+                if (inmask(i))
+                  __hip_atomic_store(&parent[i], uf_find(parent, i), __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_WAVEFRONT);
+              }
+              wave_sync();
+              for (int s2 = 0; s2 < nown; ++s2) {
+                const int i = s2 * 64 + lane;
+                lab[i] = inmask(i) ? uf_load(parent, i) : -1;
               }
               if (lane == 0) {
                 U.seeds[mv] = seedsite;
@@ -511,112 +659,120 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
               }
             }
             if (lane == 0) {
+              if (twoa) gauge[b] ^= 1;
+              info[kInMv] = mv;
+              info[kInA] = a;
+              info[kInB] = b;
+              info[kInN] = n;
               atomicAdd(&stats[kStatIcmMoves], 1ull);
               if (twoa) atomicAdd(&stats[kStat2a], 1ull);
               if (n > 0) atomicAdd(&stats[kStatIcmNontrivial], 1ull);
             }
-            mv_g[g] = mv; a_g[g] = a; b_g[g] = b; n_g[g] = n;
           }
           wave_sync();
-          // ---- the P clusters grow concurrently, one lane group each ----
-          const int my_mv = grp == 0 ? mv_g[0] : grp == 1 ? mv_g[1] : grp == 2 ? mv_g[2] : mv_g[3];
-          const int my_n = grp == 0 ? n_g[0] : grp == 1 ? n_g[1] : grp == 2 ? n_g[2] : n_g[3];
-          const int my_a = grp == 0 ? a_g[0] : grp == 1 ? a_g[1] : grp == 2 ? a_g[2] : a_g[3];
-          const int my_b = grp == 0 ? b_g[0] : grp == 1 ? b_g[1] : grp == 2 ? b_g[2] : b_g[3];
-          const int slot = wave * P + grp;
-          uint16_t* queue = (uint16_t*)(lds + lay.queue) + slot * N;
-          uint32_t* visited = (uint32_t*)(lds + lay.visited) + slot * nvis;
-          const uint32_t* mask32 = (const uint32_t*)(lds + lay.mask) + slot * nvis;
-          int head = 0, tail = (my_mv >= 0 && my_n > 0) ? 1 : 0;
-          while (__ballot(head < tail)) {
-            const int cnt = (tail - head) < lpm ? (tail - head) : lpm;
-            const bool act = li < cnt;
-            int jn[DEG];
-            bool claim[DEG];
-            if (act) {
-              const int i = queue[head + li];
-#pragma unroll
-              for (int d = 0; d < DEG; ++d) jn[d] = nbr[i * DEG + d];
-#pragma unroll
-              for (int d = 0; d < DEG; ++d) {
-                const uint32_t bitm = 1u << (jn[d] & 31);
-                claim[d] = !(atomicOr(&visited[jn[d] >> 5], bitm) & bitm);
-              }
-            } else {
-#pragma unroll
-              for (int d = 0; d < DEG; ++d) { jn[d] = 0; claim[d] = false; }
+          // ---- the P clusters grow together, a whole frontier per level ----
+          if (cube8) {
+            // one word per lane, frontier, mask and cluster kept in registers
+            const uint32_t m = gmc[2 * li];
+            uint32_t c = gmc[2 * li + 1];
+            uint32_t f = c;  // the seed, or nothing
+            while (true) {
+              const uint32_t fn = cube8_expand(f) & m & ~c;
+              c |= fn;
+              f = fn;
+              if (!__ballot(fn != 0u)) break;
             }
-            head += cnt > 0 ? cnt : 0;
-#pragma unroll
-            for (int d = 0; d < DEG; ++d) {
-              const unsigned long long bal = __ballot(claim[d]);
-              const unsigned long long gb = (bal >> (grp * lpm)) & gmask;
-              const int pos = tail + __popcll(bal & lt_in_grp);
-              if (claim[d]) queue[pos] = (uint16_t)jn[d];
-              tail += __popcll(gb);
-            }
+            gmc[2 * li + 1] = c;
             wave_sync();
           }
-          // ---- bonds leaving the cluster change sign in replica a (every q = -1
-          // neighbour of the cluster is in it, so they are the bonds to q = +1
-          // sites); then the cluster flips in both replicas ----
-          E_t dEa = 0;
-          if (my_mv >= 0) {
-            uint32_t* rowa = sp + (my_a >> 5) * N;
-            uint32_t* rowb = sp + (my_b >> 5) * N;
-            const int pa = my_a & 31, pb = my_b & 31;
-            for (int x = li; x < tail; x += lpm) {
-              const int i = queue[x];
-              const uint32_t bi = bit_of(rowa[i], pa);
-#pragma unroll
-              for (int d = 0; d < DEG; ++d) {
-                const int j2 = nbr[i * DEG + d];
-                if (!((mask32[j2 >> 5] >> (j2 & 31)) & 1u)) {
-                  const int sgn = (bi ^ bit_of(rowa[j2], pa)) ? -1 : 1;  // s_a,i s_a,j
-                  if (JK) dEa += (E_t)((double)cf[i * DEG + d] * (double)sgn);
-                  else dEa += (E_t)(cj[i * DEG + d] * sgn);
-                }
+          int cur = 0;
+          while (!cube8) {
+            const uint32_t* fc = gsl + 1 + cur * (nw + 2);
+            uint32_t* fnx = gsl + 1 + (cur ^ 1) * (nw + 2);
+            bool grew = false;
+            for (int w = li; w < nw; w += lpm) {
+              uint32_t gw = chim ? chimera_in_cell(fc[w]) : 0u;
+              for (int t = 0; t < nterm; ++t)
+                gw |= shifted_word(fc, w, tshift[t], nw) & tmask[t * nw + w];
+              const uint32_t m = gmc[2 * w], c = gmc[2 * w + 1];
+              const uint32_t fn = gw & m & ~c;
+              fnx[w] = fn;
+              if (fn) {
+                gmc[2 * w + 1] = c | fn;
+                grew = true;
               }
-              if (rowa == rowb) {
-                atomicXor(&rowa[i], (1u << pa) | (1u << pb));
-              } else {
-                atomicXor(&rowa[i], 1u << pa);
-                atomicXor(&rowb[i], 1u << pb);
+            }
+            wave_sync();
+            cur ^= 1;
+            if (!__ballot(grew)) break;
+          }
+          // ---- bonds leaving the cluster, then the flips ----
+          E_t dEa = 0;
+          int csize = 0;
+          {
+            const int ga = ginfo[kInA], gb = ginfo[kInB];
+            uint32_t* rowa = sp + (ga >> 5) * N;
+            uint32_t* rowb = sp + (gb >> 5) * N;
+            const uint32_t fa = 1u << (ga & 31), fb = 1u << (gb & 31);
+            for (int w = li; w < nw; w += lpm) {
+              uint32_t cw = gmc[2 * w + 1];
+              const uint32_t awd = gaw[w];
+              csize += __popc(cw);
+              while (cw) {
+                const int bpos = __builtin_ctz(cw);
+                cw &= cw - 1u;
+                const int i = 32 * w + bpos;
+                const uint32_t ai = (awd >> bpos) & 1u;
+#pragma unroll
+                for (int d = 0; d < DEG; ++d) {
+                  const int j = nbr[i * DEG + d];
+                  if (!((gmc[2 * (j >> 5)] >> (j & 31)) & 1u)) {
+                    const bool anti = (ai ^ (gaw[j >> 5] >> (j & 31))) & 1u;  // s_a,i s_a,j = -1
+                    if (JK) {
+                      const double J = (double)cf[i * DEG + d];
+                      dEa += anti ? -J : J;
+                    } else {
+                      const int J = cj[i * DEG + d];
+                      dEa += anti ? -J : J;
+                    }
+                  }
+                }
+                if (rowa == rowb) {
+                  atomicXor(&rowa[i], fa | fb);
+                } else {
+                  atomicXor(&rowa[i], fa);
+                  atomicXor(&rowb[i], fb);
+                }
               }
             }
           }
           // per-group sums: DPP row sums are 16-lane sums, groups are 1, 2 or 4 rows
-          E_t rows[4];
           {
-            E_t v = dEa;
+            E_t rows[4];
             if (JK) {
-              double dv = (double)v;
+              double dv = (double)dEa;
               dv += dpp_d<0xB1>(dv); dv += dpp_d<0x4E>(dv); dv += dpp_d<0x141>(dv); dv += dpp_d<0x140>(dv);
 #pragma unroll
               for (int r2 = 0; r2 < 4; ++r2) rows[r2] = (E_t)readlane_d(dv, 16 * r2);
             } else {
-              int iv = (int)v;
-              iv = dpp_row_sum(iv);
+              int iv = dpp_row_sum((int)dEa);
 #pragma unroll
               for (int r2 = 0; r2 < 4; ++r2) rows[r2] = (E_t)__builtin_amdgcn_readlane(iv, 16 * r2);
             }
-          }
-          if (lane == 0) {
-#pragma unroll
-            for (int g = 0; g < 4; ++g) {
-              if (g >= P || mv_g[g] < 0 || n_g[g] == 0) continue;
-              E_t sum = 0;
-              for (int r2 = g * (4 / P); r2 < (g + 1) * (4 / P); ++r2) sum += rows[r2];
-              energy[a_g[g]] += (E_t)2 * sum;
-              energy[b_g[g]] -= (E_t)2 * sum;
+            const int sites = wave_sum(csize);
+            if (lane == 0) {
+              const int rpg = 4 / P;  // DPP rows per group
+              for (int g = 0; g < P; ++g) {
+                const int* inf = (const int*)((uint32_t*)(lds + lay.slots) + (wave * P + g) * sw +
+                                              2 * (nw + 2) + 3 * nw);
+                if (inf[kInMv] < 0 || inf[kInN] == 0) continue;
+                E_t sum = 0;
+                for (int r2 = g * rpg; r2 < (g + 1) * rpg; ++r2) sum += rows[r2];
+                energy[inf[kInA]] += (E_t)2 * sum;
+                energy[inf[kInB]] -= (E_t)2 * sum;
+              }
+              if (sites) atomicAdd(&stats[kStatIcmSites], (unsigned long long)sites);
             }
-          }
-#pragma unroll
-          for (int g = 0; g < 4; ++g) {
-            if (g >= P) continue;
-            const int tg = __builtin_amdgcn_readlane(tail, g * lpm);
-            if (lane == 0 && mv_g[g] >= 0 && n_g[g] > 0)
-              atomicAdd(&stats[kStatIcmSites], (unsigned long long)tg);
           }
           wave_sync();
         }

@@ -566,6 +566,8 @@ int add_instance_impl(icm_ctx* c, const icm_instance_desc* d, int32_t* out) {
   U.jkind = in->jkind;
   U.jscale = in->jscale;
   U.flags = in->flags;
+  U.topo = T->topo;
+  U.L = T->L;
   U.seed = c->seed;
   U.key = in->key;
 
