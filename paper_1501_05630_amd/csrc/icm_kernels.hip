@@ -278,6 +278,19 @@ __device__ __forceinline__ uint32_t cube8_expand(uint32_t f) {
   return xp | xm | yp | ym | zp | zm;
 }
 
+
+// The six neighbour words of the 8^3 layout above, in neighbour-table order
+// (+x, -x, +y, -y, +z, -z): out[d] bit b = F at the d-neighbour of site 32 w + b.
+__device__ __forceinline__ void cube8_dirs(uint32_t f, uint32_t out[6]) {
+  const uint32_t fp = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)f, 0xB1, 0xF, 0xF, false);
+  out[0] = ((f >> 1) & 0x7F7F7F7Fu) | ((f << 7) & 0x80808080u);
+  out[1] = ((f << 1) & 0xFEFEFEFEu) | ((f >> 7) & 0x01010101u);
+  out[2] = (f >> 8) | (fp << 24);
+  out[3] = (f << 8) | (fp >> 24);
+  out[4] = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)f, 0x12E, 0xF, 0xF, false);  // word w + 2
+  out[5] = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)f, 0x122, 0xF, 0xF, false);  // word w - 2
+}
+
 // Bits i..i+31 of a bitset shifted by s (result bit b = F[32 w + b + s]).  F
 // points at word 0 of an array padded with one zero word on each side; the
 // reads are clamped to the padding, which only matters for words where the
@@ -714,7 +727,43 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
             uint32_t* rowa = sp + (ga >> 5) * N;
             uint32_t* rowb = sp + (gb >> 5) * N;
             const uint32_t fa = 1u << (ga & 31), fb = 1u << (gb & 31);
-            for (int w = li; w < nw; w += lpm) {
+            if (cube8) {
+              // boundary bonds per direction d: i in the cluster, its d-neighbour
+              // not (then outside the q-mask); anti-aligned in replica a where
+              // the spin words differ
+              const uint32_t cw = gmc[2 * li + 1], awd = gaw[li];
+              uint32_t cd[6], ad[6];
+              cube8_dirs(cw, cd);
+              cube8_dirs(awd, ad);
+              csize = __popc(cw);
+#pragma unroll
+              for (int d = 0; d < 6; ++d) {
+                uint32_t bb = cw & ~cd[d];
+                const uint32_t anti = awd ^ ad[d];
+                while (bb) {
+                  const int bpos = __builtin_ctz(bb);
+                  bb &= bb - 1u;
+                  const int x = (32 * li + bpos) * DEG + d;
+                  if (JK) {
+                    const double J = (double)cf[x];
+                    dEa += ((anti >> bpos) & 1u) ? -J : J;
+                  } else {
+                    const int J = cj[x];
+                    dEa += ((anti >> bpos) & 1u) ? -J : J;
+                  }
+                }
+              }
+              for (uint32_t fl = cw; fl; fl &= fl - 1u) {
+                const int i = 32 * li + __builtin_ctz(fl);
+                if (rowa == rowb) {
+                  atomicXor(&rowa[i], fa | fb);
+                } else {
+                  atomicXor(&rowa[i], fa);
+                  atomicXor(&rowb[i], fb);
+                }
+              }
+            }
+            for (int w = li; w < nw && !cube8; w += lpm) {
               uint32_t cw = gmc[2 * w + 1];
               const uint32_t awd = gaw[w];
               csize += __popc(cw);
