@@ -31,8 +31,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="3d_L8_gauss_1024inst")
     ap.add_argument("--sweeps-per-step", type=int, default=256)
-    ap.add_argument("--threads", type=int, default=512)
-    ap.add_argument("--icm-slots", type=int, default=32)
+    ap.add_argument("--threads", type=int, default=256)
+    ap.add_argument("--icm-slots", type=int, default=16)
     ap.add_argument("--graph", type=int, default=1)
     ap.add_argument("--per-instance-sample", type=int, default=32)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -262,7 +262,7 @@ def main():
     achieved_gbs = bytes_per_launch / (launch_ms / 1e3) / 1e9
     tr = TRAFFIC.get(name, {})
     traffic = tr.get("bytes_per_launch") if (tr.get("kernel") == kernel_source_digest()
-                                              and spsw == 256 and args.threads == 512) else None
+                                              and spsw == 256 and args.threads == 256 and args.icm_slots == 16) else None
 
     out = {
         "metric": "spin-flip attempts/s + ICM moves/s, batched vs per-instance; % HBM roofline",

@@ -12,7 +12,7 @@ import os
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "icm_autotune.json")
 THREADS = (256, 512, 1024)
-SLOTS = (2, 4, 8, 16)
+SLOTS = (4, 8, 16, 32)
 SWEEPS = (64, 256)
 
 
@@ -55,7 +55,7 @@ def tune(ctx, handles, cache_path=DEFAULT_CACHE, budget_sweeps=None, verbose=Fal
         return best
     results = []
     for threads, slots, spl in itertools.product(THREADS, SLOTS, SWEEPS):
-        if slots > threads // 64:
+        if slots > 4 * (threads // 64):  # at most four moves per wave
             continue
         cfg = dict(threads=threads, icm_slots=slots, sweeps_per_launch=spl, use_graph=1)
         ctx.icm_set_run_config(**cfg)

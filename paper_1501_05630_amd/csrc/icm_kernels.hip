@@ -550,11 +550,13 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
         uint32_t* gmc = gsl + 2 * (nw + 2);
         const uint32_t* gaw = gmc + 2 * nw;
         const int* ginfo = (const int*)(gaw + nw);
-        for (int mbase = wave * P; mbase < nmoves; mbase += iwaves * P) {
+        // moves are dealt round-robin over the ICM waves, so every wave gets a
+        // mix of cold (small clusters) and warm temperatures
+        for (int mbase = wave; mbase < nmoves; mbase += iwaves * P) {
           // ---- set-up, one move at a time with the full wave ----
 #pragma unroll 1
           for (int g = 0; g < P; ++g) {
-            const int mv = mbase + g, slot = wave * P + g;
+            const int mv = mbase + g * iwaves, slot = wave * P + g;
             uint32_t* sl = (uint32_t*)(lds + lay.slots) + slot * sw;
             uint32_t* f0 = sl + 1;
             uint32_t* mc = sl + 2 * (nw + 2);
