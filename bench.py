@@ -89,33 +89,37 @@ def cpu_baseline(name, spec, seconds):
 
     cores = os.cpu_count() or 1
     cores = min(cores, 16)
-    N = inputs.n_sites(spec["topology"], spec["L"])
     S = spec["n_temps"] * spec["n_replicas"]
-    # calibrate: sweeps per instance so that the sample takes ~`seconds`
-    J, temps, kc, _ = inputs.workload_instance(name, 0)
-    o = oracle.Sim(spec["topology"], spec["L"], J, temps, spec["n_replicas"], kc,
-                   seed=inputs.MASTER_SEED, instance_key=0, j_scale=spec["j_scale"])
-    o.init_hot()
+    n_inst = cores
+    # sampled instances spread evenly over the batch (every size class of an
+    # uneven batch is represented)
+    picks = [b * spec["n_instances"] // n_inst for b in range(n_inst)]
+
+    def sim(b):
+        J, temps, kc, sp = inputs.workload_instance(name, b)
+        o = oracle.Sim(sp["topology"], sp["L"], J, temps, spec["n_replicas"], kc,
+                       seed=inputs.MASTER_SEED, instance_key=b, j_scale=spec["j_scale"])
+        o.init_hot()
+        return o, inputs.n_sites(sp["topology"], sp["L"])
+
+    # calibrate on the largest sampled instance: sweeps so that the sample takes ~`seconds`
+    o, _ = sim(picks[-1])
     t0 = time.perf_counter()
     o.run(4)
     per_sweep = (time.perf_counter() - t0) / 4
-    n_inst = cores
     sweeps = max(4, int(seconds / max(per_sweep, 1e-9)))
 
     def job(b):
-        J, temps, kc, _ = inputs.workload_instance(name, b)
-        s = oracle.Sim(spec["topology"], spec["L"], J, temps, spec["n_replicas"], kc,
-                       seed=inputs.MASTER_SEED, instance_key=b, j_scale=spec["j_scale"])
-        s.init_hot()
-        s.run(sweeps)
-        return s.stats()["icm_moves"]
+        o, N = sim(b)
+        o.run(sweeps)
+        return o.stats()["icm_moves"], S * N * sweeps
 
     t0 = time.perf_counter()
     with cf.ThreadPoolExecutor(max_workers=cores) as ex:
-        moves = sum(ex.map(job, range(n_inst)))
+        res = list(ex.map(job, picks))
     dt = time.perf_counter() - t0
-    return {"value": S * N * sweeps * n_inst / dt, "unit": "spin-flip attempts/s", "cores": cores,
-            "kind": "oracle", "icm_moves_per_s": moves / dt,
+    return {"value": sum(r[1] for r in res) / dt, "unit": "spin-flip attempts/s", "cores": cores,
+            "kind": "oracle", "icm_moves_per_s": sum(r[0] for r in res) / dt,
             "sample": f"{n_inst} instances x {sweeps} sweeps of {name}, one oracle per thread"}
 
 
@@ -219,20 +223,19 @@ def main():
     name = args.workload
     spec = inputs.WORKLOADS[name]
     n_inst = spec["n_instances"]
-    N = inputs.n_sites(spec["topology"], spec["L"])
     S = spec["n_temps"] * spec["n_replicas"]
-    ctx = icm.Context(arena_bytes=2 << 30, seed=inputs.MASTER_SEED)
-    hs = []
-    n_bonds = None
+    ctx = icm.Context(arena_bytes=4 << 30, seed=inputs.MASTER_SEED)
+    hs, sizes, moves_per_sweep, bonds = [], [], [], []
     for b in range(n_inst):
-        J, temps, kc, _ = inputs.workload_instance(name, b)
-        hs.append(ctx.icm_add_instance(spec["topology"], spec["L"], J, temps, spec["n_replicas"], kc,
+        J, temps, kc, sp = inputs.workload_instance(name, b)
+        hs.append(ctx.icm_add_instance(sp["topology"], sp["L"], J, temps, spec["n_replicas"], kc,
                                        instance_key=b, j_scale=spec["j_scale"]))
         ctx.icm_init_states(hs[-1])
-        if n_bonds is None:
-            n_bonds = {inputs.SQUARE2D: 2 * N, inputs.CUBIC3D: 3 * N,
-                       inputs.CHIMERA: 16 * spec["L"] ** 2 + 8 * spec["L"] * (spec["L"] - 1)}[spec["topology"]]
-            n_moves_per_sweep = kc * spec["n_replicas"] // 2
+        N = inputs.n_sites(sp["topology"], sp["L"])
+        sizes.append(N)
+        moves_per_sweep.append(kc * spec["n_replicas"] // 2)
+        bonds.append({inputs.SQUARE2D: 2 * N, inputs.CUBIC3D: 3 * N,
+                      inputs.CHIMERA: 16 * sp["L"] ** 2 + 8 * sp["L"] * (sp["L"] - 1)}[sp["topology"]])
     jbytes = 4 if spec["kind"] == "gauss" else 1
     spsw = args.sweeps_per_step
     ctx.icm_set_run_config(threads=args.threads, sweeps_per_launch=spsw, use_graph=args.graph,
@@ -249,43 +252,50 @@ def main():
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1)
     sweeps = spsw * args.steps
-    attempts = S * N * sweeps * n_inst
+    attempts_per_sweep = S * sum(sizes)
     secs = ms / 1e3
-    value = attempts / secs
-    icm_moves = n_moves_per_sweep * sweeps * n_inst
-    launch_ms = ms / args.steps  # one launch of the fused kernel per step
+    value = attempts_per_sweep * sweeps / secs
+    icm_moves = sum(moves_per_sweep) * sweeps
+    step_ms = ms / args.steps
     deg = {inputs.SQUARE2D: 4, inputs.CUBIC3D: 6, inputs.CHIMERA: 6}[spec["topology"]]
-    ops_per_launch = (algorithmic_ops_per_attempt(deg, spec["kind"]) * S * N
-                      + algorithmic_ops_per_move(N) * n_moves_per_sweep) * spsw * n_inst
-    achieved_tops = ops_per_launch / (launch_ms / 1e3) / 1e12
-    bytes_per_launch = algorithmic_bytes_per_sweep(spec, N, n_bonds, jbytes) * spsw * n_inst
-    achieved_gbs = bytes_per_launch / (launch_ms / 1e3) / 1e9
+    opa = algorithmic_ops_per_attempt(deg, spec["kind"])
+    ops_per_step = (opa * attempts_per_sweep
+                    + sum(algorithmic_ops_per_move(N) * m for N, m in zip(sizes, moves_per_sweep))) * spsw
+    bytes_per_sweep = sum(2 * S * N + nb * jbytes for N, nb in zip(sizes, bonds))
+    # one launch per size class: the roofline is taken over the whole step
+    achieved_tops = ops_per_step / (step_ms / 1e3) / 1e12
+    achieved_gbs = bytes_per_sweep * spsw / (step_ms / 1e3) / 1e9
     tr = TRAFFIC.get(name, {})
     traffic = tr.get("bytes_per_launch") if (tr.get("kernel") == kernel_source_digest()
                                               and spsw == 256 and args.threads == 256 and args.icm_slots == 16) else None
+    uneven = bool(spec.get("sides"))
 
     out = {
         "metric": "spin-flip attempts/s + ICM moves/s, batched vs per-instance; % HBM roofline",
         "value": value, "unit": "spin-flip attempts/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": launch_ms, "higher_is_better": True,
+        "warmup": args.warmup, "ms_per_step": step_ms, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64" if spec["kind"] == "gauss" else "i32",
         "data": "synthetic (seeded disorder, hot start)",
         "config": {"workload": name, "instances": n_inst, "topology": inputs.TOPOLOGY_NAMES[spec["topology"]],
-                   "L": spec["L"], "N": N, "temps": spec["n_temps"], "replicas": spec["n_replicas"],
-                   "icm_temps": kc, "sweeps_per_step": spsw, "threads": args.threads,
+                   "L": list(spec["sides"]) if uneven else spec["L"],
+                   "N": sorted(set(sizes)) if uneven else sizes[0], "temps": spec["n_temps"],
+                   "replicas": spec["n_replicas"], "icm_temps": moves_per_sweep[0] * 2 // spec["n_replicas"],
+                   "sweeps_per_step": spsw, "threads": args.threads,
                    "icm_slots": args.icm_slots, "graph": bool(args.graph),
                    "parallelism": "single GPU, one workgroup per instance"},
         "icm_moves_per_s": icm_moves / secs,
         "roofline": {"bound": "alu", "achieved": achieved_tops, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
                      "frac": achieved_tops / VALU_PEAK_TOPS, "traffic": traffic,
-                     "ops_per_attempt": algorithmic_ops_per_attempt(deg, spec["kind"]),
-                     "ops_per_icm_move": algorithmic_ops_per_move(N)},
+                     "ops_per_attempt": opa, "ops_per_icm_move": "2 N"},
         "hbm_effective": {"achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                           "frac": achieved_gbs / HBM_PEAK_GBS,
-                          "bytes_per_attempt": algorithmic_bytes_per_sweep(spec, N, n_bonds, jbytes) / (S * N)},
+                          "bytes_per_attempt": bytes_per_sweep / attempts_per_sweep},
     }
     if not args.no_per_instance:
-        sample = hs[: args.per_instance_sample]
+        # plain per-instance launches over a sample spread evenly over the batch
+        k = min(args.per_instance_sample, n_inst)
+        pick = [b * n_inst // k for b in range(k)]
+        sample = [hs[b] for b in pick]
         ctx.icm_set_run_config(use_graph=0)
         ctx.icm_run_per_instance(sample, spsw)
         torch.cuda.synchronize()
@@ -294,9 +304,9 @@ def main():
         ev1.record(stream)
         torch.cuda.synchronize()
         pms = ev0.elapsed_time(ev1)
-        out["per_instance"] = {"value": S * N * spsw * len(sample) / (pms / 1e3),
-                               "icm_moves_per_s": n_moves_per_sweep * spsw * len(sample) / (pms / 1e3),
-                               "sample": f"{len(sample)} instances, one launch each"}
+        out["per_instance"] = {"value": S * sum(sizes[b] for b in pick) * spsw / (pms / 1e3),
+                               "icm_moves_per_s": sum(moves_per_sweep[b] for b in pick) * spsw / (pms / 1e3),
+                               "sample": f"{k} instances, one launch each"}
         out["batched_over_per_instance"] = value / out["per_instance"]["value"]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(name, spec, args.cpu_seconds)

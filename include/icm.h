@@ -117,11 +117,15 @@ typedef struct {
 
 /* Launch configuration of icm_run (0 = library default / autotuned). */
 typedef struct {
-  int32_t threads;          /* threads per workgroup: 256, 512 or 1024 */
+  int32_t threads;          /* threads per workgroup: 256, 512 or 1024, for units of up
+                               to 512 sites; a run launches once per size class (sites
+                               <= 512, <= 1024, <= 2048, more) and larger classes use at
+                               least 512, 1024 and 1024 threads */
   int32_t sweeps_per_launch;/* sweeps fused into one kernel launch */
   int32_t use_graph;        /* 1: replay launches from a captured hipGraph */
-  int32_t icm_slots;        /* ICM moves in flight per workgroup, 1..64 (LDS scratch);
-                               up to 4 per wavefront, in lane groups */
+  int32_t icm_slots;        /* ICM moves in flight per workgroup, 1..64 (LDS scratch):
+                               a wavefront carries 64 / l moves, l = lanes per move
+                               (16, 32 or 64 for units of up to 512, 1024, 4096 sites) */
   int32_t table_placement;  /* 0: automatic, 1: neighbour/coupling tables in LDS,
                                2: tables read from global memory */
 } icm_run_config;

@@ -635,16 +635,29 @@ void drop_cached_tables(icm_ctx* c, int32_t h) {
 
 // Groups of instances that share a kernel instantiation (coupling kind, degree).
 struct Group {
-  int jkind, deg;
+  int jkind, deg, cls;
   std::vector<int32_t> handles;
 };
+
+// Size classes of units (sites): up to 512, 1024, 2048, more.  Units of one
+// class share a launch (its LDS size is the largest member's), and larger
+// classes get more threads per workgroup.
+int size_class(int N) { return N <= 512 ? 0 : (N <= 1024 ? 1 : (N <= 2048 ? 2 : 3)); }
+
+int class_threads(int threads, int cls) {
+  const int floor_t = cls == 0 ? 0 : (cls == 1 ? 512 : 1024);
+  return std::max(threads, floor_t);
+}
 
 std::vector<Group> group_handles(icm_ctx* c, const int32_t* handles, int n) {
   std::vector<Group> g;
   for (int x = 0; x < n; ++x) {
     Instance* in = find(c, handles[x]);
-    auto it = std::find_if(g.begin(), g.end(), [&](const Group& q) { return q.jkind == in->jkind && q.deg == in->deg; });
-    if (it == g.end()) g.push_back({in->jkind, in->deg, {handles[x]}});
+    const int cls = size_class(in->N);
+    auto it = std::find_if(g.begin(), g.end(), [&](const Group& q) {
+      return q.jkind == in->jkind && q.deg == in->deg && q.cls == cls;
+    });
+    if (it == g.end()) g.push_back({in->jkind, in->deg, cls, {handles[x]}});
     else it->handles.push_back(handles[x]);
   }
   return g;
@@ -686,7 +699,7 @@ int unit_table(icm_ctx* c, const std::vector<int32_t>& hs, UnitDesc** out) {
 }
 
 int launch_group(icm_ctx* c, const Group& g, uint32_t n_sweeps, bool per_instance) {
-  const int threads = c->cfg.threads;
+  const int threads = class_threads(c->cfg.threads, g.cls);
   size_t lds = 0;
   int tables = 1;
   const int slots = effective_slots(c, g.handles, threads, c->cfg.icm_slots, lds, tables);

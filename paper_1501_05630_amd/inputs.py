@@ -109,7 +109,19 @@ WORKLOADS = {
     "chimera_C12_int3_512inst": dict(config=2, topology=CHIMERA, L=12, kind="int3", j_scale=3,
                                      n_temps=30, t_min=0.2, t_max=3.0, n_replicas=2,
                                      n_sweeps=1 << 14, n_instances=512),
+    # uneven batch: 256 instances of each side, in this order
+    "3d_uneven_gauss_1536inst": dict(config=3, topology=CUBIC3D, L=None, sides=(4, 6, 8, 10, 12, 16),
+                                     per_side=256, kind="gauss", j_scale=1,
+                                     n_temps=24, t_min=0.2, t_max=2.0, n_replicas=4,
+                                     n_sweeps=1 << 13, n_instances=1536),
 }
+
+
+def instance_side(spec, instance_index):
+    """Side L (or chimera cells per side) of one instance of a workload."""
+    if spec.get("sides"):
+        return spec["sides"][instance_index // spec["per_side"]]
+    return spec["L"]
 
 
 def make_couplings(kind, topology, L, rng):
@@ -125,8 +137,7 @@ def make_couplings(kind, topology, L, rng):
 def workload_instance(name, instance_index, L=None):
     """(couplings, temps, icm_ntemps, spec) for one instance of a named workload."""
     spec = dict(WORKLOADS[name])
-    if L is not None:
-        spec["L"] = L
+    spec["L"] = L if L is not None else instance_side(spec, instance_index)
     rng = make_rng(spec["config"], instance_index)
     J = make_couplings(spec["kind"], spec["topology"], spec["L"], rng)
     temps = geometric_temps(spec["t_min"], spec["t_max"], spec["n_temps"])

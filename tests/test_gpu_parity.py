@@ -253,15 +253,14 @@ def test_gaussian_energy_per_temperature_statistics(ctx):
 
 
 # ---------------------------------------------------------- full-size workloads
-def _full_size(ctx, name, n_inst, sweeps, sample):
-    hs, Js = [], []
+def _full_size(ctx, name, n_inst, sweeps, sample, threads=512):
+    hs = []
     for b in range(n_inst):
         J, temps, kc, spec = inputs.workload_instance(name, b)
         hs.append(ctx.icm_add_instance(spec["topology"], spec["L"], J, temps, spec["n_replicas"], kc,
                                        instance_key=b, j_scale=spec["j_scale"]))
-        Js.append(J)
         ctx.icm_init_states(hs[-1])
-    ctx.icm_set_run_config(threads=512, sweeps_per_launch=sweeps)
+    ctx.icm_set_run_config(threads=threads, sweeps_per_launch=sweeps)
     ctx.icm_run(hs, sweeps)
     ctx.icm_sync()
     for b in sample:
@@ -272,17 +271,15 @@ def _full_size(ctx, name, n_inst, sweeps, sample):
         o.run(sweeps)
         assert_same(ctx, hs[b], o, f"{name} instance {b}")
     # property at any size: every reported energy equals the energy of the state
-    ref = orc.Sim(spec["topology"], spec["L"], Js[0], temps, spec["n_replicas"], kc,
-                  seed=SEED, j_scale=spec["j_scale"])
     for b in range(0, n_inst, max(1, n_inst // 64)):
-        o = orc.Sim(spec["topology"], spec["L"], Js[b], temps, spec["n_replicas"], kc,
+        J, temps, kc, spec = inputs.workload_instance(name, b)
+        o = orc.Sim(spec["topology"], spec["L"], J, temps, spec["n_replicas"], kc,
                     seed=SEED, j_scale=spec["j_scale"])
         st = ctx.icm_read_states(hs[b])
         raw, _ = ctx.icm_read_energies(hs[b])
         for k in range(st.shape[0]):
             for r in range(st.shape[1]):
                 assert raw[k, r] == o.energy_raw(st[k, r]), (b, k, r)
-    del ref
     for h in hs:
         ctx.icm_remove_instance(h)
     ctx.icm_set_run_config(sweeps_per_launch=256)
@@ -294,3 +291,14 @@ def test_full_size_3d_gauss_1024_instances_sampled(ctx):
 
 def test_full_size_chimera_512_instances_sampled(ctx):
     _full_size(ctx, "chimera_C12_int3_512inst", 512, 6, [0, 511])
+
+
+def test_full_size_uneven_3d_batch_sampled():
+    # 256 instances each of L = 4, 6, 8, 10, 12, 16 in one run (one launch per
+    # size class); one instance of every side checked against the oracle.
+    c = icm.Context(arena_bytes=3 << 30, seed=SEED)
+    try:
+        _full_size(c, "3d_uneven_gauss_1536inst", 1536, 4,
+                   [0, 256 + 5, 512 + 77, 768 + 130, 1024 + 201, 1280 + 255], threads=256)
+    finally:
+        c.close()
