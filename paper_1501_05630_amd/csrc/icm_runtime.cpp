@@ -239,6 +239,10 @@ struct icm_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   hipStream_t capture_stream = nullptr;  // private stream for graph capture
+  // extra streams (default priority) that run the launches of different
+  // kernel variants / size classes of one icm_run concurrently
+  hipStream_t side[3] = {nullptr, nullptr, nullptr};
+  std::vector<hipEvent_t> events;
   uint32_t seed = 0;
   Arena arena;
   bool poisoned = false;
@@ -247,6 +251,7 @@ struct icm_ctx {
   std::map<int32_t, std::unique_ptr<Instance>> instances;
   int32_t next_handle = 1;
   size_t lds_limit = 65536;
+  int n_cus = 256;
   icm_run_config cfg{512, 256, 0, 32, 0};
   // unit tables cached per (handle list)
   std::map<std::vector<int32_t>, UnitDesc*> unit_tables;
@@ -698,7 +703,7 @@ int unit_table(icm_ctx* c, const std::vector<int32_t>& hs, UnitDesc** out) {
   return ICM_OK;
 }
 
-int launch_group(icm_ctx* c, const Group& g, uint32_t n_sweeps, bool per_instance) {
+int launch_group(icm_ctx* c, const Group& g, uint32_t n_sweeps, bool per_instance, hipStream_t strm) {
   const int threads = class_threads(c->cfg.threads, g.cls);
   size_t lds = 0;
   int tables = 1;
@@ -714,7 +719,7 @@ int launch_group(icm_ctx* c, const Group& g, uint32_t n_sweeps, bool per_instanc
       if (rc) return rc;
       for (uint32_t done = 0; done < n_sweeps; done += spl) {
         const uint32_t n = std::min(spl, n_sweeps - done);
-        KERNEL_OK(c, icmk_launch_sweep(d, 1, g.jkind, g.deg, tables, n, threads, slots, lds, c->stream));
+        KERNEL_OK(c, icmk_launch_sweep(d, 1, g.jkind, g.deg, tables, n, threads, slots, lds, strm));
       }
     }
     return ICM_OK;
@@ -728,7 +733,7 @@ int launch_group(icm_ctx* c, const Group& g, uint32_t n_sweeps, bool per_instanc
     auto it = c->graphs.find(key);
     if (it == c->graphs.end()) {
       // Capture on a private stream (the context stream may be the legacy null
-      // stream, which cannot be captured); the graph is replayed on c->stream.
+      // stream, which cannot be captured); the graph is replayed on strm.
       if (!c->capture_stream)
         HIP_OK(c, hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
       HIP_OK(c, hipStreamSynchronize(c->stream));
@@ -749,13 +754,13 @@ int launch_group(icm_ctx* c, const Group& g, uint32_t n_sweeps, bool per_instanc
       HIP_OK(c, hipGraphDestroy(graph));
       it = c->graphs.emplace(key, exec).first;
     }
-    HIP_OK(c, hipGraphLaunch(it->second, c->stream));
+    HIP_OK(c, hipGraphLaunch(it->second, strm));
   } else {
     for (uint32_t x = 0; x < full; ++x)
-      KERNEL_OK(c, icmk_launch_sweep(d, (int)g.handles.size(), g.jkind, g.deg, tables, spl, threads, slots, lds, c->stream));
+      KERNEL_OK(c, icmk_launch_sweep(d, (int)g.handles.size(), g.jkind, g.deg, tables, spl, threads, slots, lds, strm));
   }
   if (rest)
-    KERNEL_OK(c, icmk_launch_sweep(d, (int)g.handles.size(), g.jkind, g.deg, tables, rest, threads, slots, lds, c->stream));
+    KERNEL_OK(c, icmk_launch_sweep(d, (int)g.handles.size(), g.jkind, g.deg, tables, rest, threads, slots, lds, strm));
   return ICM_OK;
 }
 
@@ -767,9 +772,51 @@ int run_impl(icm_ctx* c, const int32_t* handles, int32_t n, uint32_t n_sweeps, b
       if (handles[y] == handles[x]) return fail(c, ICM_E_INVALID, "handle %d listed twice", handles[x]);
   }
   if (n == 0 || n_sweeps == 0) return ICM_OK;
-  for (const Group& g : group_handles(c, handles, n)) {
-    int rc = launch_group(c, g, n_sweeps, per_instance);
-    if (rc) return rc;
+  const std::vector<Group> groups = group_handles(c, handles, n);
+  if (per_instance || groups.size() == 1) {
+    for (const Group& g : groups) {
+      int rc = launch_group(c, g, n_sweeps, per_instance, c->stream);
+      if (rc) return rc;
+    }
+  } else {
+    // Groups that fill the device on their own (at least one workgroup per
+    // CU) run one after the other on the context stream; smaller ones run
+    // concurrently on side streams (fork after the work queued so far, join
+    // the context stream to all of them).
+    std::vector<size_t> big, small;
+    for (size_t gi = 0; gi < groups.size(); ++gi)
+      (groups[gi].handles.size() >= (size_t)c->n_cus ? big : small).push_back(gi);
+    const size_t nside = std::min<size_t>(small.size(), 3);
+    while (c->events.size() < nside + 1) {
+      hipEvent_t e;
+      HIP_OK(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      c->events.push_back(e);
+    }
+    for (size_t x = 0; x < nside; ++x)
+      if (!c->side[x]) HIP_OK(c, hipStreamCreateWithFlags(&c->side[x], hipStreamNonBlocking));
+    // device work tables first: building one synchronises the context stream,
+    // which must not wait for a group already launched
+    for (const Group& g : groups) {
+      UnitDesc* d = nullptr;
+      int rc = unit_table(c, g.handles, &d);
+      if (rc) return rc;
+    }
+    if (nside) {
+      HIP_OK(c, hipEventRecord(c->events[0], c->stream));
+      for (size_t x = 0; x < nside; ++x) HIP_OK(c, hipStreamWaitEvent(c->side[x], c->events[0], 0));
+    }
+    for (size_t x = 0; x < small.size(); ++x) {
+      int rc = launch_group(c, groups[small[x]], n_sweeps, false, c->side[x % 3]);
+      if (rc) return rc;
+    }
+    for (size_t gi : big) {
+      int rc = launch_group(c, groups[gi], n_sweeps, false, c->stream);
+      if (rc) return rc;
+    }
+    for (size_t x = 0; x < nside; ++x) {
+      HIP_OK(c, hipEventRecord(c->events[x + 1], c->side[x]));
+      HIP_OK(c, hipStreamWaitEvent(c->stream, c->events[x + 1], 0));
+    }
   }
   for (int x = 0; x < n; ++x) find(c, handles[x])->sweep_host += n_sweeps;
   return ICM_OK;
@@ -847,6 +894,9 @@ int icm_create(icm_ctx** out, int device, void* stream, void* arena, size_t aren
   int lds = 0;
   if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
     c->lds_limit = (size_t)lds;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+    c->n_cus = cus;
   (void)icmk_set_lds_limit(c->lds_limit);
   (void)hipGetLastError();
   *out = c.release();
@@ -859,6 +909,9 @@ int icm_destroy(icm_ctx* c) {
   (void)hipStreamSynchronize(c->stream);
   for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.second);
   if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
+  for (hipStream_t& x : c->side)
+    if (x) (void)hipStreamDestroy(x);
+  for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
   delete c;
   return ICM_OK;
 }
