@@ -291,6 +291,43 @@ __device__ __forceinline__ void cube8_dirs(uint32_t f, uint32_t out[6]) {
   out[5] = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)f, 0x122, 0xF, 0xF, false);  // word w - 2
 }
 
+
+// Chimera with one word per lane (at most 64 words): word w holds cells
+// 4w..4w+3, one byte each (bits u = 0..7).  The four inter-cell terms of the
+// shift program (rows +-1 for u < 4, columns +-1 for u >= 4) read the words
+// C/4 apart through ds_bpermute and the neighbouring words through DPP wave
+// shifts; m[] are this lane's masks of those terms (edges included), so bits
+// fetched from outside the move's words never survive.
+struct ChimeraStep {
+  int qv, rv;        // +8C bits = qv words + rv bits
+  uint32_t m[4];     // masks of: row+1, row-1, col+1, col-1
+};
+
+__device__ __forceinline__ uint32_t lane_fetch(uint32_t f, int src_lane) {
+  return (uint32_t)__builtin_amdgcn_ds_bpermute(src_lane << 2, (int)f);
+}
+
+// out: bits of F at the row+1, row-1, col+1, col-1 neighbour (zero where none)
+__device__ __forceinline__ void chimera_inter(uint32_t f, int lane, const ChimeraStep& cs, uint32_t out[4]) {
+  const uint32_t up_lo = lane_fetch(f, lane + cs.qv);
+  const uint32_t up_hi = cs.rv ? lane_fetch(f, lane + cs.qv + 1) : 0u;
+  const int qd = -cs.qv - (cs.rv ? 1 : 0), rd = (32 - cs.rv) & 31;
+  const uint32_t dn_lo = lane_fetch(f, lane + qd);
+  const uint32_t dn_hi = cs.rv ? lane_fetch(f, lane + qd + 1) : 0u;
+  const uint32_t fr = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)f, 0x130, 0xF, 0xF, false);  // lane + 1
+  const uint32_t fl = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)f, 0x138, 0xF, 0xF, false);  // lane - 1
+  out[0] = (cs.rv ? __builtin_amdgcn_alignbit(up_hi, up_lo, (uint32_t)cs.rv) : up_lo) & cs.m[0];
+  out[1] = (cs.rv ? __builtin_amdgcn_alignbit(dn_hi, dn_lo, (uint32_t)rd) : dn_lo) & cs.m[1];
+  out[2] = __builtin_amdgcn_alignbit(fr, f, 8u) & cs.m[2];
+  out[3] = __builtin_amdgcn_alignbit(f, fl, 24u) & cs.m[3];
+}
+
+// In-cell neighbour of slot k (u < 4 couples to 4 + k, u >= 4 to k).
+__device__ __forceinline__ uint32_t chimera_slot(uint32_t f, int k) {
+  const uint32_t lo = (f >> (4 + k)) & 0x01010101u, hi = (f >> k) & 0x01010101u;
+  return ((lo << 4) - lo) | (((hi << 4) - hi) << 4);
+}
+
 // Bits i..i+31 of a bitset shifted by s (result bit b = F[32 w + b + s]).  F
 // points at word 0 of an array padded with one zero word on each side; the
 // reads are clamped to the padding, which only matters for words where the
@@ -543,6 +580,7 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
       const uint32_t* tmask = (const uint32_t*)(lds + lay.terms) + kMaxTerms;
       const bool chim = U.topo == 2;
       const bool cube8 = U.topo == 1 && U.L == 8;  // lpm = 16: one word per lane
+      const bool chimreg = chim && nw <= 64;        // one word per lane
       const bool record = (flags & kFlagRecord) && s + 1 == n_sweeps;
       if (wave < iwaves) {
         const int grp = lane / lpm, li = lane - grp * lpm;
@@ -700,8 +738,28 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
             gmc[2 * li + 1] = c;
             wave_sync();
           }
+          if (chimreg) {
+            ChimeraStep cs;
+            cs.qv = (8 * U.L) >> 5;
+            cs.rv = (8 * U.L) & 31;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) cs.m[t] = li < nw ? tmask[t * nw + li] : 0u;
+            const uint32_t m = li < nw ? gmc[2 * li] : 0u;
+            uint32_t c = li < nw ? gmc[2 * li + 1] : 0u;
+            uint32_t f = c;
+            while (true) {
+              uint32_t g4[4];
+              chimera_inter(f, lane, cs, g4);
+              const uint32_t fn = (chimera_in_cell(f) | g4[0] | g4[1] | g4[2] | g4[3]) & m & ~c;
+              c |= fn;
+              f = fn;
+              if (!__ballot(fn != 0u)) break;
+            }
+            if (li < nw) gmc[2 * li + 1] = c;
+            wave_sync();
+          }
           int cur = 0;
-          while (!cube8) {
+          while (!cube8 && !chimreg) {
             const uint32_t* fc = gsl + 1 + cur * (nw + 2);
             uint32_t* fnx = gsl + 1 + (cur ^ 1) * (nw + 2);
             bool grew = false;
@@ -765,7 +823,58 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
                 }
               }
             }
-            for (int w = li; w < nw && !cube8; w += lpm) {
+            if (chimreg) {
+              // slots 0-3 in-cell, 4 = row-1 / col-1, 5 = row+1 / col+1
+              ChimeraStep cs;
+              cs.qv = (8 * U.L) >> 5;
+              cs.rv = (8 * U.L) & 31;
+#pragma unroll
+              for (int t = 0; t < 4; ++t) cs.m[t] = li < nw ? tmask[t * nw + li] : 0u;
+              const uint32_t cw = li < nw ? gmc[2 * li + 1] : 0u, awd = li < nw ? gaw[li] : 0u;
+              uint32_t ci[4], ai[4];
+              chimera_inter(cw, lane, cs, ci);
+              chimera_inter(awd, lane, cs, ai);
+              csize = __popc(cw);
+#pragma unroll
+              for (int d = 0; d < 6; ++d) {
+                uint32_t nb, na;
+                if (d < 4) {
+                  nb = chimera_slot(cw, d);
+                  na = chimera_slot(awd, d);
+                } else if (d == 4) {
+                  nb = ci[1] | ci[3];
+                  na = ai[1] | ai[3];
+                } else {
+                  nb = ci[0] | ci[2];
+                  na = ai[0] | ai[2];
+                }
+                const uint32_t exist = d < 4 ? ~0u : (d == 4 ? (cs.m[1] | cs.m[3]) : (cs.m[0] | cs.m[2]));
+                uint32_t bb = cw & ~nb & exist;
+                const uint32_t anti = awd ^ na;
+                while (bb) {
+                  const int bpos = __builtin_ctz(bb);
+                  bb &= bb - 1u;
+                  const int x = (32 * li + bpos) * DEG + d;
+                  if (JK) {
+                    const double J = (double)cf[x];
+                    dEa += ((anti >> bpos) & 1u) ? -J : J;
+                  } else {
+                    const int J = cj[x];
+                    dEa += ((anti >> bpos) & 1u) ? -J : J;
+                  }
+                }
+              }
+              for (uint32_t fl = cw; fl; fl &= fl - 1u) {
+                const int i = 32 * li + __builtin_ctz(fl);
+                if (rowa == rowb) {
+                  atomicXor(&rowa[i], fa | fb);
+                } else {
+                  atomicXor(&rowa[i], fa);
+                  atomicXor(&rowb[i], fb);
+                }
+              }
+            }
+            for (int w = li; w < nw && !cube8 && !chimreg; w += lpm) {
               uint32_t cw = gmc[2 * w + 1];
               const uint32_t awd = gaw[w];
               csize += __popc(cw);
