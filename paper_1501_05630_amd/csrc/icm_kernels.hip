@@ -328,6 +328,18 @@ __device__ __forceinline__ uint32_t chimera_slot(uint32_t f, int k) {
   return ((lo << 4) - lo) | (((hi << 4) - hi) << 4);
 }
 
+
+// Term t of the shift program applied to a register-resident bitset (one word
+// per lane, word w at lane base + w): bits F[i + shift] fetched from the
+// lanes holding words w + q and w + q + 1, masked to where the term holds.
+__device__ __forceinline__ uint32_t reg_term(uint32_t f, int lane, int shift, uint32_t mask) {
+  const int q = shift >> 5, r = shift & 31;
+  const uint32_t lo = lane_fetch(f, lane + q);
+  if (r == 0) return lo & mask;
+  const uint32_t hi = lane_fetch(f, lane + q + 1);
+  return __builtin_amdgcn_alignbit(hi, lo, (uint32_t)r) & mask;
+}
+
 // Bits i..i+31 of a bitset shifted by s (result bit b = F[32 w + b + s]).  F
 // points at word 0 of an array padded with one zero word on each side; the
 // reads are clamped to the padding, which only matters for words where the
@@ -581,6 +593,7 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
       const bool chim = U.topo == 2;
       const bool cube8 = U.topo == 1 && U.L == 8;  // lpm = 16: one word per lane
       const bool chimreg = chim && nw <= 64;        // one word per lane
+      const bool latreg = !chim && !cube8 && nw <= 64;  // periodic lattice, one word per lane
       const bool record = (flags & kFlagRecord) && s + 1 == n_sweeps;
       if (wave < iwaves) {
         const int grp = lane / lpm, li = lane - grp * lpm;
@@ -758,8 +771,28 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
             if (li < nw) gmc[2 * li + 1] = c;
             wave_sync();
           }
+          if (latreg) {
+            uint32_t tm[kMaxTerms];
+#pragma unroll
+            for (int t = 0; t < kMaxTerms; ++t) tm[t] = (t < nterm && li < nw) ? tmask[t * nw + li] : 0u;
+            const uint32_t m = li < nw ? gmc[2 * li] : 0u;
+            uint32_t c = li < nw ? gmc[2 * li + 1] : 0u;
+            uint32_t f = c;
+            while (true) {
+              uint32_t gw = 0;
+#pragma unroll
+              for (int t = 0; t < kMaxTerms; ++t)
+                if (t < nterm) gw |= reg_term(f, lane, uniform(tshift[t]), tm[t]);
+              const uint32_t fn = gw & m & ~c;
+              c |= fn;
+              f = fn;
+              if (!__ballot(fn != 0u)) break;
+            }
+            if (li < nw) gmc[2 * li + 1] = c;
+            wave_sync();
+          }
           int cur = 0;
-          while (!cube8 && !chimreg) {
+          while (!cube8 && !chimreg && !latreg) {
             const uint32_t* fc = gsl + 1 + cur * (nw + 2);
             uint32_t* fnx = gsl + 1 + (cur ^ 1) * (nw + 2);
             bool grew = false;
@@ -874,34 +907,96 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
                 }
               }
             }
-            for (int w = li; w < nw && !cube8 && !chimreg; w += lpm) {
-              uint32_t cw = gmc[2 * w + 1];
-              const uint32_t awd = gaw[w];
-              csize += __popc(cw);
-              while (cw) {
-                const int bpos = __builtin_ctz(cw);
-                cw &= cw - 1u;
-                const int i = 32 * w + bpos;
-                const uint32_t ai = (awd >> bpos) & 1u;
+            if (latreg) {
+              // slot 2a = +axis a (terms 4a, 4a+1), slot 2a+1 = -axis a (terms 4a+2, 4a+3)
+              const uint32_t cw = li < nw ? gmc[2 * li + 1] : 0u, awd = li < nw ? gaw[li] : 0u;
+              csize = __popc(cw);
 #pragma unroll
-                for (int d = 0; d < DEG; ++d) {
-                  const int j = nbr[i * DEG + d];
-                  if (!((gmc[2 * (j >> 5)] >> (j & 31)) & 1u)) {
-                    const bool anti = (ai ^ (gaw[j >> 5] >> (j & 31))) & 1u;  // s_a,i s_a,j = -1
-                    if (JK) {
-                      const double J = (double)cf[i * DEG + d];
-                      dEa += anti ? -J : J;
-                    } else {
-                      const int J = cj[i * DEG + d];
-                      dEa += anti ? -J : J;
-                    }
+              for (int d = 0; d < DEG; ++d) {
+                const int t0 = 2 * d;
+                const int s0 = uniform(tshift[t0]), s1 = uniform(tshift[t0 + 1]);
+                const uint32_t m0 = li < nw ? tmask[t0 * nw + li] : 0u;
+                const uint32_t m1 = li < nw ? tmask[(t0 + 1) * nw + li] : 0u;
+                const uint32_t nb = reg_term(cw, lane, s0, m0) | reg_term(cw, lane, s1, m1);
+                const uint32_t na = reg_term(awd, lane, s0, m0) | reg_term(awd, lane, s1, m1);
+                uint32_t bb = cw & ~nb;
+                const uint32_t anti = awd ^ na;
+                while (bb) {
+                  const int bpos = __builtin_ctz(bb);
+                  bb &= bb - 1u;
+                  const int x = (32 * li + bpos) * DEG + d;
+                  if (JK) {
+                    const double J = (double)cf[x];
+                    dEa += ((anti >> bpos) & 1u) ? -J : J;
+                  } else {
+                    const int J = cj[x];
+                    dEa += ((anti >> bpos) & 1u) ? -J : J;
                   }
                 }
+              }
+              for (uint32_t fl = cw; fl; fl &= fl - 1u) {
+                const int i = 32 * li + __builtin_ctz(fl);
                 if (rowa == rowb) {
                   atomicXor(&rowa[i], fa | fb);
                 } else {
                   atomicXor(&rowa[i], fa);
                   atomicXor(&rowb[i], fb);
+                }
+              }
+            }
+            if (!cube8 && !chimreg && !latreg) {
+              // cluster and replica-a words into the (now free) padded frontier
+              // buffers, then boundary bonds slot by slot through the shift program
+              uint32_t* pcw = gsl + 1;
+              uint32_t* paw = gsl + 1 + (nw + 2);
+              for (int w = li; w < nw; w += lpm) {
+                pcw[w] = gmc[2 * w + 1];
+                paw[w] = gaw[w];
+              }
+              wave_sync();
+              for (int w = li; w < nw; w += lpm) {
+                const uint32_t cw = pcw[w], awd = paw[w];
+                csize += __popc(cw);
+#pragma unroll
+                for (int d = 0; d < DEG; ++d) {
+                  uint32_t nb, na, exist = ~0u;
+                  if (chim && d < 4) {
+                    nb = chimera_slot(cw, d);
+                    na = chimera_slot(awd, d);
+                  } else {
+                    // lattice slot 2a / 2a+1: terms 2d, 2d+1; chimera slot 4: rows-1
+                    // and cols-1 (terms 1, 3), slot 5: rows+1 and cols+1 (terms 0, 2)
+                    const int ta = chim ? (d == 4 ? 1 : 0) : 2 * d;
+                    const int tb = chim ? (d == 4 ? 3 : 2) : 2 * d + 1;
+                    const int sa = uniform(tshift[ta]), sb = uniform(tshift[tb]);
+                    const uint32_t ma = tmask[ta * nw + w], mb = tmask[tb * nw + w];
+                    nb = (shifted_word(pcw, w, sa, nw) & ma) | (shifted_word(pcw, w, sb, nw) & mb);
+                    na = (shifted_word(paw, w, sa, nw) & ma) | (shifted_word(paw, w, sb, nw) & mb);
+                    if (chim) exist = ma | mb;
+                  }
+                  uint32_t bb = cw & ~nb & exist;
+                  const uint32_t anti = awd ^ na;
+                  while (bb) {
+                    const int bpos = __builtin_ctz(bb);
+                    bb &= bb - 1u;
+                    const int x = (32 * w + bpos) * DEG + d;
+                    if (JK) {
+                      const double J = (double)cf[x];
+                      dEa += ((anti >> bpos) & 1u) ? -J : J;
+                    } else {
+                      const int J = cj[x];
+                      dEa += ((anti >> bpos) & 1u) ? -J : J;
+                    }
+                  }
+                }
+                for (uint32_t fl = cw; fl; fl &= fl - 1u) {
+                  const int i = 32 * w + __builtin_ctz(fl);
+                  if (rowa == rowb) {
+                    atomicXor(&rowa[i], fa | fb);
+                  } else {
+                    atomicXor(&rowa[i], fa);
+                    atomicXor(&rowb[i], fb);
+                  }
                 }
               }
             }
