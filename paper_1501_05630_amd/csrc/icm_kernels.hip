@@ -136,10 +136,13 @@ __device__ __forceinline__ double uniform_d(double v) {
 // ----------------------------------------------------------------------------
 // Metropolis acceptance for float couplings.  dE is exact (2^-32 grid); the
 // decision is u * 2^-32 < exp(-beta dE) in double.  A float estimate settles
-// all but a ~1e-4 band around the boundary: p32 = 2^(-dE * beta log2 e) has a
-// relative error below 2^-18 for every exponent that matters, so with a 2^-14
-// margin the fast accept/reject can only be taken when the double comparison
-// gives the same answer; the band falls back to the double evaluation.
+// all but a ~1e-4 band around the boundary: P = 2^(32 - dE * beta log2 e)
+// (the 2^32 scale folded into the exponent of one fma) has a relative error
+// below 2^-18 wherever 1 <= P <= 2^32, and float(u) is within a relative
+// 2^-24 of u; with a 2^-14 margin on both sides the fast accept/reject is only
+// taken where the double comparison gives the same answer (for P < 1 only
+// u = 0 can be accepted, and that case reaches the double test whenever P
+// underflows).  The band falls back to the double evaluation.
 // ----------------------------------------------------------------------------
 // Out of line: taken for ~1e-4 of the attempts, and inlining it would keep the
 // double exp's constants in registers across the whole sweep loop.
@@ -149,10 +152,10 @@ __device__ __noinline__ bool accept_exact(uint32_t u, double dE, double beta) {
 
 __device__ __forceinline__ bool accept_float(uint32_t u, double dE, double beta, float bl2e) {
   if (dE <= 0.0) return true;
-  const float p = __builtin_amdgcn_exp2f(-((float)dE * bl2e));
-  const float uf = (float)(u >> 8) * 0x1p-24f;  // exact; true u/2^32 lies in [uf, uf + 2^-24)
-  if (uf > p * (1.0f + 0x1p-14f)) return false;
-  if (uf + 0x1p-24f <= p * (1.0f - 0x1p-14f)) return true;
+  const float P = __builtin_amdgcn_exp2f(__builtin_fmaf(-(float)dE, bl2e, 32.0f));
+  const float uf = (float)u;
+  if (uf > P * (1.0f + 0x1p-14f)) return false;
+  if (uf < P * (1.0f - 0x1p-14f)) return true;
   return accept_exact(u, dE, beta);
 }
 
@@ -449,7 +452,7 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
   const uint32_t t0 = *U.sweep;
   const uint32_t flags = U.flags, seed = U.seed, key = U.key;
   const int lane = lane_id(), wave = wave_id(), nwaves = nthr >> 6;
-  unsigned long long metro_acc = 0;  // wave-uniform counter, flushed at the end
+  uint32_t metro_cnt = 0;  // accepted flips of this lane, flushed once per sweep
 
   for (uint32_t s = 0; s < n_sweeps; ++s) {
     const uint32_t t = t0 + s;
@@ -506,10 +509,11 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
             const int g = q >> 3, sh = 4 * (q & 7);
             uint32_t* row = sp + g * N;
             const int i = clist[c * Nc + j];
-            const uint32_t own = row[i] >> sh;
+            // bit sh + b of a word is walker 4q + b (one bit-field extract each)
+            const uint32_t own = row[i];
             uint32_t nw[DEG];
 #pragma unroll
-            for (int d = 0; d < DEG; ++d) nw[d] = row[nbr[i * DEG + d]] >> sh;
+            for (int d = 0; d < DEG; ++d) nw[d] = row[nbr[i * DEG + d]];
             const Words4 u = philox4x32_10((uint32_t)i, t, (uint32_t)q, kStreamMetro, seed, key);
             uint32_t flip = 0;
             if (JK) {
@@ -523,9 +527,9 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
                 if (tq[b] >= K) continue;
                 double m = 0.0;
 #pragma unroll
-                for (int d = 0; d < DEG; ++d) m += Jd[d] * (double)bit_of(nw[d], b);
+                for (int d = 0; d < DEG; ++d) m += Jd[d] * (double)bit_of(nw[d], sh + b);
                 const double h = Jsum - 2.0 * m;
-                const double dE = bit_of(own, b) ? -2.0 * h : 2.0 * h;
+                const double dE = bit_of(own, sh + b) ? -2.0 * h : 2.0 * h;
                 if (accept_float(u.w[b], dE, bq[b], lq[b])) {
                   flip |= 1u << b;
                   acc[b] += (E_t)dE;
@@ -541,9 +545,9 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
                 if (tq[b] >= K) continue;
                 int m = 0;
 #pragma unroll
-                for (int d = 0; d < DEG; ++d) m += Ji[d] * (int)bit_of(nw[d], b);
+                for (int d = 0; d < DEG; ++d) m += Ji[d] * (int)bit_of(nw[d], sh + b);
                 const int h = Jsum - 2 * m;
-                const int e = bit_of(own, b) ? -h : h;  // dE = 2e
+                const int e = bit_of(own, sh + b) ? -h : h;  // dE = 2e
                 if (e <= 0 || u.w[b] < thr[rowb[b] + e]) {
                   flip |= 1u << b;
                   acc[b] += (E_t)(2 * e);
@@ -551,10 +555,7 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
               }
             }
             if (flip) atomicXor(&row[i], flip << sh);
-            metro_acc += (unsigned long long)__popcll(__ballot(flip & 1u)) +
-                         (unsigned long long)__popcll(__ballot(flip & 2u)) +
-                         (unsigned long long)__popcll(__ballot(flip & 4u)) +
-                         (unsigned long long)__popcll(__ballot(flip & 8u));
+            metro_cnt += __popc(flip);
           }
         }
         if (cur_q >= 0) {
@@ -565,6 +566,11 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
           }
         }
         __syncthreads();
+      }
+      {
+        const int tot = wave_sum((int)metro_cnt);
+        if (lane == 0 && tot) atomicAdd(&stats[kStatMetroAcc], (unsigned long long)tot);
+        metro_cnt = 0;
       }
     }
 
@@ -1070,7 +1076,6 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
   }
 
   // ---- store the unit back (bit-packed -> int8 quad words) ----
-  if (lane == 0 && metro_acc) atomicAdd(&stats[kStatMetroAcc], metro_acc);
   __syncthreads();
   for (int x = tid; x < Wq * N; x += nthr) {
     const int q = x / N, i = x - q * N;
