@@ -1169,14 +1169,84 @@ size_t desc_coupling_bytes(const icm_instance_desc* d) {
   return (size_t)coupling_count(d->topology, d->L) * (d->jkind == ICM_J_F32 ? 4 : 1);
 }
 
+// Resident requests that share a kernel variant and size class advance
+// together, one sweep block at a time, on a serving stream of their own: a
+// group launches its next block as soon as its previous one is done, so small
+// requests are not held back by the block time of large ones.
+struct ServeGroup {
+  int jkind = 0, deg = 0, cls = 0;
+  std::vector<std::shared_ptr<Request>> members;   // resident, not finished
+  std::vector<std::shared_ptr<Request>> inflight;  // those in the running block
+  uint32_t block = 0;
+  bool running = false;
+  hipStream_t strm = nullptr;
+  hipEvent_t done = nullptr;
+};
+
+void retire(icm_ctx* c, const std::shared_ptr<Request>& r) {
+  Instance* in = find(c, r->handle);
+  std::vector<int64_t> e((size_t)in->K * in->R);
+  std::vector<int8_t> st((size_t)in->W * in->N);
+  icm_read_energies(c, r->handle, e.data(), nullptr, e.size());
+  icm_read_states(c, r->handle, st.data(), st.size());
+  drop_cached_tables(c, r->handle);
+  release_instance(c, in);
+  c->instances.erase(r->handle);
+  std::lock_guard<std::mutex> lk(c->mu);
+  r->energies = std::move(e);
+  r->states = std::move(st);
+  r->done = true;
+  r->t_done = std::chrono::steady_clock::now();
+}
+
+void fail_all(icm_ctx* c, std::vector<ServeGroup>& groups) {
+  c->poisoned = true;
+  std::lock_guard<std::mutex> lk(c->mu);
+  for (auto& g : groups)
+    for (auto& r : g.members) {
+      r->error = ICM_E_DEVICE;
+      r->done = true;
+      r->t_done = std::chrono::steady_clock::now();
+    }
+  for (auto& r : c->queue) {
+    r->error = ICM_E_DEVICE;
+    r->done = true;
+    r->t_done = std::chrono::steady_clock::now();
+  }
+  c->queue.clear();
+}
+
 void serve_loop(icm_ctx* c) {
-  std::vector<std::shared_ptr<Request>> active;
-  while (true) {
+  constexpr int kServeStreams = 4;
+  hipStream_t streams[kServeStreams] = {};
+  std::vector<ServeGroup> groups;
+  bool ok = true;
+  for (auto& x : streams) ok = ok && hipStreamCreateWithFlags(&x, hipStreamNonBlocking) == hipSuccess;
+  auto group_of = [&](Instance* in) -> ServeGroup* {
+    const int cls = size_class(in->N);
+    for (auto& g : groups)
+      if (g.jkind == in->jkind && g.deg == in->deg && g.cls == cls) return &g;
+    ServeGroup g;
+    g.jkind = in->jkind;
+    g.deg = in->deg;
+    g.cls = cls;
+    g.strm = streams[groups.size() % kServeStreams];
+    if (hipEventCreateWithFlags(&g.done, hipEventDisableTiming) != hipSuccess) return nullptr;
+    groups.push_back(std::move(g));
+    return &groups.back();
+  };
+  auto resident = [&] {
+    for (auto& g : groups)
+      if (!g.members.empty()) return true;
+    return false;
+  };
+  while (ok) {
+    bool progressed = false, stopping = false;
+    std::vector<std::shared_ptr<Request>> admitted;
     {
-      std::unique_lock<std::mutex> lk(c->mu);
-      if (active.empty())
-        c->cv.wait_for(lk, std::chrono::milliseconds(2), [&] { return !c->queue.empty() || !c->serving; });
-      if (!c->serving && active.empty()) {
+      std::lock_guard<std::mutex> lk(c->mu);
+      stopping = !c->serving;
+      if (stopping) {
         // stopping: whatever is still queued is returned unrun
         for (auto& r : c->queue) {
           r->error = ICM_E_BUSY;
@@ -1184,14 +1254,13 @@ void serve_loop(icm_ctx* c) {
           r->t_done = std::chrono::steady_clock::now();
         }
         c->queue.clear();
-        break;
       }
       // admission: as many queued requests as the arena holds, in arrival order
       while (!c->queue.empty() && !c->poisoned) {
         std::shared_ptr<Request> r = c->queue.front();
         int32_t h = -1;
         int rc = add_instance_impl(c, &r->desc, &h);
-        if (rc == ICM_E_NOMEM && !active.empty()) break;  // wait for a retirement
+        if (rc == ICM_E_NOMEM && (resident() || !admitted.empty())) break;  // wait for a retirement
         c->queue.pop_front();
         if (rc == ICM_OK) rc = icm_init_states(c, h);
         if (rc != ICM_OK) {  // invalid, or larger than the whole arena
@@ -1201,54 +1270,73 @@ void serve_loop(icm_ctx* c) {
           continue;
         }
         r->handle = h;
-        active.push_back(r);
+        admitted.push_back(r);
       }
     }
-    if (active.empty()) {
-      if (!c->serving) {
-        std::lock_guard<std::mutex> lk(c->mu);
-        if (c->queue.empty()) break;
+    if (!admitted.empty()) {
+      progressed = true;
+      // the hot starts ran on the context stream: done before any group uses them
+      if (hipStreamSynchronize(c->stream) != hipSuccess) { fail_all(c, groups); break; }
+      for (auto& r : admitted) {
+        ServeGroup* g = group_of(find(c, r->handle));
+        if (!g) { ok = false; break; }
+        g->members.push_back(r);
       }
-      continue;
+      if (!ok) { fail_all(c, groups); break; }
     }
-    uint32_t b = (uint32_t)c->serve_block;
-    for (auto& r : active) b = std::min(b, r->n_sweeps - r->done_sweeps);
-    std::vector<int32_t> hs;
-    for (auto& r : active) hs.push_back(r->handle);
-    if (run_impl(c, hs.data(), (int)hs.size(), b, false) != ICM_OK ||
-        hipStreamSynchronize(c->stream) != hipSuccess) {
-      c->poisoned = true;
-      std::lock_guard<std::mutex> lk(c->mu);
-      for (auto& r : active) {
-        r->error = ICM_E_DEVICE;
-        r->done = true;
-        r->t_done = std::chrono::steady_clock::now();
+    // completions
+    for (auto& g : groups) {
+      if (!g.running) continue;
+      const hipError_t q = hipEventQuery(g.done);
+      if (q == hipErrorNotReady) continue;
+      if (q != hipSuccess) { ok = false; break; }
+      g.running = false;
+      progressed = true;
+      for (auto& r : g.inflight) {
+        r->done_sweeps += g.block;
+        if (r->done_sweeps < r->n_sweeps) continue;
+        g.members.erase(std::find(g.members.begin(), g.members.end(), r));
+        retire(c, r);
       }
-      active.clear();
-      break;
+      g.inflight.clear();
     }
-    std::vector<std::shared_ptr<Request>> still;
-    for (auto& r : active) {
-      r->done_sweeps += b;
-      if (r->done_sweeps < r->n_sweeps) { still.push_back(r); continue; }
-      Instance* in = find(c, r->handle);
-      std::vector<int64_t> e((size_t)in->K * in->R);
-      std::vector<int8_t> st((size_t)in->W * in->N);
-      icm_read_energies(c, r->handle, e.data(), nullptr, e.size());
-      icm_read_states(c, r->handle, st.data(), st.size());
-      HostState dummy;
-      (void)dummy;
-      drop_cached_tables(c, r->handle);
-      release_instance(c, in);
-      c->instances.erase(r->handle);
-      std::lock_guard<std::mutex> lk(c->mu);
-      r->energies = std::move(e);
-      r->states = std::move(st);
-      r->done = true;
-      r->t_done = std::chrono::steady_clock::now();
+    if (!ok) { fail_all(c, groups); break; }
+    // launches: every idle group with resident requests starts its next block
+    for (auto& g : groups) {
+      if (g.running || g.members.empty()) continue;
+      uint32_t b = (uint32_t)c->serve_block;
+      Group lg{g.jkind, g.deg, g.cls, {}};
+      for (auto& r : g.members) {
+        b = std::min(b, r->n_sweeps - r->done_sweeps);
+        lg.handles.push_back(r->handle);
+      }
+      if (launch_group(c, lg, b, false, g.strm) != ICM_OK || hipEventRecord(g.done, g.strm) != hipSuccess) {
+        ok = false;
+        break;
+      }
+      for (auto& r : g.members) find(c, r->handle)->sweep_host += b;
+      g.inflight = g.members;
+      g.block = b;
+      g.running = true;
+      progressed = true;
     }
-    active.swap(still);
+    if (!ok) { fail_all(c, groups); break; }
+    if (stopping) {
+      bool busy = false;
+      for (auto& g : groups) busy = busy || g.running || !g.members.empty();
+      if (!busy) break;
+    }
+    if (!progressed) {
+      std::unique_lock<std::mutex> lk(c->mu);
+      c->cv.wait_for(lk, std::chrono::microseconds(200),
+                     [&] { return (!c->queue.empty() && !c->poisoned) || !c->serving; });
+    }
   }
+  for (auto& x : streams)
+    if (x) (void)hipStreamSynchronize(x);
+  for (auto& g : groups) (void)hipEventDestroy(g.done);
+  for (auto& x : streams)
+    if (x) (void)hipStreamDestroy(x);
 }
 
 }  // namespace
