@@ -343,6 +343,59 @@ __device__ __forceinline__ uint32_t reg_term(uint32_t f, int lane, int shift, ui
   return __builtin_amdgcn_alignbit(hi, lo, (uint32_t)r) & mask;
 }
 
+
+// Two words per lane (lane l holds words 2l and 2l+1, a 64-bit value) for the
+// two large periodic lattices of the workloads.
+//  2D L=64: lane y holds row y (x = 0..63); x steps rotate the row, y steps are
+//   the rows of lanes y +- 1 (DPP wave rotates wrap at 64 rows).
+//  3D L=16: lane l holds plane z = l / 4, rows y = 4 (l % 4) .. +3 (16 bits
+//   each); x steps rotate within 16-bit rows, y steps shift rows and borrow one
+//   row from the next / previous lane of the quad (the quad is the whole plane,
+//   so the quad rotation is the periodic wrap), z steps are the lanes 4 apart.
+// Neighbour bitset of direction d (neighbour-table order +x, -x, +y, -y[, +z, -z]).
+__device__ __forceinline__ void pair_dir(bool sq, uint32_t lo, uint32_t hi, int lane, int d, uint32_t& olo,
+                                         uint32_t& ohi) {
+  if (sq) {
+    switch (d) {
+      case 0: olo = __builtin_amdgcn_alignbit(hi, lo, 1u); ohi = __builtin_amdgcn_alignbit(lo, hi, 1u); break;
+      case 1: olo = __builtin_amdgcn_alignbit(lo, hi, 31u); ohi = __builtin_amdgcn_alignbit(hi, lo, 31u); break;
+      case 2:
+        olo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lo, 0x134, 0xF, 0xF, false);
+        ohi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)hi, 0x134, 0xF, 0xF, false);
+        break;
+      default:
+        olo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lo, 0x13C, 0xF, 0xF, false);
+        ohi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)hi, 0x13C, 0xF, 0xF, false);
+        break;
+    }
+    return;
+  }
+  switch (d) {
+    case 0:
+      olo = ((lo >> 1) & 0x7FFF7FFFu) | ((lo << 15) & 0x80008000u);
+      ohi = ((hi >> 1) & 0x7FFF7FFFu) | ((hi << 15) & 0x80008000u);
+      break;
+    case 1:
+      olo = ((lo << 1) & 0xFFFEFFFEu) | ((lo >> 15) & 0x00010001u);
+      ohi = ((hi << 1) & 0xFFFEFFFEu) | ((hi >> 15) & 0x00010001u);
+      break;
+    case 2: {
+      const uint32_t nlo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lo, 0x39, 0xF, 0xF, false);
+      olo = (lo >> 16) | (hi << 16);
+      ohi = (hi >> 16) | (nlo << 16);
+      break;
+    }
+    case 3: {
+      const uint32_t phi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)hi, 0x93, 0xF, 0xF, false);
+      olo = (lo << 16) | (phi >> 16);
+      ohi = (hi << 16) | (lo >> 16);
+      break;
+    }
+    case 4: olo = lane_fetch(lo, (lane + 4) & 63); ohi = lane_fetch(hi, (lane + 4) & 63); break;
+    default: olo = lane_fetch(lo, (lane - 4) & 63); ohi = lane_fetch(hi, (lane - 4) & 63); break;
+  }
+}
+
 // Bits i..i+31 of a bitset shifted by s (result bit b = F[32 w + b + s]).  F
 // points at word 0 of an array padded with one zero word on each side; the
 // reads are clamped to the padding, which only matters for words where the
@@ -351,6 +404,95 @@ __device__ __forceinline__ uint32_t shifted_word(const uint32_t* F, int w, int s
   int q = w + (s >> 5);
   q = q < -1 ? -1 : (q > nw - 1 ? nw - 1 : q);
   return __builtin_amdgcn_alignbit(F[q + 1], F[q], (uint32_t)(s & 31));
+}
+
+
+// The two-word layouts' cluster growth and boundary walk, out of line: they
+// run once per move batch, and inlined they push the fused kernel past its
+// register budget.  LDS regions are passed as byte offsets into the dynamic
+// LDS array (so the accesses stay LDS accesses).
+extern __shared__ __align__(16) unsigned char lds[];
+
+__device__ __noinline__ void pair_grow(bool sq64, uint32_t mc_off, int lane) {
+  uint32_t* gmc = (uint32_t*)(lds + mc_off);
+  const uint32_t m0 = gmc[4 * lane], m1 = gmc[4 * lane + 2];
+  uint32_t c0 = gmc[4 * lane + 1], c1 = gmc[4 * lane + 3];
+  uint32_t f0 = c0, f1 = c1;
+  while (true) {
+    uint32_t g0 = 0, g1 = 0;
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+      if (sq64 && d >= 4) break;
+      uint32_t o0, o1;
+      pair_dir(sq64, f0, f1, lane, d, o0, o1);
+      g0 |= o0;
+      g1 |= o1;
+    }
+    const uint32_t n0 = g0 & m0 & ~c0, n1 = g1 & m1 & ~c1;
+    c0 |= n0;
+    c1 |= n1;
+    f0 = n0;
+    f1 = n1;
+    if (!__ballot((n0 | n1) != 0u)) break;
+  }
+  gmc[4 * lane + 1] = c0;
+  gmc[4 * lane + 3] = c1;
+}
+
+// Boundary bonds (slot by slot) and the flips of one cluster in the two-word
+// layouts; returns the sum of J s_a,i s_a,j over the bonds that leave it.
+template <int JK, int DEG>
+__device__ __noinline__ typename EnergyT<JK>::T pair_boundary(bool sq64, uint32_t mc_off, uint32_t aw_off,
+                                                             uint32_t coup_off, const void* coup_global,
+                                                             uint32_t rowa_off, uint32_t rowb_off,
+                                                             uint32_t fa, uint32_t fb, int lane, int& csize) {
+  using E_t = typename EnergyT<JK>::T;
+  const uint32_t* gmc = (const uint32_t*)(lds + mc_off);
+  const uint32_t* gaw = (const uint32_t*)(lds + aw_off);
+  const float* cf = coup_global ? (const float*)coup_global : (const float*)(lds + coup_off);
+  const int8_t* cj = coup_global ? (const int8_t*)coup_global : (const int8_t*)(lds + coup_off);
+  uint32_t* rowa = (uint32_t*)(lds + rowa_off);
+  uint32_t* rowb = (uint32_t*)(lds + rowb_off);
+  const uint32_t cw0 = gmc[4 * lane + 1], cw1 = gmc[4 * lane + 3];
+  const uint32_t aw0 = gaw[2 * lane], aw1 = gaw[2 * lane + 1];
+  csize = __popc(cw0) + __popc(cw1);
+  E_t dEa = 0;
+#pragma unroll
+  for (int d = 0; d < DEG; ++d) {
+    uint32_t c_lo, c_hi, a_lo, a_hi;
+    pair_dir(sq64, cw0, cw1, lane, d, c_lo, c_hi);
+    pair_dir(sq64, aw0, aw1, lane, d, a_lo, a_hi);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      uint32_t bb = (h ? cw1 : cw0) & ~(h ? c_hi : c_lo);
+      const uint32_t anti = (h ? aw1 : aw0) ^ (h ? a_hi : a_lo);
+      while (bb) {
+        const int bpos = __builtin_ctz(bb);
+        bb &= bb - 1u;
+        const int x = (64 * lane + 32 * h + bpos) * DEG + d;
+        if (JK) {
+          const double J = (double)cf[x];
+          dEa += ((anti >> bpos) & 1u) ? -J : J;
+        } else {
+          const int J = cj[x];
+          dEa += ((anti >> bpos) & 1u) ? -J : J;
+        }
+      }
+    }
+  }
+  const bool same = rowa == rowb;
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+    for (uint32_t fl = h ? cw1 : cw0; fl; fl &= fl - 1u) {
+      const int i = 64 * lane + 32 * h + __builtin_ctz(fl);
+      if (same) {
+        atomicXor(&rowa[i], fa | fb);
+      } else {
+        atomicXor(&rowa[i], fa);
+        atomicXor(&rowb[i], fb);
+      }
+    }
+  return dEa;
 }
 
 // ----------------------------------------------------------------------------
@@ -597,9 +739,12 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
       const int* tshift = (const int*)(lds + lay.terms);
       const uint32_t* tmask = (const uint32_t*)(lds + lay.terms) + kMaxTerms;
       const bool chim = U.topo == 2;
-      const bool cube8 = U.topo == 1 && U.L == 8;  // lpm = 16: one word per lane
-      const bool chimreg = chim && nw <= 64;        // one word per lane
+      const bool cube8 = DEG == 6 && U.topo == 1 && U.L == 8;  // lpm = 16: one word per lane
+      const bool chimreg = DEG == 6 && chim && nw <= 64;        // one word per lane
       const bool latreg = !chim && !cube8 && nw <= 64;  // periodic lattice, one word per lane
+      const bool sq64 = DEG == 4 && U.topo == 0 && U.L == 64;    // two words per lane
+      const bool cube16 = DEG == 6 && U.topo == 1 && U.L == 16;
+      const bool pair = sq64 || cube16;
       const bool record = (flags & kFlagRecord) && s + 1 == n_sweeps;
       if (wave < iwaves) {
         const int grp = lane / lpm, li = lane - grp * lpm;
@@ -797,8 +942,12 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
             if (li < nw) gmc[2 * li + 1] = c;
             wave_sync();
           }
+          if (pair) {
+            pair_grow(sq64, (uint32_t)((unsigned char*)gmc - lds), lane);
+            wave_sync();
+          }
           int cur = 0;
-          while (!cube8 && !chimreg && !latreg) {
+          while (!cube8 && !chimreg && !latreg && !pair) {
             const uint32_t* fc = gsl + 1 + cur * (nw + 2);
             uint32_t* fnx = gsl + 1 + (cur ^ 1) * (nw + 2);
             bool grew = false;
@@ -950,7 +1099,16 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
                 }
               }
             }
-            if (!cube8 && !chimreg && !latreg) {
+            if (pair) {
+              int cs2 = 0;
+              dEa = pair_boundary<JK, DEG>(sq64, (uint32_t)((unsigned char*)gmc - lds),
+                                           (uint32_t)((const unsigned char*)gaw - lds),
+                                           TL ? (uint32_t)((const unsigned char*)cf - lds) : 0u,
+                                           TL ? nullptr : U.coup, (uint32_t)((unsigned char*)rowa - lds),
+                                           (uint32_t)((unsigned char*)rowb - lds), fa, fb, lane, cs2);
+              csize = cs2;
+            }
+            if (!cube8 && !chimreg && !latreg && !pair) {
               // cluster and replica-a words into the (now free) padded frontier
               // buffers, then boundary bonds slot by slot through the shift program
               uint32_t* pcw = gsl + 1;
