@@ -155,6 +155,31 @@ def test_edge_cases_bit_exact(ctx, case):
     ctx.icm_remove_instance(h)
 
 
+@pytest.mark.parametrize("top,L,kind,K,R", [
+    (inputs.CHIMERA, 16, "int3", 6, 2),     # 64 words: one word per lane, full wave
+    (inputs.CHIMERA, 17, "gauss", 4, 2),    # 73 words: LDS shift program, chimera terms
+    (inputs.CHIMERA, 7, "int3", 6, 4),      # 13 words, rows not word-aligned (C % 4 = 3)
+    (inputs.CUBIC3D, 12, "gauss", 5, 4),    # 54 words, x-rows straddle words
+    (inputs.CUBIC3D, 10, "pmJ", 6, 2),      # 32 words: two moves per wave
+    (inputs.SQUARE2D, 32, "pmJ", 6, 2),     # 32 words
+    (inputs.SQUARE2D, 40, "gauss", 5, 2),   # 50 words
+    (inputs.SQUARE2D, 48, "pmJ", 5, 2),     # 72 words: LDS shift program, lattice terms
+])
+def test_each_cluster_search_layout_bit_exact(ctx, top, L, kind, K, R):
+    # every layout the cluster search uses (register words, two words per lane,
+    # LDS shift program) against the oracle, with cold temperatures so that
+    # clusters are large
+    rng = inputs.make_rng(76, L * 10 + top)
+    J = inputs.make_couplings(kind, top, L, rng)
+    sc = 3 if kind == "int3" else 1
+    temps = inputs.geometric_temps(0.2, 1.0, K)
+    h, o = make_pair(ctx, top, L, J, temps, R, K, icm.FLAG_2A | icm.FLAG_PT, key=13, j_scale=sc)
+    ctx.icm_init_states(h)
+    o.init_hot()
+    run_both(ctx, h, o, [1, 12], f"layout top={top} L={L}")
+    ctx.icm_remove_instance(h)
+
+
 def test_batched_per_instance_and_graph_agree(ctx):
     rng = inputs.make_rng(73, 0)
     specs = [(inputs.SQUARE2D, 8, "pmJ", 1, 16, 2), (inputs.CUBIC3D, 4, "gauss", 1, 10, 4),
