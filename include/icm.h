@@ -80,6 +80,10 @@ extern "C" {
 #define ICM_FLAG_PT 2            /* step 3 (parallel tempering) */
 #define ICM_FLAG_RECORD_LABELS 4 /* keep the labels of the last ICM move (parity/debug) */
 #define ICM_FLAG_SKIP_METRO 8    /* diagnostic: a step is ICM (+PT) only */
+#define ICM_FLAG_MEASURE 16      /* accumulate the observables after every step
+                                    (icm_read_observables) */
+#define ICM_OBS_BINS 32
+#define ICM_OBS_FIELDS 3
 
 typedef struct icm_ctx icm_ctx;
 
@@ -178,6 +182,20 @@ int icm_read_overlaps(icm_ctx* ctx, int32_t handle, int32_t* q_sum, int32_t* ql_
 int icm_read_labels(icm_ctx* ctx, int32_t handle, int32_t k, int32_t pair, int32_t* labels,
                     int32_t* seed, int32_t* n_minus, size_t cap);
 int icm_read_stats(icm_ctx* ctx, int32_t handle, icm_stats* out);
+/* Observables of the paper's "Benchmark model and observables" paragraph (the
+   energy, the link overlap q_l of Eq. 1 and the spin overlap), for the two
+   replicas of each ICM pair (chains 2p, 2p+1) at each temperature k, summed
+   over the steps since the last icm_init_states / icm_set_states in
+   logarithmic time bins: a step that ends at sweep count t (t = 1, 2, ...)
+   lands in bin floor(log2 t).  Requires ICM_FLAG_MEASURE.
+   sums [ICM_OBS_BINS][K][R/2][ICM_OBS_FIELDS], int64:
+     0: E_a + E_b in raw energy units (see icm_read_energies),
+     1: sum over bonds of q_i q_j = N_b q_l (q_i = s_a,i s_b,i),
+     2: (sum_i q_i)^2;
+   counts [ICM_OBS_BINS]: steps per bin.  E(q_l) = -(J^2/T)(N_b/N)(1 - q_l)
+   and Delta = <E(q_l)> - <H/N> (Eq. 2) follow from the bin means.
+   cap = capacity of sums in elements; ICM_E_BUFSIZE if too small. */
+int icm_read_observables(icm_ctx* ctx, int32_t handle, int64_t* sums, int64_t* counts, size_t cap);
 /* Walker index at (k, r), [K][R] (PT permutation). */
 int icm_read_walkers(icm_ctx* ctx, int32_t handle, int32_t* out, size_t cap);
 uint32_t icm_sweep_index(icm_ctx* ctx, int32_t handle);

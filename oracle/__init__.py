@@ -15,7 +15,8 @@ _lib = None
 
 SQUARE2D, CUBIC3D, CHIMERA, EXPLICIT = 0, 1, 2, 3
 J_INT8, J_F32 = 0, 1
-FLAG_2A, FLAG_PT, FLAG_SKIP_METRO = 1, 2, 8
+FLAG_2A, FLAG_PT, FLAG_SKIP_METRO, FLAG_MEASURE = 1, 2, 8, 16
+OBS_BINS, OBS_FIELDS = 32, 3
 
 
 class _Params(ctypes.Structure):
@@ -76,6 +77,7 @@ def _load():
     lib.orc_energy.argtypes = [P, P]
     lib.orc_energy.restype = I64
     lib.orc_bonds.argtypes = [P, P, P]
+    lib.orc_get_observables.argtypes = [P, P, P]
     lib.orc_metro_accept_count.argtypes = [P, I32, I64]
     lib.orc_metro_accept_count.restype = ctypes.c_uint64
     _lib = lib
@@ -183,6 +185,14 @@ class Sim:
         st = Stats()
         self._lib.orc_get_stats(self._h, ctypes.byref(st))
         return st.as_dict()
+
+    def observables(self):
+        """(sums [32][K][R/2][3], counts [32]): per logarithmic time bin and pair
+        of chains, E_a + E_b (raw), N_b q_l, q^2 summed over the steps in the bin."""
+        sums = np.zeros((OBS_BINS, self.K, self.R // 2, OBS_FIELDS), dtype=np.int64)
+        counts = np.zeros(OBS_BINS, dtype=np.int64)
+        self._lib.orc_get_observables(self._h, _ptr(sums), _ptr(counts))
+        return sums, counts
 
     def labels(self, k, p):
         lab = np.zeros(self.N, dtype=np.int32)

@@ -68,6 +68,8 @@ struct orc_sim {
   uint32_t sweep = 0;
   orc_stats stats{};
   std::vector<std::vector<int32_t>> last_labels;  // [Kc*R/2][N]
+  std::vector<int64_t> obs;                // [32][K][R/2][3] observable sums
+  std::vector<int64_t> obs_count;          // [32] samples per time bin
   std::vector<int32_t> last_seed, last_nminus;
 };
 
@@ -375,6 +377,8 @@ void orc_init_hot(orc_sim* s) {
     s->energy[w] = energy_of(s, &s->spin[(size_t)w * s->N]);
   }
   s->sweep = 0;
+  s->obs.clear();
+  s->obs_count.clear();
 }
 
 void orc_set_states(orc_sim* s, const int8_t* spins, uint32_t sweep0) {
@@ -385,6 +389,39 @@ void orc_set_states(orc_sim* s, const int8_t* spins, uint32_t sweep0) {
     s->energy[w] = energy_of(s, &s->spin[(size_t)w * s->N]);
   }
   s->sweep = sweep0;
+  s->obs.clear();
+  s->obs_count.clear();
+}
+
+// Observables of the "Benchmark model and observables" paragraph, for the two
+// replicas (chains 2p, 2p+1) at each temperature after a step: the energies,
+// the link overlap's numerator sum_bonds s_a,i s_a,j s_b,i s_b,j (q_l times
+// N_b) and the squared spin overlap, summed per logarithmic time bin.  E(q_l)
+// of Eq. 1 and Delta of Eq. 2 follow from these sums and the bin counts.
+void measure(orc_sim* s, uint32_t t_after) {
+  if (s->obs.empty()) {
+    s->obs.assign((size_t)ORC_OBS_BINS * s->K * (s->R / 2) * ORC_OBS_FIELDS, 0);
+    s->obs_count.assign(ORC_OBS_BINS, 0);
+  }
+  int bin = 0;
+  while ((t_after >> (bin + 1)) != 0) ++bin;
+  s->obs_count[bin] += 1;
+  std::vector<int> q(s->N);
+  for (int k = 0; k < s->K; ++k)
+    for (int p = 0; p < s->R / 2; ++p) {
+      const int a = s->walker_at[k * s->R + 2 * p], b = s->walker_at[k * s->R + 2 * p + 1];
+      int64_t qsum = 0;
+      for (int i = 0; i < s->N; ++i) {
+        q[i] = s->spin[(size_t)a * s->N + i] * s->spin[(size_t)b * s->N + i];
+        qsum += q[i];
+      }
+      int64_t link = 0;
+      for (const Bond& e : s->bonds) link += q[e.i] * q[e.j];
+      int64_t* o = &s->obs[(((size_t)bin * s->K + k) * (s->R / 2) + p) * ORC_OBS_FIELDS];
+      o[0] += s->energy[a] + s->energy[b];
+      o[1] += link;
+      o[2] += qsum * qsum;
+    }
 }
 
 void orc_run(orc_sim* s, uint32_t n_sweeps) {
@@ -395,6 +432,7 @@ void orc_run(orc_sim* s, uint32_t n_sweeps) {
       for (int p = 0; p < s->R / 2; ++p) icm_move(s, k, p, t);
     if (s->p.flags & ORC_FLAG_PT) pt_step(s, t);       // step 3
     s->sweep = t + 1;
+    if (s->p.flags & ORC_FLAG_MEASURE) measure(s, t + 1);
   }
 }
 
@@ -442,6 +480,12 @@ void orc_bonds(const orc_sim* s, int32_t* ij, int64_t* raw) {
   for (size_t b = 0; b < s->bonds.size(); ++b) {
     ij[2 * b] = s->bonds[b].i; ij[2 * b + 1] = s->bonds[b].j; raw[b] = s->bonds[b].raw;
   }
+}
+
+void orc_get_observables(const orc_sim* s, int64_t* sums, int64_t* counts) {
+  const size_t n = (size_t)ORC_OBS_BINS * s->K * (s->R / 2) * ORC_OBS_FIELDS;
+  for (size_t x = 0; x < n; ++x) sums[x] = s->obs.empty() ? 0 : s->obs[x];
+  for (int b = 0; b < ORC_OBS_BINS; ++b) counts[b] = s->obs_count.empty() ? 0 : s->obs_count[b];
 }
 
 uint64_t orc_metro_accept_count(const orc_sim* s, int32_t k, int64_t dE) {

@@ -28,8 +28,12 @@ extern "C" {
 
 enum { ORC_SQUARE2D = 0, ORC_CUBIC3D = 1, ORC_CHIMERA = 2, ORC_EXPLICIT = 3 };
 enum { ORC_J_INT8 = 0, ORC_J_F32 = 1 };
-/* ORC_FLAG_SKIP_METRO: diagnostic mode, a step is ICM (+PT) only. */
-enum { ORC_FLAG_2A = 1, ORC_FLAG_PT = 2, ORC_FLAG_SKIP_METRO = 8 };
+/* ORC_FLAG_SKIP_METRO: diagnostic mode, a step is ICM (+PT) only.
+   ORC_FLAG_MEASURE: after every step, accumulate the observables of the
+   "Benchmark model and observables" paragraph per temperature and replica
+   pair into logarithmic time bins (orc_get_observables). */
+enum { ORC_FLAG_2A = 1, ORC_FLAG_PT = 2, ORC_FLAG_SKIP_METRO = 8, ORC_FLAG_MEASURE = 16 };
+enum { ORC_OBS_BINS = 32, ORC_OBS_FIELDS = 3 };
 
 typedef struct {
   int32_t topology;    /* ORC_SQUARE2D / ORC_CUBIC3D / ORC_CHIMERA / ORC_EXPLICIT */
@@ -107,6 +111,13 @@ int64_t orc_energy(const orc_sim* s, const int8_t* spins);
 /* The coupling of each bond as the oracle stores it, raw units, [n_bonds],
    with the endpoints in bonds_ij [n_bonds][2]. */
 void orc_bonds(const orc_sim* s, int32_t* bonds_ij, int64_t* j_raw);
+/* Observable sums [ORC_OBS_BINS][K][R/2][ORC_OBS_FIELDS] and sample counts
+   [ORC_OBS_BINS], accumulated since the last orc_init_hot / orc_set_states.  A step that ends at sweep count t (t = 1, 2, ...) lands in
+   bin floor(log2 t).  Fields per pair of chains (2p, 2p+1) at temperature k:
+   0: E_a + E_b (raw energy units), 1: sum over bonds of q_i q_j = N_b - 2 D
+   (D = bonds whose ends have different site overlaps q_i = s_a,i s_b,i),
+   2: (sum_i q_i)^2. */
+void orc_get_observables(const orc_sim* s, int64_t* sums, int64_t* counts);
 
 /* Metropolis acceptance as a 2^-32 fraction for a raw energy change dE
    at temperature index k: returns the number of u in [0, 2^32) accepted. */

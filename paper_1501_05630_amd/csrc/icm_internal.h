@@ -47,13 +47,15 @@ struct UnitDesc {
   unsigned long long* stats;// [kNumStats]
   int32_t* labels;          // [Kc][R/2][N] (RECORD_LABELS only)
   int32_t* seeds;           // [Kc][R/2] seed site, then [Kc][R/2] n_minus
+  int64_t* obs;             // MEASURE only: [32][K][R/2][3] observable sums, then [32] counts
   uint32_t* sweep;          // sweep counter t
   int32_t N, Nc, deg, W, Wq, K, R, Kc, HM, ptlen, jkind, jscale;
   uint32_t flags, seed, key;
   int32_t topo, L, pad0;    // lattice kind (ICM_TOPO_*) and side / cells per side
 };
 
-constexpr uint32_t kFlag2a = 1, kFlagPt = 2, kFlagRecord = 4, kFlagSkipMetro = 8;
+constexpr uint32_t kFlag2a = 1, kFlagPt = 2, kFlagRecord = 4, kFlagSkipMetro = 8, kFlagMeasure = 16;
+constexpr int kObsBins = 32, kObsFields = 3;
 
 ICM_HD uint32_t align16(uint32_t x) { return (x + 15u) & ~15u; }
 
@@ -62,7 +64,7 @@ ICM_HD uint32_t align16(uint32_t x) { return (x + 15u) & ~15u; }
 // bit set = spin down.
 struct LdsLayout {
   uint32_t sp, nbr, clist, coup, tau, at, gauge, energy, thr, beta, bl2e, ptu, icmu, terms, slots,
-      parent, stats, total;
+      parent, meas, stats, total;
 };
 
 // Neighbour relation of the lattice as bit shifts of a site bitset (for the
@@ -93,7 +95,9 @@ ICM_HD int bit_words(int Wq) { return (4 * Wq + 31) / 32; }
 // tables = 1: neighbour table, colour lists and couplings are copied into LDS;
 // tables = 0: they are read from global memory (for units too large otherwise).
 ICM_HD LdsLayout lds_layout(int N, int deg, int Wq, int K, int R, int HM, int jkind, int slots,
-                            int tables, int record, int Kc) {
+                            int tables, int extras, int Kc) {
+  // extras: bit 0 = ICM labels recorded, bit 1 = observables measured
+  const int record = extras & 1, measure = extras & 2;
   LdsLayout L{};
   uint32_t o = 0;
   const int Wp = 4 * Wq;
@@ -115,6 +119,7 @@ ICM_HD LdsLayout lds_layout(int N, int deg, int Wq, int K, int R, int HM, int jk
   L.terms = o;   o = align16(o + (Kc > 0 ? 4u * kMaxTerms * (1 + site_words(N)) : 0u));
   L.slots = o;   o = align16(o + 4u * slot_words(N) * ns);
   L.parent = o;  o = align16(o + (record ? 4u * N * ns : 0u));
+  L.meas = o;    o = align16(o + (measure ? 4u * site_words(N) * 16u : 0u));  // q-mask words per wave
   L.stats = o;   o = align16(o + 8u * kNumStats);
   L.total = o;
   return L;

@@ -496,6 +496,79 @@ __device__ __noinline__ typename EnergyT<JK>::T pair_boundary(bool sq64, uint32_
 }
 
 // ----------------------------------------------------------------------------
+// Observables after a step (only with the measure flag; out of line so that it
+// costs the fused kernel no registers).  For the two replicas (chains 2p,
+// 2p+1) at each temperature: the energies, the link-overlap sum over bonds of
+// q_i q_j (N_b q_l) and (sum_i q_i)^2, added to the time bin floor(log2 t) of
+// the step's end t.  One wave per pair: ballots give the q-mask words, each
+// lane counts the bonds of its sites whose ends differ (D; sum q_i q_j =
+// N_b - 2 D).  The stored replica b may be reversed (gauge bit): that flips
+// every q_i and leaves all three quantities unchanged.  LDS regions come as
+// byte offsets into the dynamic LDS array.
+// ----------------------------------------------------------------------------
+template <int JK, int DEG>
+__device__ __noinline__ void measure_step(uint32_t t_end, int N, int K, int R, int topo, int L, uint32_t sp_off,
+                                          uint32_t at_off, uint32_t energy_off, uint32_t meas_off,
+                                          uint32_t nbr_off, const uint16_t* nbr_global, int64_t* obs) {
+  using E_t = typename EnergyT<JK>::T;
+  t_end = (uint32_t)uniform((int)t_end);
+  N = uniform(N); K = uniform(K); R = uniform(R); topo = uniform(topo); L = uniform(L);
+  const uint32_t* sp = (const uint32_t*)(lds + uniform((int)sp_off));
+  const int* at = (const int*)(lds + uniform((int)at_off));
+  const E_t* energy = (const E_t*)(lds + uniform((int)energy_off));
+  const uint16_t* nbr = nbr_global ? nbr_global : (const uint16_t*)(lds + uniform((int)nbr_off));
+  const int lane = lane_id(), wave = wave_id(), nwaves = (int)(blockDim.x >> 6);
+  const int half = R >> 1, nw = site_words(N);
+  const int bin = 31 - __builtin_clz(t_end);
+  const int nbonds = topo == 2 ? 16 * L * L + 8 * L * (L - 1) : N * (DEG / 2);
+  uint32_t* qw = (uint32_t*)(lds + uniform((int)meas_off)) + wave * nw;
+  for (int x = wave; x < K * half; x += nwaves) {
+    const int k = x / half, p = x - k * half;
+    const int a = at[k * R + 2 * p], b = at[k * R + 2 * p + 1];
+    const uint32_t* rowa = sp + (a >> 5) * N;
+    const uint32_t* rowb = sp + (b >> 5) * N;
+    const int pa = a & 31, pb = b & 31;
+    int n = 0;
+    for (int s2 = 0; s2 * 64 < N; ++s2) {
+      const int i = s2 * 64 + lane;
+      const uint32_t qb = i < N ? (bit_of(rowa[i], pa) ^ bit_of(rowb[i], pb)) : 0u;
+      const unsigned long long bal = __ballot(qb);
+      n += __popcll(bal);
+      if (lane == 0) {
+        qw[2 * s2] = (uint32_t)bal;
+        if (2 * s2 + 1 < nw) qw[2 * s2 + 1] = (uint32_t)(bal >> 32);
+      }
+    }
+    n = uniform(n);
+    wave_sync();
+    int diff = 0;
+    for (int i = lane; i < N; i += 64) {
+      const uint32_t qi = (qw[i >> 5] >> (i & 31)) & 1u;
+#pragma unroll
+      for (int d = 0; d < DEG; ++d) {
+        const int j = nbr[i * DEG + d];
+        // each bond once: lattices from the +axis slots; chimera in-cell bonds
+        // from u < 4, inter-cell bonds from the "next" slot if present
+        const bool bond = topo == 2 ? (((i & 7) < 4 && d < 4) || (d == 5 && j != i)) : (d & 1) == 0;
+        if (bond) diff += (int)(qi ^ ((qw[j >> 5] >> (j & 31)) & 1u));
+      }
+    }
+    const int D = wave_sum(diff);
+    if (lane == 0) {
+      int64_t* o = obs + (((size_t)bin * K + k) * half + p) * kObsFields;
+      const int64_t ea = JK ? (int64_t)((double)energy[a] * 0x1p32) : (int64_t)energy[a];
+      const int64_t eb = JK ? (int64_t)((double)energy[b] * 0x1p32) : (int64_t)energy[b];
+      const int64_t q = (int64_t)N - 2 * n;
+      o[0] += ea + eb;
+      o[1] += (int64_t)nbonds - 2 * D;
+      o[2] += q * q;
+    }
+    wave_sync();
+  }
+  if (threadIdx.x == 0) obs[(size_t)kObsBins * K * half * kObsFields + bin] += 1;
+}
+
+// ----------------------------------------------------------------------------
 // The fused sweep-block kernel.  JK: 0 = int8 couplings, 1 = float couplings.
 // DEG: neighbour slots (4 for square2d, 6 otherwise).  One workgroup runs one
 // unit; its spins live bit-packed in LDS for the whole block of sweeps.
@@ -509,7 +582,7 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
   const int N = U.N, Nc = U.Nc, W = U.W, Wq = U.Wq, K = U.K, R = U.R, Kc = U.Kc, HM = U.HM;
   const int Wp = 4 * Wq, G = bit_words(Wq);
   const LdsLayout lay = lds_layout(N, DEG, Wq, K, R, HM, JK, icm_slots, TL,
-                                   (U.flags & kFlagRecord) ? 1 : 0, Kc);
+                                   ((U.flags & kFlagRecord) ? 1 : 0) | ((U.flags & kFlagMeasure) ? 2 : 0), Kc);
 
   uint32_t* sp = (uint32_t*)(lds + lay.sp);
   // TL: tables in LDS; otherwise read-only global memory (cached in L1/L2)
@@ -1229,6 +1302,15 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
           stats[kStatPtAccepts] += (unsigned long long)tot;
         }
       }
+      __syncthreads();
+    }
+
+    // ---------------- observables (out of line, only when measured) ---------------
+    if (flags & kFlagMeasure) {
+      measure_step<JK, DEG>(t + 1u, N, K, R, U.topo, U.L, (uint32_t)((unsigned char*)sp - lds),
+                            (uint32_t)((unsigned char*)at - lds), (uint32_t)((unsigned char*)energy - lds),
+                            lay.meas, TL ? (uint32_t)((const unsigned char*)nbr - lds) : 0u,
+                            TL ? nullptr : U.nbr, U.obs);
       __syncthreads();
     }
   }

@@ -222,12 +222,15 @@ struct Instance {
   uint32_t flags = 0, key = 0;
   std::vector<double> temps;
   uint32_t sweep_host = 0;
+  size_t obs_words = 0;              // observable sums + counts (MEASURE)
+  std::vector<int64_t> obs_zero;     // host source for clearing them
   // device regions
   std::vector<void*> blocks;  // everything this instance owns in the arena
   UnitDesc unit{};
   size_t lds_bytes_at(int slots, int tables) const {
     return icm::lds_layout(N, deg, Wq, K, R, HM, jkind, slots, tables,
-                           (flags & ICM_FLAG_RECORD_LABELS) ? 1 : 0, Kc).total;
+                           ((flags & ICM_FLAG_RECORD_LABELS) ? 1 : 0) | ((flags & ICM_FLAG_MEASURE) ? 2 : 0),
+                           Kc).total;
   }
 };
 
@@ -346,7 +349,7 @@ int validate_desc(const icm_instance_desc* d, std::string& why) {
   }
   if (d->n_replicas < 2 || (d->n_replicas & 1) || d->n_replicas > icm::kMaxReplicas) { why = "n_replicas must be even, 2..64"; return ICM_E_INVALID; }
   if (d->icm_ntemps < 0 || d->icm_ntemps > d->n_temps) { why = "icm_ntemps out of range"; return ICM_E_INVALID; }
-  if (d->flags & ~15u) { why = "unknown flags"; return ICM_E_INVALID; }
+  if (d->flags & ~31u) { why = "unknown flags"; return ICM_E_INVALID; }
   const int nc = coupling_count(d->topology, d->L);
   if (d->jkind == ICM_J_F32) {
     const float* J = (const float*)d->couplings;
@@ -401,7 +404,7 @@ Topology* get_topology(icm_ctx* c, int topo, int L, int& rc) {
 }
 
 struct Sizes {
-  size_t spins, coup, thr, ptthr, beta, bl2e, tau, at, gauge, energy, stats, labels, seeds, sweep;
+  size_t spins, coup, thr, ptthr, beta, bl2e, tau, at, gauge, energy, stats, labels, seeds, sweep, obs;
   int HM, ptlen;
 };
 
@@ -469,6 +472,9 @@ int plan_instance(const icm_instance_desc* d, const Topology& T, Sizes& S,
   S.labels = (d->flags & ICM_FLAG_RECORD_LABELS) ? (size_t)slots * N * 4 : 0;
   S.seeds = (d->flags & ICM_FLAG_RECORD_LABELS) ? (size_t)slots * 2 * 4 : 0;
   S.sweep = 4;
+  S.obs = (d->flags & ICM_FLAG_MEASURE)
+              ? ((size_t)icm::kObsBins * K * (R / 2) * icm::kObsFields + icm::kObsBins) * 8
+              : 0;
   (void)W;
   return ICM_OK;
 }
@@ -476,7 +482,7 @@ int plan_instance(const icm_instance_desc* d, const Topology& T, Sizes& S,
 size_t total_bytes(const Sizes& S) {
   size_t t = 0;
   for (size_t b : {S.spins, S.coup, S.thr, S.ptthr, S.beta, S.bl2e, S.tau, S.at, S.gauge, S.energy,
-                   S.stats, S.labels, S.seeds, S.sweep})
+                   S.stats, S.labels, S.seeds, S.sweep, S.obs})
     t += (std::max(b, size_t(1)) + 255) & ~size_t(255);
   return t;
 }
@@ -498,6 +504,11 @@ int reset_walkers(icm_ctx* c, Instance* in, uint32_t sweep0) {
   HIP_OK(c, hipMemcpyAsync(in->unit.gauge, gauge.data(), gauge.size(), hipMemcpyHostToDevice, c->stream));
   HIP_OK(c, hipMemcpyAsync(in->unit.stats, stats.data(), stats.size() * 8, hipMemcpyHostToDevice, c->stream));
   HIP_OK(c, hipMemcpyAsync(in->unit.sweep, &sweep0, 4, hipMemcpyHostToDevice, c->stream));
+  if (in->flags & ICM_FLAG_MEASURE) {
+    in->obs_zero.assign(in->obs_words, 0);
+    HIP_OK(c, hipMemcpyAsync(in->unit.obs, in->obs_zero.data(), in->obs_words * 8, hipMemcpyHostToDevice,
+                             c->stream));
+  }
   HIP_OK(c, hipStreamSynchronize(c->stream));
   in->sweep_host = sweep0;
   return ICM_OK;
@@ -550,7 +561,9 @@ int add_instance_impl(icm_ctx* c, const icm_instance_desc* d, int32_t* out) {
   U.labels = (int32_t*)grab(S.labels);
   U.seeds = (int32_t*)grab(S.seeds);
   U.sweep = (uint32_t*)grab(S.sweep);
-  if (in->blocks.size() != 14) {
+  U.obs = (int64_t*)grab(S.obs);
+  in->obs_words = S.obs / 8;
+  if (in->blocks.size() != 15) {
     T->refs++;
     release_instance(c, in.get());
     return fail(c, ICM_E_NOMEM, "arena full: instance needs %zu bytes", total_bytes(S));
@@ -1122,6 +1135,22 @@ int icm_read_labels(icm_ctx* c, int32_t h, int32_t k, int32_t pair, int32_t* lab
   HIP_OK(c, hipMemcpy(&sv[1], in->unit.seeds + nmoves + mv, 4, hipMemcpyDeviceToHost));
   if (seed) *seed = sv[0];
   if (n_minus) *n_minus = sv[1];
+  return ICM_OK;
+}
+
+int icm_read_observables(icm_ctx* c, int32_t h, int64_t* sums, int64_t* counts, size_t cap) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  Instance* in = find(c, h);
+  if (!in) return fail(c, ICM_E_NOTFOUND, "unknown handle %d", h);
+  if (!(in->flags & ICM_FLAG_MEASURE)) return fail(c, ICM_E_INVALID, "instance does not measure observables");
+  const size_t n = in->obs_words - icm::kObsBins;
+  if (cap < n) return fail(c, ICM_E_BUFSIZE, "observables need %zu elements", n);
+  std::vector<int64_t> all(in->obs_words);
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  HIP_OK(c, hipMemcpy(all.data(), in->unit.obs, in->obs_words * 8, hipMemcpyDeviceToHost));
+  if (sums) std::memcpy(sums, all.data(), n * 8);
+  if (counts) std::memcpy(counts, all.data() + n, icm::kObsBins * 8);
   return ICM_OK;
 }
 

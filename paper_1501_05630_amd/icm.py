@@ -17,7 +17,8 @@ ICM_OK, ICM_E_INVALID, ICM_E_NOMEM, ICM_E_DEVICE = 0, -1, -2, -3
 ICM_E_NOTFOUND, ICM_E_BUSY, ICM_E_BUFSIZE = -4, -5, -6
 TOPO_SQUARE2D, TOPO_CUBIC3D, TOPO_CHIMERA = 0, 1, 2
 J_INT8, J_F32 = 0, 1
-FLAG_2A, FLAG_PT, FLAG_RECORD_LABELS, FLAG_SKIP_METRO = 1, 2, 4, 8
+FLAG_2A, FLAG_PT, FLAG_RECORD_LABELS, FLAG_SKIP_METRO, FLAG_MEASURE = 1, 2, 4, 8, 16
+OBS_BINS, OBS_FIELDS = 32, 3
 
 _P = ctypes.c_void_p
 _I32, _U32, _U64, _SZ = ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_size_t
@@ -61,6 +62,7 @@ EXPORTS = {
     "icm_read_overlaps": (ctypes.c_int, [_P, _I32, _P, _P, _SZ]),
     "icm_read_labels": (ctypes.c_int, [_P, _I32, _I32, _I32, _P, _P, _P, _SZ]),
     "icm_read_stats": (ctypes.c_int, [_P, _I32, ctypes.POINTER(Stats)]),
+    "icm_read_observables": (ctypes.c_int, [_P, _I32, _P, _P, _SZ]),
     "icm_read_walkers": (ctypes.c_int, [_P, _I32, _P, _SZ]),
     "icm_sweep_index": (_U32, [_P, _I32]),
     "icm_serve_start": (ctypes.c_int, [_P, _I32]),
@@ -248,6 +250,15 @@ class Context:
         st = Stats()
         _check(self.h, self._lib.icm_read_stats(self.h, h, ctypes.byref(st)), "icm_read_stats")
         return st.as_dict()
+
+    def icm_read_observables(self, h):
+        """(sums [32][K][R/2][3] int64, counts [32] int64); see icm_read_observables."""
+        m = self.meta[h]
+        sums = np.zeros((OBS_BINS, m["K"], m["R"] // 2, OBS_FIELDS), dtype=np.int64)
+        counts = np.zeros(OBS_BINS, dtype=np.int64)
+        _check(self.h, self._lib.icm_read_observables(self.h, h, _ptr(sums), _ptr(counts), sums.size),
+               "icm_read_observables")
+        return sums, counts
 
     def icm_sweep_index(self, h):
         return int(self._lib.icm_sweep_index(self.h, h))

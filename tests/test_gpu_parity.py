@@ -327,3 +327,55 @@ def test_full_size_uneven_3d_batch_sampled():
                    [0, 256 + 5, 512 + 77, 768 + 130, 1024 + 201, 1280 + 255], threads=256)
     finally:
         c.close()
+
+
+@pytest.mark.parametrize("top,L,kind,K,R", [
+    (inputs.SQUARE2D, 8, "pmJ", 6, 2),
+    (inputs.CUBIC3D, 8, "gauss", 5, 4),
+    (inputs.CHIMERA, 12, "int3", 6, 2),
+    (inputs.CUBIC3D, 6, "gauss", 4, 6),
+    (inputs.SQUARE2D, 64, "pmJ", 3, 2),
+])
+def test_observables_bit_exact(ctx, top, L, kind, K, R):
+    # energies, link overlap and spin overlap per logarithmic time bin, summed
+    # on the device after every step, equal the oracle's sums
+    rng = inputs.make_rng(77, L * 10 + top)
+    J = inputs.make_couplings(kind, top, L, rng)
+    sc = 3 if kind == "int3" else 1
+    temps = inputs.geometric_temps(0.3, 1.8, K)
+    flags = icm.FLAG_2A | icm.FLAG_PT | icm.FLAG_MEASURE
+    h = ctx.icm_add_instance(top, L, J, temps, R, inputs.icm_cutoff(temps), flags=flags, instance_key=21,
+                             j_scale=sc)
+    o = orc.Sim(top, L, J, temps, R, inputs.icm_cutoff(temps), flags=orc.FLAG_2A | orc.FLAG_PT | orc.FLAG_MEASURE,
+                seed=SEED, instance_key=21, j_scale=sc)
+    ctx.icm_init_states(h)
+    o.init_hot()
+    for n in (1, 6, 40, 90):
+        ctx.icm_run([h], n)
+        o.run(n)
+        ctx.icm_sync()
+        gs, gc = ctx.icm_read_observables(h)
+        os_, oc = o.observables()
+        assert np.array_equal(gc, oc), (n, gc[:8], oc[:8])
+        assert np.array_equal(gs, os_), (n, np.argwhere(gs != os_)[:4].tolist())
+    assert_same(ctx, h, o, "with observables")
+    ctx.icm_remove_instance(h)
+
+
+def test_observables_reset_by_set_states_and_absent_without_flag(ctx):
+    J = inputs.pm_j_couplings(inputs.SQUARE2D, 8, inputs.make_rng(78, 0))
+    temps = inputs.geometric_temps(0.4, 1.4, 3)
+    h = ctx.icm_add_instance(inputs.SQUARE2D, 8, J, temps, 2, 2, flags=icm.FLAG_MEASURE | icm.FLAG_PT)
+    ctx.icm_init_states(h)
+    ctx.icm_run([h], 20)
+    st = ctx.icm_read_states(h)
+    ctx.icm_set_states(h, st, sweep0=100)
+    ctx.icm_run([h], 3)
+    ctx.icm_sync()
+    _, counts = ctx.icm_read_observables(h)
+    assert counts.sum() == 3 and counts[6] == 3           # t = 101..103 -> bin 6
+    ctx.icm_remove_instance(h)
+    h2 = ctx.icm_add_instance(inputs.SQUARE2D, 8, J, temps, 2, 2, flags=icm.FLAG_PT)
+    with pytest.raises(icm.IcmError):
+        ctx.icm_read_observables(h2)
+    ctx.icm_remove_instance(h2)

@@ -1,0 +1,128 @@
+"""Pins of the oracle's observables (link overlap, spin overlap, energies per
+logarithmic time bin; "Benchmark model and observables" paragraph, Eq. 1-2).
+
+- frozen states (no Metropolis, ICM or PT): every sample equals a closed form
+  (identical or reversed replicas give N_b and N^2; one differing site gives
+  N_b - 2 deg(i) and (N - 2)^2; random replicas the bond sum over an
+  independently built bond list); bin counts are the sizes of [2^b, 2^(b+1));
+- the thermal link overlap and squared overlap of two independent replicas
+  equal the exact enumeration values (1/N_b) sum_bonds <s_i s_j>^2 and
+  sum_ij <s_i s_j>^2 within 4 standard errors;
+- Eq. 1 read with H = -sum J s s: for Gaussian disorder the exact
+  disorder-averaged Delta of Eq. 2 vanishes within its sampling error.
+"""
+import numpy as np
+import pytest
+
+import oracle as orc
+from paper_1501_05630_amd import inputs
+
+import exact
+
+
+def make(top, L, J, temps, R, Kc, flags, scale=1, key=0):
+    return orc.Sim(top, L, J, temps, R, Kc, flags=flags, seed=7, instance_key=key, j_scale=scale)
+
+
+def bin_counts(t0, n):
+    c = np.zeros(orc.OBS_BINS, dtype=np.int64)
+    for t in range(t0 + 1, t0 + n + 1):
+        c[int(np.floor(np.log2(t)))] += 1
+    return c
+
+
+@pytest.mark.parametrize("top,L,kind,scale", [(inputs.SQUARE2D, 4, "pmJ", 1), (inputs.CUBIC3D, 2, "pmJ", 1),
+                                              (inputs.CHIMERA, 2, "int3", 3)])
+def test_frozen_states_give_closed_forms(top, L, kind, scale):
+    rng = inputs.make_rng(90, L * 10 + top)
+    J = inputs.make_couplings(kind, top, L, rng)
+    temps = inputs.geometric_temps(0.5, 1.5, 2)
+    s = make(top, L, J, temps, 4, 0, orc.FLAG_SKIP_METRO | orc.FLAG_MEASURE, scale)
+    N = s.N
+    bonds = exact.bond_list(top, L, np.asarray(J, np.float64))
+    Nb = len(bonds)
+    a = np.where(rng.random(N) < 0.5, 1, -1).astype(np.int8)
+    i0 = 3
+    one = a.copy()
+    one[i0] = -one[i0]
+    rnd = np.where(rng.random(N) < 0.5, 1, -1).astype(np.int8)
+    st = np.zeros((2, 4, N), dtype=np.int8)
+    st[0, 0], st[0, 1] = a, a            # identical
+    st[0, 2], st[0, 3] = a, -a           # reversed
+    st[1, 0], st[1, 1] = a, one          # one site differs
+    st[1, 2], st[1, 3] = a, rnd          # independent
+    t0, n = 5, 40
+    s.set_states(st, sweep0=t0)
+    s.run(n)
+    sums, counts = s.observables()
+    assert np.array_equal(counts, bin_counts(t0, n))
+    deg = sum((i == i0) + (j == i0) for i, j, _ in bonds)
+    q_rnd = a.astype(np.int64) * rnd
+    link_rnd = sum(int(q_rnd[i] * q_rnd[j]) for i, j, _ in bonds)
+    expect = {(0, 0): (Nb, N * N), (0, 1): (Nb, N * N), (1, 0): (Nb - 2 * deg, (N - 2) ** 2),
+              (1, 1): (link_rnd, int(q_rnd.sum()) ** 2)}
+    total = counts.sum()
+    for (k, p), (link, q2) in expect.items():
+        assert sums[:, k, p, 1].sum() == link * total, (k, p)
+        assert sums[:, k, p, 2].sum() == q2 * total, (k, p)
+        ea = exact.energy(top, L, np.asarray(J, np.float64) / scale, st[k, 2 * p])
+        eb = exact.energy(top, L, np.asarray(J, np.float64) / scale, st[k, 2 * p + 1])
+        assert sums[:, k, p, 0].sum() == round((ea + eb) * scale) * total, (k, p)
+
+
+def exact_pair_observables(top, L, J, temps):
+    """Exact <H>, <q_l> and <q^2> of two independent replicas by enumeration."""
+    N = inputs.n_sites(top, L)
+    bonds = exact.bond_list(top, L, np.asarray(J, np.float64))
+    S = exact.all_states(N).astype(np.float64)
+    E = exact.all_energies(N, bonds)
+    out = []
+    for T in temps:
+        w = np.exp(-(E - E.min()) / T)
+        w /= w.sum()
+        corr = (S * w[:, None]).T @ S                      # <s_i s_j>
+        ql = np.mean([corr[i, j] ** 2 for i, j, _ in bonds])
+        q2 = float(np.sum(corr ** 2))
+        out.append((float(np.sum(w * E)), ql, q2))
+    return np.array(out), len(bonds), N
+
+
+def test_link_and_spin_overlap_match_exact_enumeration():
+    top, L = inputs.SQUARE2D, 4
+    J = inputs.gaussian_couplings(top, L, inputs.make_rng(91, 0))
+    temps = inputs.geometric_temps(0.7, 1.6, 4)
+    ref, Nb, N = exact_pair_observables(top, L, J, temps)
+    s = make(top, L, J, temps, 2, 4, orc.FLAG_2A | orc.FLAG_PT | orc.FLAG_MEASURE)
+    s.init_hot()
+    s.run(2048)
+    prev, _ = s.observables()
+    blocks = []
+    for _ in range(40):
+        s.run(2048)
+        cur, _ = s.observables()
+        blocks.append((cur - prev).sum(axis=0)[:, 0, :] / 2048.0)   # [K][3] per sample
+        prev = cur
+    b = np.array(blocks)
+    m, se = b.mean(axis=0), b.std(axis=0, ddof=1) / np.sqrt(len(b))
+    ql, q2 = m[:, 1] / Nb, m[:, 2]
+    for k in range(len(temps)):
+        assert abs(ql[k] - ref[k, 1]) < 4 * se[k, 1] / Nb + 1e-9, (k, ql[k], ref[k, 1])
+        assert abs(q2[k] - ref[k, 2]) < 4 * se[k, 2] + 1e-9, (k, q2[k], ref[k, 2])
+        e = m[k, 0] * 2.0 ** -32 / 2        # raw units of the 2^-32 grid, two replicas
+        assert abs(e - ref[k, 0]) < 4 * se[k, 0] * 2.0 ** -32 / 2 + 1e-9, (k, e, ref[k, 0])
+
+
+def test_delta_vanishes_for_gaussian_disorder_exactly_averaged():
+    # Eq. 1 with H = -sum J s s: [<H>]/N = -(1/T)(N_b/N)(1 - [<q_l>]) for
+    # unit-variance Gaussian couplings; Delta of Eq. 2 averaged over instances.
+    top, L = inputs.SQUARE2D, 4
+    temps = [0.8, 1.2]
+    d = []
+    for b in range(64):
+        J = inputs.gaussian_couplings(top, L, inputs.make_rng(92, b))
+        ref, Nb, N = exact_pair_observables(top, L, J, temps)
+        e_ql = -(1.0 / np.array(temps)) * (Nb / N) * (1.0 - ref[:, 1])
+        d.append(e_ql - ref[:, 0] / N)
+    d = np.array(d)
+    mean, se = d.mean(axis=0), d.std(axis=0, ddof=1) / np.sqrt(len(d))
+    assert np.all(np.abs(mean) < 3 * se + 1e-3), (mean, se)
