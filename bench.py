@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--serve-block", type=int, default=256)
     ap.add_argument("--serve-load", type=float, default=0.8)
     ap.add_argument("--arena-mib", type=int, default=1024)
+    ap.add_argument("--thermalization", type=int, default=0,
+                    help="run this many sweeps with and without ICM and report Delta(t) (Eq. 2) instead")
     return ap.parse_args()
 
 
@@ -203,8 +205,64 @@ def run_serving(args):
             "attempts_per_s": attempts / wall, "arena_mib": args.arena_mib}
 
 
+def run_thermalization(args):
+    """Delta(t) of Eq. 2, disorder-averaged per logarithmic time bin, for PT
+    alone and PT + ICM on the same instances, seeds and temperatures."""
+    import numpy as np
+    import torch
+
+    from paper_1501_05630_amd import icm, inputs
+    name = args.workload
+    spec = inputs.WORKLOADS[name]
+    n_inst = spec["n_instances"]
+    out = {"metric": "thermalization: disorder-averaged Delta (Eq. 2) per time bin t in [2^b, 2^(b+1))",
+           "workload": name, "instances": n_inst, "sweeps": args.thermalization}
+    for mode in ("pt", "pt_icm"):
+        ctx = icm.Context(arena_bytes=4 << 30, seed=inputs.MASTER_SEED)
+        ctx.icm_set_run_config(threads=args.threads, sweeps_per_launch=args.sweeps_per_step, use_graph=1,
+                               icm_slots=args.icm_slots)
+        hs, meta = [], []
+        for b in range(n_inst):
+            J, temps, kc, sp = inputs.workload_instance(name, b)
+            hs.append(ctx.icm_add_instance(sp["topology"], sp["L"], J, temps, spec["n_replicas"],
+                                           kc if mode == "pt_icm" else 0,
+                                           flags=icm.FLAG_2A | icm.FLAG_PT | icm.FLAG_MEASURE,
+                                           instance_key=b, j_scale=spec["j_scale"]))
+            ctx.icm_init_states(hs[-1])
+            N = inputs.n_sites(sp["topology"], sp["L"])
+            nb = {inputs.SQUARE2D: 2 * N, inputs.CUBIC3D: 3 * N,
+                  inputs.CHIMERA: 16 * sp["L"] ** 2 + 8 * sp["L"] * (sp["L"] - 1)}[sp["topology"]]
+            meta.append((temps, N, nb))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.icm_run(hs, args.thermalization)
+        ctx.icm_sync()
+        wall = time.perf_counter() - t0
+        unit = 2.0 ** -32 if spec["kind"] == "gauss" else 1.0 / spec["j_scale"]
+        deltas = []
+        for h, (temps, N, nb) in zip(hs, meta):
+            sums, counts = ctx.icm_read_observables(h)
+            deltas.append(icm.delta_per_bin(sums, counts, temps, N, nb, unit)[2])
+        d = np.array(deltas)                                   # [instances][bins][K]
+        nbins = int(np.floor(np.log2(args.thermalization))) + 1
+        mean = d[:, :nbins, :].mean(axis=0)
+        se = d[:, :nbins, :].std(axis=0, ddof=1) / np.sqrt(len(d))
+        out[mode] = {"wall_s": wall, "temps": [float(x) for x in meta[0][0]],
+                     "delta_coldest": [float(x) for x in mean[:, 0]],
+                     "se_coldest": [float(x) for x in se[:, 0]],
+                     "delta_all_temps_last_bin": [float(x) for x in mean[-1]]}
+        ctx.close()
+    return out
+
+
 def main():
     args = parse()
+    if args.thermalization:
+        if args.gpus != 1:
+            print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+            sys.exit(2)
+        print(json.dumps(run_thermalization(args)), flush=True)
+        return
     if args.serve:
         if args.gpus != 1:
             print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))

@@ -294,3 +294,17 @@ class Context:
         _check(self.h, self._lib.icm_take_result(self.h, ticket, _ptr(e), _ptr(s), e.size, s.size),
                "icm_take_result")
         return e, s
+
+
+def delta_per_bin(sums, counts, temps, n_sites, n_bonds, energy_unit):
+    """Eq. 1 and 2 from the observable sums of one instance (icm_read_observables):
+    returns (e_ql, e, delta) arrays [bins][K], averaged over the replica pairs:
+    e_ql = E(q_l) = -(1/T)(N_b/N)(1 - q_l) for unit-variance couplings, e = <H/N>,
+    delta = e_ql - e.  Bins without samples are NaN."""
+    sums = np.asarray(sums, dtype=np.float64)
+    c = np.asarray(counts, dtype=np.float64)[:, None]
+    with np.errstate(invalid="ignore", divide="ignore"):
+        ql = sums[:, :, :, 1].mean(axis=2) / (n_bonds * c)
+        e = sums[:, :, :, 0].mean(axis=2) * energy_unit / (2.0 * n_sites * c)
+        e_ql = -(1.0 / np.asarray(temps, dtype=np.float64))[None, :] * (n_bonds / n_sites) * (1.0 - ql)
+    return e_ql, e, e_ql - e

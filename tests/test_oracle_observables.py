@@ -126,3 +126,28 @@ def test_delta_vanishes_for_gaussian_disorder_exactly_averaged():
     d = np.array(d)
     mean, se = d.mean(axis=0), d.std(axis=0, ddof=1) / np.sqrt(len(d))
     assert np.all(np.abs(mean) < 3 * se + 1e-3), (mean, se)
+
+
+def test_delta_helper_reproduces_eq_1_and_2_from_the_sums():
+    # delta_per_bin (used on the device sums) against a direct evaluation of
+    # E(q_l) and <H/N> from the oracle's per-bin sums on frozen states
+    from paper_1501_05630_amd import icm
+    top, L = inputs.SQUARE2D, 4
+    J = inputs.gaussian_couplings(top, L, inputs.make_rng(93, 0))
+    temps = inputs.geometric_temps(0.6, 1.2, 2)
+    s = make(top, L, J, temps, 2, 0, orc.FLAG_SKIP_METRO | orc.FLAG_MEASURE)
+    s.init_hot()
+    s.run(12)
+    sums, counts = s.observables()
+    e_ql, e, delta = icm.delta_per_bin(sums, counts, temps, s.N, 2 * s.N, 2.0 ** -32)
+    st = s.states()
+    bonds = exact.bond_list(top, L, np.asarray(J, np.float64))
+    for k, T in enumerate(temps):
+        q = st[k, 0].astype(np.int64) * st[k, 1]
+        ql = np.mean([q[i] * q[j] for i, j, _ in bonds])
+        ref_eql = -(1.0 / T) * 2.0 * (1.0 - ql)
+        ref_e = (exact.energy(top, L, J, st[k, 0]) + exact.energy(top, L, J, st[k, 1])) / (2 * s.N)
+        for b in np.flatnonzero(counts):
+            assert abs(e_ql[b, k] - ref_eql) < 1e-12
+            assert abs(e[b, k] - ref_e) < 1e-6
+            assert abs(delta[b, k] - (ref_eql - ref_e)) < 1e-6
