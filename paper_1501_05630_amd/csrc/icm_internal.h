@@ -63,7 +63,7 @@ ICM_HD uint32_t align16(uint32_t x) { return (x + 15u) & ~15u; }
 // Spins are bit-packed in LDS: word (g, i) holds walkers 32g..32g+31 at site i,
 // bit set = spin down.
 struct LdsLayout {
-  uint32_t sp, nbr, clist, coup, tau, at, gauge, energy, thr, beta, bl2e, ptu, icmu, terms, slots,
+  uint32_t sp, nbr, clist, coup, tau, at, gauge, energy, thr, beta, bl2e, dbl2e, ptu, icmu, terms, slots,
       parent, meas, stats, total;
 };
 
@@ -114,6 +114,7 @@ ICM_HD LdsLayout lds_layout(int N, int deg, int Wq, int K, int R, int HM, int jk
   L.thr = o;     o = align16(o + (jkind ? 0u : 4u * K * HM));
   L.beta = o;    o = align16(o + 8u * K);
   L.bl2e = o;    o = align16(o + 4u * K);
+  L.dbl2e = o;   o = align16(o + 4u * K);   // float((beta_k - beta_k+1) log2 e), PT filter
   L.ptu = o;     o = align16(o + 4u * (K > 1 ? K - 1 : 1) * R);
   L.icmu = o;    o = align16(o + 4u * (Kc > 0 ? Kc * (R / 2) : 1));
   L.terms = o;   o = align16(o + (Kc > 0 ? 4u * kMaxTerms * (1 + site_words(N)) : 0u));

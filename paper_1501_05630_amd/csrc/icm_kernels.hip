@@ -597,6 +597,7 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
   uint32_t* thr = (uint32_t*)(lds + lay.thr);
   double* beta = (double*)(lds + lay.beta);
   float* bl2e = (float*)(lds + lay.bl2e);
+  float* dbl2e = (float*)(lds + lay.dbl2e);
   uint32_t* ptu = (uint32_t*)(lds + lay.ptu);
   uint32_t* icmu = (uint32_t*)(lds + lay.icmu);
   unsigned long long* stats = (unsigned long long*)(lds + lay.stats);
@@ -638,7 +639,12 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
     else energy[x] = (E_t)U.energy[x];
   }
   for (int x = tid; x < K * R; x += nthr) at[x] = U.at[x];
-  for (int x = tid; x < K; x += nthr) { beta[x] = U.beta[x]; bl2e[x] = U.bl2e[x]; }
+  for (int x = tid; x < K; x += nthr) {
+    beta[x] = U.beta[x];
+    bl2e[x] = U.bl2e[x];
+    // PT pre-filter factor: the gap of neighbouring betas times log2 e, rounded once
+    dbl2e[x] = x + 1 < K ? (float)((U.beta[x] - U.beta[x + 1]) * 1.4426950408889634) : 0.0f;
+  }
   for (int x = tid; x < kNumStats; x += nthr) stats[x] = 0;
   if (Kc > 0) {
     // shift program of the lattice and zeroed frontier padding of every slot
@@ -683,32 +689,39 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
     if (flags & kFlagSkipMetro) __syncthreads();
     // ---------------- step 1: Metropolis sweep, colour 0 then colour 1 ----------
     if (!(flags & kFlagSkipMetro)) {
+      // A task is one site of one colour for the walkers of QPT Philox quads
+      // (4 QPT walkers in one bit-word): the neighbour words and couplings are
+      // read once for all of them.  Two quads pay off for float couplings (the
+      // per-site part is the larger there), one for integer couplings.
+      constexpr int QPT = JK ? 2 : 1, WPT = 4 * QPT;
+      const int Wqt = (Wq + QPT - 1) / QPT;
       for (int c = 0; c < 2; ++c) {
         const int nchunk = (Nc + 63) >> 6;
-        const int ntasks = Wq * nchunk;
+        const int ntasks = Wqt * nchunk;
         const int tb = (int)(((long long)ntasks * wave) / nwaves);
         const int te = (int)(((long long)ntasks * (wave + 1)) / nwaves);
         int cur_q = -1;
-        E_t acc[4] = {0, 0, 0, 0};
-        int tq[4] = {K, K, K, K};
-        int rowb[4] = {0, 0, 0, 0};
-        double bq[4] = {0, 0, 0, 0};
-        float lq[4] = {0, 0, 0, 0};
-        int q = tb / nchunk, chunk = tb - q * nchunk;
-        for (int task = tb; task < te; ++task, (++chunk == nchunk ? (chunk = 0, ++q) : 0)) {
-          if (q != cur_q) {
+        E_t acc[WPT];
+        int tq[WPT], rowb[WPT];
+        double bq[WPT];
+        float lq[WPT];
+#pragma unroll
+        for (int b = 0; b < WPT; ++b) { acc[b] = 0; tq[b] = K; rowb[b] = 0; bq[b] = 0.0; lq[b] = 0.0f; }
+        int qt = tb / nchunk, chunk = tb - qt * nchunk;
+        for (int task = tb; task < te; ++task, (++chunk == nchunk ? (chunk = 0, ++qt) : 0)) {
+          if (qt != cur_q) {
             if (cur_q >= 0) {
 #pragma unroll
-              for (int b = 0; b < 4; ++b) {
+              for (int b = 0; b < WPT; ++b) {
                 const E_t v = wave_sum(acc[b]);
-                if (lane == b && v != (E_t)0) atomicAdd(&energy[4 * cur_q + b], v);
+                if (lane == b && v != (E_t)0) atomicAdd(&energy[WPT * cur_q + b], v);
                 acc[b] = 0;
               }
             }
-            cur_q = q;
+            cur_q = qt;
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
-              tq[b] = uniform(4 * q + b < W ? tau[4 * q + b] : K);
+            for (int b = 0; b < WPT; ++b) {
+              tq[b] = uniform(WPT * qt + b < W ? tau[WPT * qt + b] : K);
               if (tq[b] < K) {
                 if (JK) {
                   bq[b] = uniform_d(beta[tq[b]]);
@@ -721,15 +734,20 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
           }
           const int j = chunk * 64 + lane;
           if (j < Nc) {
-            const int g = q >> 3, sh = 4 * (q & 7);
+            const int q0 = QPT * qt;
+            const int g = q0 >> 3, sh = 4 * (q0 & 7);
             uint32_t* row = sp + g * N;
             const int i = clist[c * Nc + j];
-            // bit sh + b of a word is walker 4q + b (one bit-field extract each)
+            // bit sh + b of a word is walker 4 q0 + b (one bit-field extract each)
             const uint32_t own = row[i];
             uint32_t nw[DEG];
 #pragma unroll
             for (int d = 0; d < DEG; ++d) nw[d] = row[nbr[i * DEG + d]];
-            const Words4 u = philox4x32_10((uint32_t)i, t, (uint32_t)q, kStreamMetro, seed, key);
+            Words4 u[QPT];
+#pragma unroll
+            for (int h = 0; h < QPT; ++h)
+              if (h == 0 || q0 + h < Wq) u[h] = philox4x32_10((uint32_t)i, t, (uint32_t)(q0 + h), kStreamMetro, seed, key);
+              else u[h] = u[0];
             uint32_t flip = 0;
             if (JK) {
               // h = sum_d J_d s_d with s_d = 1 - 2 bit_d: h = sum J - 2 sum_d J_d bit_d (exact)
@@ -738,14 +756,14 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
 #pragma unroll
               for (int d = 0; d < DEG; ++d) { Jd[d] = (double)cf[i * DEG + d]; Jsum += Jd[d]; }
 #pragma unroll
-              for (int b = 0; b < 4; ++b) {
+              for (int b = 0; b < WPT; ++b) {
                 if (tq[b] >= K) continue;
                 double m = 0.0;
 #pragma unroll
                 for (int d = 0; d < DEG; ++d) m += Jd[d] * (double)bit_of(nw[d], sh + b);
                 const double h = Jsum - 2.0 * m;
                 const double dE = bit_of(own, sh + b) ? -2.0 * h : 2.0 * h;
-                if (accept_float(u.w[b], dE, bq[b], lq[b])) {
+                if (accept_float(u[b >> 2].w[b & 3], dE, bq[b], lq[b])) {
                   flip |= 1u << b;
                   acc[b] += (E_t)dE;
                 }
@@ -756,14 +774,14 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
 #pragma unroll
               for (int d = 0; d < DEG; ++d) { Ji[d] = cj[i * DEG + d]; Jsum += Ji[d]; }
 #pragma unroll
-              for (int b = 0; b < 4; ++b) {
+              for (int b = 0; b < WPT; ++b) {
                 if (tq[b] >= K) continue;
                 int m = 0;
 #pragma unroll
                 for (int d = 0; d < DEG; ++d) m += Ji[d] * (int)bit_of(nw[d], sh + b);
                 const int h = Jsum - 2 * m;
                 const int e = bit_of(own, sh + b) ? -h : h;  // dE = 2e
-                if (e <= 0 || u.w[b] < thr[rowb[b] + e]) {
+                if (e <= 0 || u[b >> 2].w[b & 3] < thr[rowb[b] + e]) {
                   flip |= 1u << b;
                   acc[b] += (E_t)(2 * e);
                 }
@@ -775,9 +793,9 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
         }
         if (cur_q >= 0) {
 #pragma unroll
-          for (int b = 0; b < 4; ++b) {
+          for (int b = 0; b < WPT; ++b) {
             const E_t v = wave_sum(acc[b]);
-            if (lane == b && v != (E_t)0) atomicAdd(&energy[4 * cur_q + b], v);
+            if (lane == b && v != (E_t)0) atomicAdd(&energy[WPT * cur_q + b], v);
           }
         }
         __syncthreads();
@@ -1282,8 +1300,10 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
           bool accept;
           const uint32_t u = ptu[k * R + r];
           if (JK) {
+            // u 2^-32 < exp(-(beta_k - beta_k+1) D) in double, after the float
+            // pre-filter that settles all but a thin band (as for Metropolis)
             const double D = (double)energy[y] - (double)energy[x];
-            accept = D <= 0.0 || (double)u * 0x1p-32 < exp(-((beta[k] - beta[k + 1]) * D));
+            accept = accept_float(u, D, beta[k] - beta[k + 1], dbl2e[k]);
           } else {
             const int D = (int)energy[y] - (int)energy[x];
             accept = D <= 0 || (D <= U.ptlen && u < U.ptthr[k * U.ptlen + (D - 1)]);
