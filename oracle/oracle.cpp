@@ -12,6 +12,7 @@
 
 #include "oracle.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -71,19 +72,36 @@ struct orc_sim {
   std::vector<int64_t> obs;                // [32][K][R/2][3] observable sums
   std::vector<int64_t> obs_count;          // [32] samples per time bin
   std::vector<int32_t> last_seed, last_nminus;
+  int jexp = 0;                            // float couplings: grid 2^-jexp
 };
 
 namespace {
 
-int64_t quantize_f32(float J) {
-  // Gaussian couplings are represented on the 2^-32 grid: raw = rint(J * 2^32).
-  // For |J| >= 2^-8 this is J itself; smaller |J| move by at most 2^-33.
-  return (int64_t)std::nearbyint(std::ldexp((double)J, 32));
+// Float couplings are represented on the grid 2^-e, e the largest exponent
+// <= 20 for which every |J| 2^e rounds to at most 2^23 - 1 (e = 20 whenever
+// all |J| < 8): then every coupling is an integer multiple of 2^-e that a
+// signed 24-bit integer holds, and local fields and energy changes are exact
+// integer sums.  Raw energies are kept in units of 2^-32: raw = rint(J 2^e) 2^(32-e).
+int64_t n_couplings(const orc_params& p) {
+  if (p.topology == ORC_SQUARE2D) return (int64_t)p.L * p.L * 2;
+  if (p.topology == ORC_CUBIC3D) return (int64_t)p.L * p.L * p.L * 3;
+  if (p.topology == ORC_CHIMERA) return (int64_t)p.L * p.L * 24;
+  return p.n_edges;
 }
 
-int64_t coupling_raw(const orc_params& p, int64_t idx) {
+int grid_exponent(const orc_params& p) {
+  double m = 0.0;
+  const int64_t n = n_couplings(p);
+  for (int64_t x = 0; x < n; ++x) m = std::max(m, std::fabs((double)((const float*)p.couplings)[x]));
+  int e = 20;
+  while (e > -32 && std::nearbyint(std::ldexp(m, e)) > 8388607.0) --e;
+  return e;
+}
+
+int64_t coupling_raw(const orc_params& p, int jexp, int64_t idx) {
   if (p.jkind == ORC_J_INT8) return ((const int8_t*)p.couplings)[idx];
-  return quantize_f32(((const float*)p.couplings)[idx]);
+  const double q = std::nearbyint(std::ldexp((double)((const float*)p.couplings)[idx], jexp));
+  return (int64_t)std::ldexp(q, 32 - jexp);
 }
 
 bool coupling_valid(const orc_params& p, int64_t idx) {
@@ -121,7 +139,7 @@ int build_graph(orc_sim* s) {
                     x + L * y + L * L * ((z + 1) % L)};
       for (int d = 0; d < dim; ++d) {
         if (!coupling_valid(p, (int64_t)i * dim + d)) return -1;
-        add_bond(s, i, fwd[d], coupling_raw(p, (int64_t)i * dim + d));
+        add_bond(s, i, fwd[d], coupling_raw(p, s->jexp, (int64_t)i * dim + d));
       }
     }
     return 0;
@@ -139,14 +157,14 @@ int build_graph(orc_sim* s) {
           if (!coupling_valid(p, (int64_t)cell * 24 + e)) return -1;
         for (int u = 0; u < 4; ++u)
           for (int v = 4; v < 8; ++v)
-            add_bond(s, base + u, base + v, coupling_raw(p, (int64_t)cell * 24 + u * 4 + (v - 4)));
+            add_bond(s, base + u, base + v, coupling_raw(p, s->jexp, (int64_t)cell * 24 + u * 4 + (v - 4)));
         for (int u = 0; u < 4; ++u) {
-          int64_t raw = coupling_raw(p, (int64_t)cell * 24 + 16 + u);
+          int64_t raw = coupling_raw(p, s->jexp, (int64_t)cell * 24 + 16 + u);
           if (row + 1 < C) add_bond(s, base + u, 8 * ((row + 1) * C + col) + u, raw);
           else if (raw != 0) return -1;
         }
         for (int u = 4; u < 8; ++u) {
-          int64_t raw = coupling_raw(p, (int64_t)cell * 24 + 20 + (u - 4));
+          int64_t raw = coupling_raw(p, s->jexp, (int64_t)cell * 24 + 20 + (u - 4));
           if (col + 1 < C) add_bond(s, base + u, 8 * (row * C + col + 1) + u, raw);
           else if (raw != 0) return -1;
         }
@@ -163,7 +181,7 @@ int build_graph(orc_sim* s) {
       if (i < 0 || j < 0 || i >= s->N || j >= s->N || i == j) return -1;
       if (s->colour[i] == s->colour[j]) return -1;  // checkerboard needs a proper 2-colouring
       if (!coupling_valid(p, e)) return -1;
-      add_bond(s, i, j, coupling_raw(p, e));
+      add_bond(s, i, j, coupling_raw(p, s->jexp, e));
     }
     return 0;
   }
@@ -336,6 +354,14 @@ int orc_create(const orc_params* p, orc_sim** out) {
   }
   orc_sim* s = new orc_sim();
   s->p = *p;
+  if (p->jkind == ORC_J_F32 && p->topology != ORC_EXPLICIT) {
+    const int64_t n = n_couplings(*p);
+    for (int64_t x = 0; x < n; ++x) {
+      const float J = ((const float*)p->couplings)[x];
+      if (!std::isfinite(J) || std::fabs(J) > 64.0f) { delete s; return -1; }
+    }
+  }
+  if (p->jkind == ORC_J_F32) s->jexp = grid_exponent(*p);
   if (build_graph(s) != 0) { delete s; return -1; }
   s->K = p->n_temps; s->R = p->n_replicas; s->W = s->K * s->R; s->Kc = p->icm_ntemps;
   s->beta.resize(s->K);

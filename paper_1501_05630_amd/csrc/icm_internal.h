@@ -35,7 +35,8 @@ struct UnitDesc {
   uint32_t* spins;          // [Wq][N] words; byte b of word (q, i) = walker 4q+b at site i
   const uint16_t* nbr;      // [N][deg] neighbour sites (missing chimera slots: i itself)
   const uint16_t* clist;    // [2][Nc] sites of colour 0, then colour 1
-  const void* coup;         // [N][deg] int8 j or float J (grid-rounded), slot-aligned with nbr
+  const void* coup;         // [N][deg] int8 j, or int32 J 2^jexp (float couplings rounded to the
+                            // grid 2^-jexp, 24-bit signed), slot-aligned with nbr
   const uint32_t* thr;      // int kinds: [K][HM] Metropolis thresholds, index e = s*h
   const double* beta;       // [K] 1/T_k
   const float* bl2e;        // [K] float(beta_k * log2(e)) for the fast acceptance filter
@@ -51,7 +52,8 @@ struct UnitDesc {
   uint32_t* sweep;          // sweep counter t
   int32_t N, Nc, deg, W, Wq, K, R, Kc, HM, ptlen, jkind, jscale;
   uint32_t flags, seed, key;
-  int32_t topo, L, pad0;    // lattice kind (ICM_TOPO_*) and side / cells per side
+  int32_t topo, L;          // lattice kind (ICM_TOPO_*) and side / cells per side
+  int32_t jexp;             // float couplings: grid exponent (J = coup 2^-jexp)
 };
 
 constexpr uint32_t kFlag2a = 1, kFlagPt = 2, kFlagRecord = 4, kFlagSkipMetro = 8, kFlagMeasure = 16;

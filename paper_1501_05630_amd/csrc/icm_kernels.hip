@@ -159,6 +159,19 @@ __device__ __forceinline__ bool accept_float(uint32_t u, double dE, double beta,
   return accept_exact(u, dE, beta);
 }
 
+// The same decision for an integer field: dE = e 2^(1 - jexp) (e = s_i h in
+// units of the coupling grid); lq2 = float(beta log2 e) 2^(1 - jexp), jq2 =
+// 2^(1 - jexp).  float(e) is within a relative 2^-24 of e, which the margin
+// covers as before; the exact test sees the same double dE as the oracle.
+__device__ __forceinline__ bool accept_int_field(uint32_t u, int e, double beta, float lq2, double jq2) {
+  if (e <= 0) return true;
+  const float P = __builtin_amdgcn_exp2f(__builtin_fmaf(-(float)e, lq2, 32.0f));
+  const float uf = (float)u;
+  if (uf > P * (1.0f + 0x1p-14f)) return false;
+  if (uf < P * (1.0f - 0x1p-14f)) return true;
+  return accept_exact(u, (double)e * jq2, beta);
+}
+
 // ----------------------------------------------------------------------------
 // union-find on an LDS parent array (parent[x] <= x; roots satisfy parent[x] == x)
 // ----------------------------------------------------------------------------
@@ -449,7 +462,7 @@ __device__ __noinline__ typename EnergyT<JK>::T pair_boundary(bool sq64, uint32_
   using E_t = typename EnergyT<JK>::T;
   const uint32_t* gmc = (const uint32_t*)(lds + mc_off);
   const uint32_t* gaw = (const uint32_t*)(lds + aw_off);
-  const float* cf = coup_global ? (const float*)coup_global : (const float*)(lds + coup_off);
+  const int32_t* cf = coup_global ? (const int32_t*)coup_global : (const int32_t*)(lds + coup_off);
   const int8_t* cj = coup_global ? (const int8_t*)coup_global : (const int8_t*)(lds + coup_off);
   uint32_t* rowa = (uint32_t*)(lds + rowa_off);
   uint32_t* rowb = (uint32_t*)(lds + rowb_off);
@@ -589,7 +602,8 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
   const uint16_t* nbr = TL ? (const uint16_t*)(lds + lay.nbr) : U.nbr;
   const uint16_t* clist = TL ? (const uint16_t*)(lds + lay.clist) : U.clist;
   const int8_t* cj = TL ? (const int8_t*)(lds + lay.coup) : (const int8_t*)U.coup;
-  const float* cf = TL ? (const float*)(lds + lay.coup) : (const float*)U.coup;
+  // float couplings as integers in units of 2^-jexp (exact 24-bit values)
+  const int32_t* cf = TL ? (const int32_t*)(lds + lay.coup) : (const int32_t*)U.coup;
   int* tau = (int*)(lds + lay.tau);
   int* at = (int*)(lds + lay.at);
   int* gauge = (int*)(lds + lay.gauge);
@@ -623,8 +637,8 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
     for (int x = tid; x < N * DEG; x += nthr) nbr_w[x] = U.nbr[x];
     for (int x = tid; x < N; x += nthr) clist_w[x] = U.clist[x];
     if (JK) {
-      float* cf_w = (float*)(lds + lay.coup);
-      for (int x = tid; x < N * DEG; x += nthr) cf_w[x] = ((const float*)U.coup)[x];
+      int32_t* cf_w = (int32_t*)(lds + lay.coup);
+      for (int x = tid; x < N * DEG; x += nthr) cf_w[x] = ((const int32_t*)U.coup)[x];
     } else {
       int8_t* cj_w = (int8_t*)(lds + lay.coup);
       for (int x = tid; x < N * DEG; x += nthr) cj_w[x] = ((const int8_t*)U.coup)[x];
@@ -713,7 +727,8 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
             if (cur_q >= 0) {
 #pragma unroll
               for (int b = 0; b < WPT; ++b) {
-                const E_t v = wave_sum(acc[b]);
+                E_t v = wave_sum(acc[b]);
+                if (JK) v = (E_t)ldexp((double)v, -U.jexp);  // units of 2^-jexp -> energy
                 if (lane == b && v != (E_t)0) atomicAdd(&energy[WPT * cur_q + b], v);
                 acc[b] = 0;
               }
@@ -725,7 +740,7 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
               if (tq[b] < K) {
                 if (JK) {
                   bq[b] = uniform_d(beta[tq[b]]);
-                  lq[b] = __int_as_float(uniform(__float_as_int(bl2e[tq[b]])));
+                  lq[b] = ldexpf(__int_as_float(uniform(__float_as_int(bl2e[tq[b]]))), 1 - U.jexp);
                 } else {
                   rowb[b] = tq[b] * HM;
                 }
@@ -750,37 +765,52 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
               else u[h] = u[0];
             uint32_t flip = 0;
             if (JK) {
-              // h = sum_d J_d s_d with s_d = 1 - 2 bit_d: h = sum J - 2 sum_d J_d bit_d (exact)
-              double Jd[DEG];
-              double Jsum = 0.0;
+              // e = s_i h = sum_d J_d s_i s_d = sum J - 2 sum_d J_d x_d, x_d = 1 where
+              // the spin and its d-neighbour differ (own word xor neighbour word,
+              // once for all walkers of the task); exact in units of 2^-jexp
+              const double jq2 = ldexp(1.0, 1 - U.jexp);
+              int Ji[DEG];
+              int Jsum = 0;
+              uint32_t xw[DEG];
 #pragma unroll
-              for (int d = 0; d < DEG; ++d) { Jd[d] = (double)cf[i * DEG + d]; Jsum += Jd[d]; }
+              for (int d = 0; d < DEG; ++d) {
+                Ji[d] = cf[i * DEG + d];
+                Jsum += Ji[d];
+                xw[d] = nw[d] ^ own;
+              }
 #pragma unroll
               for (int b = 0; b < WPT; ++b) {
                 if (tq[b] >= K) continue;
-                double m = 0.0;
+                // the bit extracted sign-extended (0 or -1) masks J_d
+                int m = 0;
 #pragma unroll
-                for (int d = 0; d < DEG; ++d) m += Jd[d] * (double)bit_of(nw[d], sh + b);
-                const double h = Jsum - 2.0 * m;
-                const double dE = bit_of(own, sh + b) ? -2.0 * h : 2.0 * h;
-                if (accept_float(u[b >> 2].w[b & 3], dE, bq[b], lq[b])) {
+                for (int d = 0; d < DEG; ++d)
+                  m += Ji[d] & __builtin_amdgcn_sbfe((int)xw[d], (unsigned)(sh + b), 1u);
+                const int e = Jsum - 2 * m;  // dE = e 2^(1 - jexp)
+                if (accept_int_field(u[b >> 2].w[b & 3], e, bq[b], lq[b], jq2)) {
                   flip |= 1u << b;
-                  acc[b] += (E_t)dE;
+                  acc[b] += (E_t)(2 * e);
                 }
               }
             } else {
+              // e = s_i h = sum J - 2 sum_d J_d x_d as for float couplings
               int Ji[DEG];
               int Jsum = 0;
+              uint32_t xw[DEG];
 #pragma unroll
-              for (int d = 0; d < DEG; ++d) { Ji[d] = cj[i * DEG + d]; Jsum += Ji[d]; }
+              for (int d = 0; d < DEG; ++d) {
+                Ji[d] = cj[i * DEG + d];
+                Jsum += Ji[d];
+                xw[d] = nw[d] ^ own;
+              }
 #pragma unroll
               for (int b = 0; b < WPT; ++b) {
                 if (tq[b] >= K) continue;
                 int m = 0;
 #pragma unroll
-                for (int d = 0; d < DEG; ++d) m += Ji[d] * (int)bit_of(nw[d], sh + b);
-                const int h = Jsum - 2 * m;
-                const int e = bit_of(own, sh + b) ? -h : h;  // dE = 2e
+                for (int d = 0; d < DEG; ++d)
+                  m += Ji[d] & __builtin_amdgcn_sbfe((int)xw[d], (unsigned)(sh + b), 1u);
+                const int e = Jsum - 2 * m;  // dE = 2e
                 if (e <= 0 || u[b >> 2].w[b & 3] < thr[rowb[b] + e]) {
                   flip |= 1u << b;
                   acc[b] += (E_t)(2 * e);
@@ -794,7 +824,8 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
         if (cur_q >= 0) {
 #pragma unroll
           for (int b = 0; b < WPT; ++b) {
-            const E_t v = wave_sum(acc[b]);
+            E_t v = wave_sum(acc[b]);
+            if (JK) v = (E_t)ldexp((double)v, -U.jexp);
             if (lane == b && v != (E_t)0) atomicAdd(&energy[WPT * cur_q + b], v);
           }
         }
@@ -1278,6 +1309,8 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
                 if (inf[kInMv] < 0 || inf[kInN] == 0) continue;
                 E_t sum = 0;
                 for (int r2 = g * rpg; r2 < (g + 1) * rpg; ++r2) sum += rows[r2];
+                // float couplings: sums in units of 2^-jexp (exact scaling)
+                if (JK) sum = (E_t)ldexp((double)sum, -U.jexp);
                 energy[inf[kInA]] += (E_t)2 * sum;
                 energy[inf[kInB]] -= (E_t)2 * sum;
               }
@@ -1397,7 +1430,7 @@ __global__ void scatter_spins_kernel(uint32_t* spins, const int8_t* src, int N, 
 // as int64 after scaling).  grid: (Wp), block 256.
 template <int JK>
 __global__ void energy_kernel(const uint32_t* spins, const uint16_t* nbr, const void* coup, int N,
-                              int deg, int64_t* energy) {
+                              int deg, int jexp, int64_t* energy) {
   const int w = blockIdx.x, q = w >> 2, b = w & 3;
   __shared__ long long part[256];
   long long acc = 0;
@@ -1407,7 +1440,7 @@ __global__ void energy_kernel(const uint32_t* spins, const uint16_t* nbr, const 
       const int j = nbr[i * deg + d];
       const int sj = spin_of(spins[(size_t)q * N + j], b);
       long long Jraw;
-      if (JK) Jraw = (long long)((double)((const float*)coup)[i * deg + d] * 0x1p32);
+      if (JK) Jraw = (long long)((const int32_t*)coup)[i * deg + d] << (32 - jexp);
       else Jraw = ((const int8_t*)coup)[i * deg + d];
       acc -= Jraw * si * sj;
     }
@@ -1484,13 +1517,13 @@ int icmk_launch_scatter(uint32_t* spins, const int8_t* src, int N, int Wq, int W
 }
 
 int icmk_launch_energy(const uint32_t* spins, const uint16_t* nbr, const void* coup, int N, int deg,
-                       int Wp, int jkind, int64_t* energy, hipStream_t stream) {
+                       int Wp, int jkind, int jexp, int64_t* energy, hipStream_t stream) {
   if (jkind)
     hipLaunchKernelGGL(icm::energy_kernel<1>, dim3(Wp), dim3(256), 0, stream, spins, nbr, coup, N,
-                       deg, energy);
+                       deg, jexp, energy);
   else
     hipLaunchKernelGGL(icm::energy_kernel<0>, dim3(Wp), dim3(256), 0, stream, spins, nbr, coup, N,
-                       deg, energy);
+                       deg, jexp, energy);
   return (int)hipGetLastError();
 }
 

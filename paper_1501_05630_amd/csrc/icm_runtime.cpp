@@ -33,7 +33,7 @@ int icmk_launch_init(uint32_t* spins, int N, int Wq, int W, uint32_t seed, uint3
 int icmk_launch_scatter(uint32_t* spins, const int8_t* src, int N, int Wq, int W,
                         hipStream_t stream);
 int icmk_launch_energy(const uint32_t* spins, const uint16_t* nbr, const void* coup, int N, int deg,
-                       int Wp, int jkind, int64_t* energy, hipStream_t stream);
+                       int Wp, int jkind, int jexp, int64_t* energy, hipStream_t stream);
 }
 
 namespace {
@@ -219,6 +219,7 @@ struct Instance {
   Topology* topo = nullptr;
   int N = 0, deg = 0, K = 0, R = 0, W = 0, Wq = 0, Wp = 0, Kc = 0, HM = 0, ptlen = 0;
   int jkind = 0, jscale = 1;
+  int jexp = 0;                      // float couplings: grid exponent
   uint32_t flags = 0, key = 0;
   std::vector<double> temps;
   uint32_t sweep_host = 0;
@@ -372,10 +373,19 @@ int validate_desc(const icm_instance_desc* d, std::string& why) {
   return ICM_OK;
 }
 
-float quantize_coupling(float J) {
-  // Round to the 2^-32 grid; the result is exactly representable in float.
-  return (float)std::ldexp(std::nearbyint(std::ldexp((double)J, 32)), -32);
+// Float couplings are rounded to the grid 2^-e, e the largest exponent <= 20
+// for which every |J| 2^e rounds to at most 2^23 - 1 (e = 20 whenever all
+// |J| < 8): each coupling is then a signed 24-bit integer in units of 2^-e,
+// so local fields and energy changes are exact integer sums.
+int grid_exponent(const float* J, size_t n) {
+  double m = 0.0;
+  for (size_t x = 0; x < n; ++x) m = std::max(m, std::fabs((double)J[x]));
+  int e = 20;
+  while (e > -32 && std::nearbyint(std::ldexp(m, e)) > 8388607.0) --e;
+  return e;
 }
+
+int32_t grid_coupling(float J, int e) { return (int32_t)std::nearbyint(std::ldexp((double)J, e)); }
 
 Topology* get_topology(icm_ctx* c, int topo, int L, int& rc) {
   rc = ICM_OK;
@@ -538,6 +548,9 @@ int add_instance_impl(icm_ctx* c, const icm_instance_desc* d, int32_t* out) {
   in->ptlen = S.ptlen;
   in->jkind = d->jkind;
   in->jscale = d->jkind == ICM_J_INT8 ? d->j_scale : 1;
+  in->jexp = d->jkind == ICM_J_F32
+                  ? grid_exponent((const float*)d->couplings, (size_t)coupling_count(d->topology, d->L))
+                  : 0;
   in->flags = d->flags;
   in->key = d->instance_key;
   in->temps.assign(d->temps, d->temps + d->n_temps);
@@ -585,6 +598,7 @@ int add_instance_impl(icm_ctx* c, const icm_instance_desc* d, int32_t* out) {
   U.jscale = in->jscale;
   U.flags = in->flags;
   U.topo = T->topo;
+  U.jexp = in->jexp;
   U.L = T->L;
   U.seed = c->seed;
   U.key = in->key;
@@ -596,7 +610,7 @@ int add_instance_impl(icm_ctx* c, const icm_instance_desc* d, int32_t* out) {
     for (int s = 0; s < deg; ++s) {
       const int ci = T->cidx[(size_t)i * deg + s];
       if (d->jkind == ICM_J_F32) {
-        const float v = ci >= 0 ? quantize_coupling(((const float*)d->couplings)[ci]) : 0.0f;
+        const int32_t v = ci >= 0 ? grid_coupling(((const float*)d->couplings)[ci], in->jexp) : 0;
         std::memcpy(&coup[((size_t)i * deg + s) * 4], &v, 4);
       } else {
         coup[(size_t)i * deg + s] = (uint8_t)(ci >= 0 ? ((const int8_t*)d->couplings)[ci] : 0);
@@ -618,7 +632,8 @@ int add_instance_impl(icm_ctx* c, const icm_instance_desc* d, int32_t* out) {
   HIP_OK(c, hipMemsetD32Async((hipDeviceptr_t)U.spins, 0x01010101, S.spins / 4, c->stream));
   int r2 = reset_walkers(c, in.get(), 0);
   if (r2) return r2;
-  KERNEL_OK(c, icmk_launch_energy(U.spins, U.nbr, U.coup, N, deg, in->Wp, in->jkind, U.energy, c->stream));
+  KERNEL_OK(c, icmk_launch_energy(U.spins, U.nbr, U.coup, N, deg, in->Wp, in->jkind, in->jexp, U.energy,
+                                  c->stream));
   HIP_OK(c, hipStreamSynchronize(c->stream));
   const int32_t h = c->next_handle++;
   in->handle = h;
@@ -969,7 +984,7 @@ int icm_init_states(icm_ctx* c, int32_t h) {
   rc = reset_walkers(c, in, 0);
   if (rc) return rc;
   KERNEL_OK(c, icmk_launch_energy(in->unit.spins, in->unit.nbr, in->unit.coup, in->N, in->deg, in->Wp,
-                                  in->jkind, in->unit.energy, c->stream));
+                                  in->jkind, in->jexp, in->unit.energy, c->stream));
   HIP_OK(c, hipStreamSynchronize(c->stream));
   return ICM_OK;
 }
@@ -993,7 +1008,7 @@ int icm_set_states(icm_ctx* c, int32_t h, const int8_t* spins, uint32_t sweep0) 
   rc = reset_walkers(c, in, sweep0);
   if (rc) return rc;
   KERNEL_OK(c, icmk_launch_energy(in->unit.spins, in->unit.nbr, in->unit.coup, in->N, in->deg, in->Wp,
-                                  in->jkind, in->unit.energy, c->stream));
+                                  in->jkind, in->jexp, in->unit.energy, c->stream));
   HIP_OK(c, hipStreamSynchronize(c->stream));
   return ICM_OK;
 }

@@ -57,8 +57,11 @@ def test_energy_matches_layout_formula_and_spin_reversal(top, L):
             assert raw == s.energy_raw(-spins)
             ref = exact.energy(top, L, J, spins)
             if kind == "gauss":
-                # raw is in 2^-32 units of J rounded to the 2^-32 grid
-                assert abs(raw * 2.0 ** -32 - ref) < s.n_bonds * 2.0 ** -32
+                # raw is in 2^-32 units of J rounded to the 2^-20 grid: exact
+                # against the formula on the rounded couplings
+                Jq = np.rint(np.asarray(J, np.float64) * 2.0 ** 20) * 2.0 ** -20
+                assert raw * 2.0 ** -32 == exact.energy(top, L, Jq, spins)
+                assert abs(raw * 2.0 ** -32 - ref) < s.n_bonds * 2.0 ** -21
             else:
                 assert raw == round(ref)
 
@@ -112,17 +115,29 @@ def test_chimera_rejects_couplings_off_the_grid():
         make(inputs.CHIMERA, 2, J)
 
 
-def test_gaussian_quantisation_is_exact_for_normal_magnitudes():
+def test_gaussian_couplings_sit_on_the_2_pow_minus_20_grid():
+    # every |J| < 8: J is rounded to the nearest multiple of 2^-20 (a signed
+    # 24-bit integer), raw energies stay in units of 2^-32
     rng = inputs.make_rng(98, 0)
     J = inputs.gaussian_couplings(inputs.SQUARE2D, 4, rng)
     s = make(inputs.SQUARE2D, 4, J)
     ij, raw = s.bonds()
     ref = [b[2] for b in exact.bond_list(inputs.SQUARE2D, 4, J)]
     for r, j in zip(raw, ref):
-        if abs(j) >= 2.0 ** -8:
-            assert r * 2.0 ** -32 == float(j)
-        else:
-            assert abs(r * 2.0 ** -32 - float(j)) <= 2.0 ** -33
+        assert r % (1 << 12) == 0
+        assert r * 2.0 ** -32 == np.rint(float(j) * 2.0 ** 20) * 2.0 ** -20
+        assert abs(r * 2.0 ** -32 - float(j)) <= 2.0 ** -21
+
+
+def test_large_gaussian_couplings_move_to_a_coarser_grid():
+    # one |J| = 40: 40 * 2^17 = 5242880 fits 24 signed bits, 40 * 2^18 does not
+    J = inputs.gaussian_couplings(inputs.SQUARE2D, 4, inputs.make_rng(98, 1))
+    J[3, 1] = np.float32(40.0)
+    s = make(inputs.SQUARE2D, 4, J)
+    _, raw = s.bonds()
+    assert all(r % (1 << 15) == 0 for r in raw)
+    assert any(r % (1 << 16) != 0 for r in raw)
+    assert 40 * 2 ** 32 in list(raw)
 
 
 def test_brute_force_ground_state_of_ferromagnet_is_uniform():
