@@ -897,8 +897,11 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
             const uint32_t* rowb = sp + (b >> 5) * N;
             const int pa = a & 31, pb = b & 31;
             const uint32_t gx = (uint32_t)(gauge[a] ^ gauge[b]);
-            // q_i = -1 <=> the replicas differ at i; 64 sites per ballot
+            // q_i = -1 <=> the replicas differ at i; 64 sites per ballot.  Lane l
+            // keeps words l and l + 64 of the mask and of replica a in registers
+            // (no stores in the loop, so its loads can all be in flight at once)
             int n = 0;
+            uint32_t mw0 = 0, mw1 = 0, aw0 = 0, aw1 = 0;
             for (int s2 = 0; s2 * 64 < N; ++s2) {
               const int i = s2 * 64 + lane;
               uint32_t qb = 0, ab = 0;
@@ -908,27 +911,30 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
               }
               const unsigned long long bq = __ballot(qb), ba = __ballot(ab);
               n += __popcll(bq);
-              if (lane == 0) {
-                mc[4 * s2] = (uint32_t)bq;
-                aw[2 * s2] = (uint32_t)ba;
-                if (2 * s2 + 1 < nw) {
-                  mc[4 * s2 + 2] = (uint32_t)(bq >> 32);
-                  aw[2 * s2 + 1] = (uint32_t)(ba >> 32);
-                }
+              const int w0 = (2 * s2) & 63;  // words 2 s2, 2 s2 + 1 go to lanes w0, w0 + 1
+              const bool lo = lane == w0, hi = lane == w0 + 1;
+              if (2 * s2 < 64) {
+                mw0 = lo ? (uint32_t)bq : (hi ? (uint32_t)(bq >> 32) : mw0);
+                aw0 = lo ? (uint32_t)ba : (hi ? (uint32_t)(ba >> 32) : aw0);
+              } else {
+                mw1 = lo ? (uint32_t)bq : (hi ? (uint32_t)(bq >> 32) : mw1);
+                aw1 = lo ? (uint32_t)ba : (hi ? (uint32_t)(ba >> 32) : aw1);
               }
             }
             n = uniform(n);
             const bool twoa = (flags & kFlag2a) && 2 * n > N;
-            wave_sync();
             // step 2a: reverse the second replica (the q-mask complements);
             // the cluster and frontier start empty
-            for (int w = lane; w < nw; w += 64) {
+            for (int w = lane, k2 = 0; w < nw; w += 64, ++k2) {
+              uint32_t mword = k2 ? mw1 : mw0;
               if (twoa) {
                 const int rem_bits = N - 32 * w;
                 const uint32_t valid = rem_bits >= 32 ? ~0u : ((1u << rem_bits) - 1u);
-                mc[2 * w] = ~mc[2 * w] & valid;
+                mword = ~mword & valid;
               }
+              mc[2 * w] = mword;
               mc[2 * w + 1] = 0;
+              aw[w] = k2 ? aw1 : aw0;
               f0[w] = 0;
             }
             if (twoa) n = N - n;
