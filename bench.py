@@ -46,6 +46,11 @@ def parse():
     ap.add_argument("--arena-mib", type=int, default=1024)
     ap.add_argument("--thermalization", type=int, default=0,
                     help="run this many sweeps with and without ICM and report Delta(t) (Eq. 2) instead")
+    ap.add_argument("--table1", type=int, default=0,
+                    help="run the thermalization study at the paper's Table I parameters for this many "
+                         "sweeps instead (PT vs PT + ICM per topology and size)")
+    ap.add_argument("--table1-instances", type=int, default=128, help="disorder instances per size")
+    ap.add_argument("--table1-topologies", default="2d,chimera,3d")
     return ap.parse_args()
 
 
@@ -255,8 +260,96 @@ def run_thermalization(args):
     return out
 
 
+def run_table1(args):
+    """The thermalization study at the paper's Table I parameters with fewer
+    disorder instances and sweeps: per topology and size, Delta (Eq. 2) at the
+    lowest temperature per time bin for PT alone and PT + ICM on the same
+    instances, the thermalization bin of each (icm.thermalization_bin), their
+    ratio, and the fraction p of potential cluster sites against T in the last
+    complete bin."""
+    import numpy as np
+    import torch
+
+    from paper_1501_05630_amd import icm, inputs
+    names = {"2d": "table1_2d_gauss", "chimera": "table1_chimera_gauss", "3d": "table1_3d_gauss"}
+    M = args.table1_instances
+    out = {"metric": "thermalization at the Table I parameters: Delta (Eq. 2) at T_min per time bin "
+                     "t in [2^b, 2^(b+1)), PT vs PT + ICM; cluster-site fraction p(T)",
+           "sweeps": args.table1, "instances_per_size": M, "data": "synthetic Gaussian disorder, hot start"}
+    for top in args.table1_topologies.split(","):
+        name = names[top]
+        spec = inputs.WORKLOADS[name]
+        per = {}
+        for mode in ("pt", "pt_icm"):
+            ctx = icm.Context(arena_bytes=6 << 30, seed=inputs.MASTER_SEED)
+            ctx.icm_set_run_config(threads=args.threads, sweeps_per_launch=args.sweeps_per_step,
+                                   use_graph=1, icm_slots=args.icm_slots)
+            hs = []
+            for si, L in enumerate(spec["sides"]):
+                for m in range(M):
+                    b = si * spec["per_side"] + m
+                    J, temps, kc, sp = inputs.workload_instance(name, b)
+                    hs.append((L, ctx.icm_add_instance(sp["topology"], L, J, temps, spec["n_replicas"],
+                                                       kc if mode == "pt_icm" else 0,
+                                                       flags=icm.FLAG_2A | icm.FLAG_PT | icm.FLAG_MEASURE,
+                                                       instance_key=b, j_scale=1)))
+                    ctx.icm_init_states(hs[-1][1])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            done, shown = 0, t0
+            while done < args.table1:      # in chunks, with a progress line every 30 s
+                n = min(1 << 14, args.table1 - done)
+                ctx.icm_run([h for _, h in hs], n)
+                ctx.icm_sync()
+                done += n
+                if time.perf_counter() - shown > 30:
+                    shown = time.perf_counter()
+                    print(f"table1 {top} {mode}: {done} sweeps", file=sys.stderr, flush=True)
+            wall = time.perf_counter() - t0
+            print(f"table1 {top} {mode}: {len(hs)} instances x {args.table1} sweeps in {wall:.1f} s",
+                  file=sys.stderr, flush=True)
+            for L in spec["sides"]:
+                N = inputs.n_sites(spec["topology"], L)
+                nb = {inputs.SQUARE2D: 2 * N, inputs.CUBIC3D: 3 * N,
+                      inputs.CHIMERA: 16 * L * L + 8 * L * (L - 1)}[spec["topology"]]
+                d, p = [], []
+                for L2, h in hs:
+                    if L2 != L:
+                        continue
+                    sums, counts = ctx.icm_read_observables(h)
+                    d.append(icm.delta_per_bin(sums, counts, temps, N, nb, 2.0 ** -32)[2][:, 0])
+                    p.append(icm.cluster_fraction_per_bin(sums, counts, N))
+                complete = [int(c) == (1 << b) for b, c in enumerate(counts)]
+                last = max(b for b in range(len(complete)) if complete[b])
+                d = np.array(d)                                   # [instances][bins]
+                d = d[:, :last + 1]
+                mean = d.mean(axis=0)
+                se = d.std(axis=0, ddof=1) / np.sqrt(len(d))
+                tb = icm.thermalization_bin(mean, se, complete)
+                per.setdefault(L, {"N": N})[mode] = {
+                    "wall_s": wall, "delta_tmin": [float(x) for x in mean[:last + 1]],
+                    "se_tmin": [float(x) for x in se[:last + 1]], "thermalized_bin": tb}
+                if mode == "pt_icm":
+                    per[L]["temps"] = [float(x) for x in temps]
+                    per[L]["p_last_bin"] = [float(x) for x in np.mean(np.array(p), axis=0)[last]]
+            ctx.close()
+        for L, r in per.items():
+            a, b = r["pt"]["thermalized_bin"], r["pt_icm"]["thermalized_bin"]
+            r["speedup"] = (2.0 ** (a - b) if a is not None and b is not None else
+                            (f">= 2^{len(r['pt']['delta_tmin']) - b}" if b is not None else None))
+        out[top] = {"workload": name, "t_min": spec["t_min"], "n_icm": spec["n_icm"],
+                    "sizes": {str(L): r for L, r in per.items()}}
+    return out
+
+
 def main():
     args = parse()
+    if args.table1:
+        if args.gpus != 1:
+            print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+            sys.exit(2)
+        print(json.dumps(run_table1(args)), flush=True)
+        return
     if args.thermalization:
         if args.gpus != 1:
             print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))

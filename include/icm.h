@@ -83,7 +83,7 @@ extern "C" {
 #define ICM_FLAG_MEASURE 16      /* accumulate the observables after every step
                                     (icm_read_observables) */
 #define ICM_OBS_BINS 32
-#define ICM_OBS_FIELDS 3
+#define ICM_OBS_FIELDS 4
 
 typedef struct icm_ctx icm_ctx;
 
@@ -183,7 +183,9 @@ int icm_read_labels(icm_ctx* ctx, int32_t handle, int32_t k, int32_t pair, int32
                     int32_t* seed, int32_t* n_minus, size_t cap);
 int icm_read_stats(icm_ctx* ctx, int32_t handle, icm_stats* out);
 /* Observables of the paper's "Benchmark model and observables" paragraph (the
-   energy, the link overlap q_l of Eq. 1 and the spin overlap), for the two
+   energy, the link overlap q_l of Eq. 1 and the spin overlap) and of its
+   discussion of cluster sizes (the fraction p of potential cluster sites,
+   plotted against T for the three topologies), for the two
    replicas of each ICM pair (chains 2p, 2p+1) at each temperature k, summed
    over the steps since the last icm_init_states / icm_set_states in
    logarithmic time bins: a step that ends at sweep count t (t = 1, 2, ...)
@@ -191,7 +193,9 @@ int icm_read_stats(icm_ctx* ctx, int32_t handle, icm_stats* out);
    sums [ICM_OBS_BINS][K][R/2][ICM_OBS_FIELDS], int64:
      0: E_a + E_b in raw energy units (see icm_read_energies),
      1: sum over bonds of q_i q_j = N_b q_l (q_i = s_a,i s_b,i),
-     2: (sum_i q_i)^2;
+     2: (sum_i q_i)^2,
+     3: min(n, N - n), n = sites with q_i = -1: the potential cluster sites
+        after step 2a (p = this over N);
    counts [ICM_OBS_BINS]: steps per bin.  E(q_l) = -(J^2/T)(N_b/N)(1 - q_l)
    and Delta = <E(q_l)> - <H/N> (Eq. 2) follow from the bin means.
    cap = capacity of sums in elements; ICM_E_BUFSIZE if too small. */

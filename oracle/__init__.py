@@ -16,7 +16,7 @@ _lib = None
 SQUARE2D, CUBIC3D, CHIMERA, EXPLICIT = 0, 1, 2, 3
 J_INT8, J_F32 = 0, 1
 FLAG_2A, FLAG_PT, FLAG_SKIP_METRO, FLAG_MEASURE = 1, 2, 8, 16
-OBS_BINS, OBS_FIELDS = 32, 3
+OBS_BINS, OBS_FIELDS = 32, 4
 
 
 class _Params(ctypes.Structure):
@@ -187,8 +187,9 @@ class Sim:
         return st.as_dict()
 
     def observables(self):
-        """(sums [32][K][R/2][3], counts [32]): per logarithmic time bin and pair
-        of chains, E_a + E_b (raw), N_b q_l, q^2 summed over the steps in the bin."""
+        """(sums [32][K][R/2][4], counts [32]): per logarithmic time bin and pair
+        of chains, E_a + E_b (raw), N_b q_l, q^2 and the potential cluster sites
+        min(n, N - n) summed over the steps in the bin."""
         sums = np.zeros((OBS_BINS, self.K, self.R // 2, OBS_FIELDS), dtype=np.int64)
         counts = np.zeros(OBS_BINS, dtype=np.int64)
         self._lib.orc_get_observables(self._h, _ptr(sums), _ptr(counts))

@@ -69,7 +69,7 @@ struct orc_sim {
   uint32_t sweep = 0;
   orc_stats stats{};
   std::vector<std::vector<int32_t>> last_labels;  // [Kc*R/2][N]
-  std::vector<int64_t> obs;                // [32][K][R/2][3] observable sums
+  std::vector<int64_t> obs;                // [32][K][R/2][4] observable sums
   std::vector<int64_t> obs_count;          // [32] samples per time bin
   std::vector<int32_t> last_seed, last_nminus;
   int jexp = 0;                            // float couplings: grid 2^-jexp
@@ -422,8 +422,11 @@ void orc_set_states(orc_sim* s, const int8_t* spins, uint32_t sweep0) {
 // Observables of the "Benchmark model and observables" paragraph, for the two
 // replicas (chains 2p, 2p+1) at each temperature after a step: the energies,
 // the link overlap's numerator sum_bonds s_a,i s_a,j s_b,i s_b,j (q_l times
-// N_b) and the squared spin overlap, summed per logarithmic time bin.  E(q_l)
-// of Eq. 1 and Delta of Eq. 2 follow from these sums and the bin counts.
+// N_b), the squared spin overlap and the number of potential cluster sites
+// (sites of negative overlap after step 2a's reversal, i.e. min(n, N - n) for
+// n sites where the replicas differ: the fraction p the paper plots against T
+// is this count over N), summed per logarithmic time bin.  E(q_l) of Eq. 1 and
+// Delta of Eq. 2 follow from these sums and the bin counts.
 void measure(orc_sim* s, uint32_t t_after) {
   if (s->obs.empty()) {
     s->obs.assign((size_t)ORC_OBS_BINS * s->K * (s->R / 2) * ORC_OBS_FIELDS, 0);
@@ -447,6 +450,8 @@ void measure(orc_sim* s, uint32_t t_after) {
       o[0] += s->energy[a] + s->energy[b];
       o[1] += link;
       o[2] += qsum * qsum;
+      const int64_t nminus = ((int64_t)s->N - qsum) / 2;
+      o[3] += std::min(nminus, (int64_t)s->N - nminus);
     }
 }
 

@@ -33,7 +33,7 @@ enum { ORC_J_INT8 = 0, ORC_J_F32 = 1 };
    "Benchmark model and observables" paragraph per temperature and replica
    pair into logarithmic time bins (orc_get_observables). */
 enum { ORC_FLAG_2A = 1, ORC_FLAG_PT = 2, ORC_FLAG_SKIP_METRO = 8, ORC_FLAG_MEASURE = 16 };
-enum { ORC_OBS_BINS = 32, ORC_OBS_FIELDS = 3 };
+enum { ORC_OBS_BINS = 32, ORC_OBS_FIELDS = 4 };
 
 typedef struct {
   int32_t topology;    /* ORC_SQUARE2D / ORC_CUBIC3D / ORC_CHIMERA / ORC_EXPLICIT */
@@ -116,7 +116,8 @@ void orc_bonds(const orc_sim* s, int32_t* bonds_ij, int64_t* j_raw);
    bin floor(log2 t).  Fields per pair of chains (2p, 2p+1) at temperature k:
    0: E_a + E_b (raw energy units), 1: sum over bonds of q_i q_j = N_b - 2 D
    (D = bonds whose ends have different site overlaps q_i = s_a,i s_b,i),
-   2: (sum_i q_i)^2. */
+   2: (sum_i q_i)^2, 3: min(n, N - n) for n sites with q_i = -1 (the potential
+   cluster sites after step 2a). */
 void orc_get_observables(const orc_sim* s, int64_t* sums, int64_t* counts);
 
 /* Metropolis acceptance as a 2^-32 fraction for a raw energy change dE

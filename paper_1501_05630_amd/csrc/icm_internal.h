@@ -57,7 +57,7 @@ struct UnitDesc {
 };
 
 constexpr uint32_t kFlag2a = 1, kFlagPt = 2, kFlagRecord = 4, kFlagSkipMetro = 8, kFlagMeasure = 16;
-constexpr int kObsBins = 32, kObsFields = 3;
+constexpr int kObsBins = 32, kObsFields = 4;
 
 ICM_HD uint32_t align16(uint32_t x) { return (x + 15u) & ~15u; }
 

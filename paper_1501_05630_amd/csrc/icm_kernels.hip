@@ -575,6 +575,7 @@ __device__ __noinline__ void measure_step(uint32_t t_end, int N, int K, int R, i
       o[0] += ea + eb;
       o[1] += (int64_t)nbonds - 2 * D;
       o[2] += q * q;
+      o[3] += n < N - n ? n : N - n;  // potential cluster sites after step 2a
     }
     wave_sync();
   }

@@ -18,7 +18,7 @@ ICM_E_NOTFOUND, ICM_E_BUSY, ICM_E_BUFSIZE = -4, -5, -6
 TOPO_SQUARE2D, TOPO_CUBIC3D, TOPO_CHIMERA = 0, 1, 2
 J_INT8, J_F32 = 0, 1
 FLAG_2A, FLAG_PT, FLAG_RECORD_LABELS, FLAG_SKIP_METRO, FLAG_MEASURE = 1, 2, 4, 8, 16
-OBS_BINS, OBS_FIELDS = 32, 3
+OBS_BINS, OBS_FIELDS = 32, 4
 
 _P = ctypes.c_void_p
 _I32, _U32, _U64, _SZ = ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_size_t
@@ -252,7 +252,7 @@ class Context:
         return st.as_dict()
 
     def icm_read_observables(self, h):
-        """(sums [32][K][R/2][3] int64, counts [32] int64); see icm_read_observables."""
+        """(sums [32][K][R/2][4] int64, counts [32] int64); see icm_read_observables."""
         m = self.meta[h]
         sums = np.zeros((OBS_BINS, m["K"], m["R"] // 2, OBS_FIELDS), dtype=np.int64)
         counts = np.zeros(OBS_BINS, dtype=np.int64)
@@ -308,3 +308,29 @@ def delta_per_bin(sums, counts, temps, n_sites, n_bonds, energy_unit):
         e = sums[:, :, :, 0].mean(axis=2) * energy_unit / (2.0 * n_sites * c)
         e_ql = -(1.0 / np.asarray(temps, dtype=np.float64))[None, :] * (n_bonds / n_sites) * (1.0 - ql)
     return e_ql, e, e_ql - e
+
+
+def cluster_fraction_per_bin(sums, counts, n_sites):
+    """The fraction p of potential cluster sites (sites of negative overlap after
+    step 2a) per time bin and temperature, [bins][K], averaged over the replica
+    pairs, from the observable sums of one instance.  Bins without samples are
+    NaN."""
+    sums = np.asarray(sums, dtype=np.float64)
+    c = np.asarray(counts, dtype=np.float64)[:, None]
+    with np.errstate(invalid="ignore", divide="ignore"):
+        return sums[:, :, :, 3].mean(axis=2) / (n_sites * c)
+
+
+def thermalization_bin(mean, se, complete, n_se=2.0):
+    """First time bin from which a disorder-averaged Delta stays at zero: the
+    smallest b such that every complete bin b' >= b has |mean[b']| <= n_se
+    se[b'] (the paper deems a system thermalized once Delta ~ 0 and read the
+    times off by eye).  None if the last complete bin is not at zero yet."""
+    bins = [b for b in range(len(mean)) if complete[b]]
+    first = None
+    for b in reversed(bins):
+        if abs(mean[b]) <= n_se * se[b]:
+            first = b
+        else:
+            break
+    return first

@@ -114,6 +114,20 @@ WORKLOADS = {
                                      per_side=256, kind="gauss", j_scale=1,
                                      n_temps=24, t_min=0.2, t_max=2.0, n_replicas=4,
                                      n_sweeps=1 << 13, n_instances=1536),
+    # the paper's simulation parameters (Table I): Gaussian disorder, two
+    # replicas per temperature, ICM at the n_icm coldest temperatures; per_side
+    # is the table's number of disorder instances per size, of which an
+    # experiment takes the first few of every size
+    "table1_2d_gauss": dict(config=5, topology=SQUARE2D, L=None, sides=(16, 24, 32), per_side=10000,
+                            kind="gauss", j_scale=1, n_temps=30, t_min=0.2120, t_max=1.6325,
+                            n_replicas=2, n_icm=30, n_sweeps=1 << 22, n_instances=30000),
+    "table1_chimera_gauss": dict(config=6, topology=CHIMERA, L=None, sides=(4, 6, 8, 10, 12),
+                                 per_side=10000, kind="gauss", j_scale=1, n_temps=30, t_min=0.2120,
+                                 t_max=1.6325, n_replicas=2, n_icm=19, n_sweeps=1 << 22,
+                                 n_instances=50000),
+    "table1_3d_gauss": dict(config=7, topology=CUBIC3D, L=None, sides=(4, 6, 8, 10, 12), per_side=15000,
+                            kind="gauss", j_scale=1, n_temps=26, t_min=0.42, t_max=1.8,
+                            n_replicas=2, n_icm=13, n_sweeps=1 << 23, n_instances=75000),
 }
 
 
@@ -141,4 +155,5 @@ def workload_instance(name, instance_index, L=None):
     rng = make_rng(spec["config"], instance_index)
     J = make_couplings(spec["kind"], spec["topology"], spec["L"], rng)
     temps = geometric_temps(spec["t_min"], spec["t_max"], spec["n_temps"])
-    return J, temps, icm_cutoff(temps), spec
+    kc = spec["n_icm"] if "n_icm" in spec else icm_cutoff(temps)
+    return J, temps, kc, spec

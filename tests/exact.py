@@ -116,3 +116,23 @@ def binned_mean_se(x, n_bins=32):
     m = len(x) // n_bins
     b = x[: m * n_bins].reshape(n_bins, m).mean(axis=1)
     return float(b.mean()), float(b.std(ddof=1) / np.sqrt(n_bins))
+
+
+def walsh_hadamard(v):
+    """Unnormalised fast Walsh-Hadamard transform of a length-2^N vector."""
+    a = np.array(v, dtype=np.float64)
+    h = 1
+    while h < len(a):
+        a = a.reshape(-1, 2, h)
+        a = np.stack((a[:, 0] + a[:, 1], a[:, 0] - a[:, 1]), axis=1).reshape(-1)
+        h *= 2
+    return a
+
+
+def pair_difference_distribution(w):
+    """For two independent replicas with state weights w (indexed as all_states),
+    the probability of each difference pattern d (bit i set <=> the replicas
+    differ at site i): sum_x w(x) w(x xor d), an xor autocorrelation computed
+    through the Walsh-Hadamard transform."""
+    f = walsh_hadamard(w)
+    return walsh_hadamard(f * f) / len(f)

@@ -2,12 +2,15 @@
 logarithmic time bin; "Benchmark model and observables" paragraph, Eq. 1-2).
 
 - frozen states (no Metropolis, ICM or PT): every sample equals a closed form
-  (identical or reversed replicas give N_b and N^2; one differing site gives
-  N_b - 2 deg(i) and (N - 2)^2; random replicas the bond sum over an
-  independently built bond list); bin counts are the sizes of [2^b, 2^(b+1));
-- the thermal link overlap and squared overlap of two independent replicas
-  equal the exact enumeration values (1/N_b) sum_bonds <s_i s_j>^2 and
-  sum_ij <s_i s_j>^2 within 4 standard errors;
+  (identical or reversed replicas give N_b, N^2 and no potential cluster
+  site; one differing site gives N_b - 2 deg(i), (N - 2)^2 and one site;
+  random replicas the bond sum over an independently built bond list and
+  min(n, N - n)); bin counts are the sizes of [2^b, 2^(b+1));
+- the thermal link overlap, squared overlap and potential-cluster-site count
+  of two independent replicas equal the exact enumeration values
+  (1/N_b) sum_bonds <s_i s_j>^2, sum_ij <s_i s_j>^2 and the mean of
+  min(n, N - n) over the exact distribution of difference patterns, within 4
+  standard errors;
 - Eq. 1 read with H = -sum J s s: for Gaussian disorder the exact
   disorder-averaged Delta of Eq. 2 vanishes within its sampling error.
 """
@@ -59,19 +62,22 @@ def test_frozen_states_give_closed_forms(top, L, kind, scale):
     deg = sum((i == i0) + (j == i0) for i, j, _ in bonds)
     q_rnd = a.astype(np.int64) * rnd
     link_rnd = sum(int(q_rnd[i] * q_rnd[j]) for i, j, _ in bonds)
-    expect = {(0, 0): (Nb, N * N), (0, 1): (Nb, N * N), (1, 0): (Nb - 2 * deg, (N - 2) ** 2),
-              (1, 1): (link_rnd, int(q_rnd.sum()) ** 2)}
+    n_rnd = int(np.sum(a != rnd))
+    expect = {(0, 0): (Nb, N * N, 0), (0, 1): (Nb, N * N, 0), (1, 0): (Nb - 2 * deg, (N - 2) ** 2, 1),
+              (1, 1): (link_rnd, int(q_rnd.sum()) ** 2, min(n_rnd, N - n_rnd))}
     total = counts.sum()
-    for (k, p), (link, q2) in expect.items():
+    for (k, p), (link, q2, ncl) in expect.items():
         assert sums[:, k, p, 1].sum() == link * total, (k, p)
         assert sums[:, k, p, 2].sum() == q2 * total, (k, p)
+        assert sums[:, k, p, 3].sum() == ncl * total, (k, p)
         ea = exact.energy(top, L, np.asarray(J, np.float64) / scale, st[k, 2 * p])
         eb = exact.energy(top, L, np.asarray(J, np.float64) / scale, st[k, 2 * p + 1])
         assert sums[:, k, p, 0].sum() == round((ea + eb) * scale) * total, (k, p)
 
 
 def exact_pair_observables(top, L, J, temps):
-    """Exact <H>, <q_l> and <q^2> of two independent replicas by enumeration."""
+    """Exact <H>, <q_l>, <q^2> and <min(n, N - n)> of two independent replicas
+    by enumeration (n = sites where the replicas differ)."""
     N = inputs.n_sites(top, L)
     bonds = exact.bond_list(top, L, np.asarray(J, np.float64))
     S = exact.all_states(N).astype(np.float64)
@@ -83,7 +89,12 @@ def exact_pair_observables(top, L, J, temps):
         corr = (S * w[:, None]).T @ S                      # <s_i s_j>
         ql = np.mean([corr[i, j] ** 2 for i, j, _ in bonds])
         q2 = float(np.sum(corr ** 2))
-        out.append((float(np.sum(w * E)), ql, q2))
+        pd = exact.pair_difference_distribution(w)
+        n = np.array([bin(d).count("1") for d in range(len(pd))])
+        ncl = float(np.sum(pd * np.minimum(n, N - n)))
+        q2_from_pd = float(np.sum(pd * (N - 2 * n) ** 2))
+        assert abs(q2_from_pd - q2) < 1e-9 * N * N      # the two exact routes agree
+        out.append((float(np.sum(w * E)), ql, q2, ncl))
     return np.array(out), len(bonds), N
 
 
@@ -100,7 +111,7 @@ def test_link_and_spin_overlap_match_exact_enumeration():
     for _ in range(40):
         s.run(2048)
         cur, _ = s.observables()
-        blocks.append((cur - prev).sum(axis=0)[:, 0, :] / 2048.0)   # [K][3] per sample
+        blocks.append((cur - prev).sum(axis=0)[:, 0, :] / 2048.0)   # [K][4] per sample
         prev = cur
     b = np.array(blocks)
     m, se = b.mean(axis=0), b.std(axis=0, ddof=1) / np.sqrt(len(b))
@@ -108,6 +119,7 @@ def test_link_and_spin_overlap_match_exact_enumeration():
     for k in range(len(temps)):
         assert abs(ql[k] - ref[k, 1]) < 4 * se[k, 1] / Nb + 1e-9, (k, ql[k], ref[k, 1])
         assert abs(q2[k] - ref[k, 2]) < 4 * se[k, 2] + 1e-9, (k, q2[k], ref[k, 2])
+        assert abs(m[k, 3] - ref[k, 3]) < 4 * se[k, 3] + 1e-9, (k, m[k, 3], ref[k, 3])
         e = m[k, 0] * 2.0 ** -32 / 2        # raw units of the 2^-32 grid, two replicas
         assert abs(e - ref[k, 0]) < 4 * se[k, 0] * 2.0 ** -32 / 2 + 1e-9, (k, e, ref[k, 0])
 
@@ -151,3 +163,23 @@ def test_delta_helper_reproduces_eq_1_and_2_from_the_sums():
             assert abs(e_ql[b, k] - ref_eql) < 1e-12
             assert abs(e[b, k] - ref_e) < 1e-6
             assert abs(delta[b, k] - (ref_eql - ref_e)) < 1e-6
+    # the cluster-site fraction helper: on frozen states every sample is
+    # min(n, N - n) / N of the held pair
+    p = icm.cluster_fraction_per_bin(sums, counts, s.N)
+    for k in range(len(temps)):
+        n = int(np.sum(st[k, 0] != st[k, 1]))
+        for b in np.flatnonzero(counts):
+            assert abs(p[b, k] - min(n, s.N - n) / s.N) < 1e-12
+
+
+def test_thermalization_bin_reads_the_first_bin_that_stays_at_zero():
+    from paper_1501_05630_amd import icm
+    se = np.full(8, 0.1)
+    full = [True] * 8
+    assert icm.thermalization_bin(np.array([-3, -2, -1, -0.5, -0.15, -0.1, 0.05, -0.02]), se, full) == 4
+    # a later excursion resets the start; the last bin off zero means not yet
+    assert icm.thermalization_bin(np.array([-3, -0.1, 0.0, -0.5, -0.1, 0.0, 0.0, 0.0]), se, full) == 4
+    assert icm.thermalization_bin(np.array([-3, -0.1, 0.0, 0.0, 0.0, 0.0, 0.0, -0.9]), se, full) is None
+    # incomplete bins are skipped
+    part = [True] * 7 + [False]
+    assert icm.thermalization_bin(np.array([-3, -2, -0.1, 0, 0, 0, 0, -5.0]), se, part) == 2
