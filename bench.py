@@ -51,6 +51,8 @@ def parse():
                          "sweeps instead (PT vs PT + ICM per topology and size)")
     ap.add_argument("--table1-instances", type=int, default=128, help="disorder instances per size")
     ap.add_argument("--table1-topologies", default="2d,chimera,3d")
+    ap.add_argument("--percolation", type=int, default=0,
+                    help="run the site-percolation Binder study with this many samples per (size, p) instead")
     return ap.parse_args()
 
 
@@ -342,8 +344,80 @@ def run_table1(args):
     return out
 
 
+# Site-percolation study: sizes and occupation probabilities around the
+# thresholds (chimera: the paper's own estimate; square and cubic lattices: the
+# values the paper quotes from the literature)
+PERCOLATION = {
+    "chimera": dict(topology=2, sides=(4, 6, 8, 12, 16, 22), p=(0.36, 0.41), p_ref=0.3866, nu_ref=1.39,
+                    fit_from=12),
+    "2d": dict(topology=0, sides=(16, 32, 64), p=(0.57, 0.62), p_ref=0.592, nu_ref=4 / 3, fit_from=16),
+    # cubic lattice: with sqrt(N) as the length the exponent is 3/2 of the usual nu
+    "3d": dict(topology=1, sides=(8, 12, 16), p=(0.29, 0.33), p_ref=0.311, nu_ref=1.3, fit_from=8),
+}
+
+
+def run_percolation(args):
+    """The Binder ratio g(p, N) of the largest cluster of random site
+    configurations on a grid of p for several sizes per topology, the p where
+    the curves of consecutive sizes cross (estimates of p_c), and the
+    throughput of the percolation kernel in samples/s."""
+    import numpy as np
+    import torch
+
+    from paper_1501_05630_amd import icm, inputs
+    n = args.percolation
+    ctx = icm.Context(arena_bytes=64 << 20, seed=inputs.MASTER_SEED)
+    out = {"metric": "site percolation: Binder ratio g = (3 - <s^4>/<s^2>^2)/2 of the largest cluster",
+           "samples_per_point": n}
+    buf = torch.empty(n, dtype=torch.int32, device="cuda")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for name, cfg in PERCOLATION.items():
+        ps = np.linspace(cfg["p"][0], cfg["p"][1], 11)
+        res, g_all = {}, []
+        for L in cfg["sides"]:
+            N = inputs.n_sites(cfg["topology"], L)
+            gs, ses, ms = [], [], 0.0
+            for pi, p in enumerate(ps):
+                e0.record(ctx.stream)
+                ctx.icm_percolation_smax(cfg["topology"], L, float(p), n, sample0=pi * n, key=L, out=buf)
+                e1.record(ctx.stream)
+                s = buf.cpu().numpy()
+                ms += e0.elapsed_time(e1)
+                gs.append(float(icm.binder_ratio(s)))
+                # standard error from 16 blocks of samples
+                blocks = [icm.binder_ratio(b) for b in np.array_split(s, 16)]
+                ses.append(float(np.std(blocks, ddof=1) / 4.0))
+            g_all.append(np.array(gs))
+            res[str(L)] = {"N": N, "g": gs, "se": ses,
+                           "samples_per_s": len(ps) * n / (ms * 1e-3)}
+            print(f"percolation {name} L={L}: {len(ps) * n / (ms * 1e-3):.3g} samples/s",
+                  file=sys.stderr, flush=True)
+        crossings = []
+        for a in range(len(cfg["sides"]) - 1):
+            d = g_all[a + 1] - g_all[a]
+            x = None
+            for i in range(len(ps) - 1):
+                if d[i] <= 0 < d[i + 1] or d[i] >= 0 > d[i + 1]:
+                    x = float(ps[i] + (ps[i + 1] - ps[i]) * d[i] / (d[i] - d[i + 1]))
+                    break
+            crossings.append({"sizes": [cfg["sides"][a], cfg["sides"][a + 1]], "p_cross": x})
+        fit = [L for L in cfg["sides"] if L >= cfg["fit_from"]]
+        pc, nu, chi2 = icm.binder_collapse(ps, [res[str(L)]["N"] for L in fit], [res[str(L)]["g"] for L in fit],
+                                           [res[str(L)]["se"] for L in fit], cfg["p_ref"], cfg["nu_ref"])
+        out[name] = {"p": [float(x) for x in ps], "p_ref": cfg["p_ref"], "sizes": res, "crossings": crossings,
+                     "collapse": {"sides": fit, "p_c": pc, "nu_sqrtN": nu, "chi2_per_dof": chi2}}
+    ctx.close()
+    return out
+
+
 def main():
     args = parse()
+    if args.percolation:
+        if args.gpus != 1:
+            print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+            sys.exit(2)
+        print(json.dumps(run_percolation(args)), flush=True)
+        return
     if args.table1:
         if args.gpus != 1:
             print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))

@@ -204,6 +204,24 @@ int icm_read_observables(icm_ctx* ctx, int32_t handle, int64_t* sums, int64_t* c
 int icm_read_walkers(icm_ctx* ctx, int32_t handle, int32_t* out, size_t cap);
 uint32_t icm_sweep_index(icm_ctx* ctx, int32_t handle);
 
+/* Site percolation on a topology, the study behind the paper's chimera
+   percolation threshold (Supplemental Material: the relative size of the
+   largest cluster as order parameter, its Binder ratio
+   g = (3 - <s_max^4> / <s_max^2>^2) / 2 over random site configurations).
+   Sample s (s = 0 .. n_samples-1) occupies site i independently with
+   probability p: word i mod 4 of Philox4x32-10 with counter
+   (sample0 + s, i / 4, 0, 4) and key (context seed, key) is below
+   floor(p 2^32).  smax[s] = the number of sites in the largest connected
+   cluster of occupied sites (0 if none).  topology / L as in
+   icm_instance_desc; p in [0, 1].  smax: DEVICE pointer, int32
+   [n_samples], owned by the caller; written asynchronously on the context
+   stream (icm_sync, or any later call that synchronizes, completes it).
+   Errors: ICM_E_INVALID (topology, size, p, null smax, sample range beyond
+   2^32), ICM_E_BUSY while serving, ICM_E_NOMEM (neighbour table does not fit
+   the arena), ICM_E_DEVICE. */
+int icm_percolation_smax(icm_ctx* ctx, int32_t topology, int32_t L, double p, uint32_t sample0,
+                         uint32_t n_samples, uint32_t key, int32_t* smax);
+
 /* Serving: a request = descriptor + n_sweeps from a hot start.  The loop
    admits requests at sweep-block boundaries while the arena has room, keeps
    their state on the device, runs them batched with whatever else is

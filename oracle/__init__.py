@@ -80,6 +80,8 @@ def _load():
     lib.orc_get_observables.argtypes = [P, P, P]
     lib.orc_metro_accept_count.argtypes = [P, I32, I64]
     lib.orc_metro_accept_count.restype = ctypes.c_uint64
+    lib.orc_percolation_smax.argtypes = [P, ctypes.c_double, U32, U32, P]
+    lib.orc_percolation_smax.restype = None
     _lib = lib
     return lib
 
@@ -223,3 +225,10 @@ class Sim:
 
     def metro_accept_count(self, k, dE_raw):
         return int(self._lib.orc_metro_accept_count(self._h, k, int(dE_raw)))
+
+    def percolation_smax(self, p, n_samples, sample0=0):
+        """Largest-cluster sizes [n_samples] of random site configurations on
+        this simulation's graph (key = seed, instance_key)."""
+        out = np.zeros(n_samples, dtype=np.int32)
+        self._lib.orc_percolation_smax(self._h, float(p), sample0, n_samples, _ptr(out))
+        return out

@@ -48,7 +48,7 @@ void philox(const uint32_t in[4], const uint32_t key_in[2], uint32_t out[4]) {
 }
 
 // Random-stream purposes (counter word 3).
-enum { kMetro = 0, kInit = 1, kIcm = 2, kPt = 3 };
+enum { kMetro = 0, kInit = 1, kIcm = 2, kPt = 3, kPerc = 4 };
 
 struct Bond { int32_t i, j; int64_t raw; };
 
@@ -517,6 +517,34 @@ void orc_get_observables(const orc_sim* s, int64_t* sums, int64_t* counts) {
   const size_t n = (size_t)ORC_OBS_BINS * s->K * (s->R / 2) * ORC_OBS_FIELDS;
   for (size_t x = 0; x < n; ++x) sums[x] = s->obs.empty() ? 0 : s->obs[x];
   for (int b = 0; b < ORC_OBS_BINS; ++b) counts[b] = s->obs_count.empty() ? 0 : s->obs_count[b];
+}
+
+// Site percolation on the simulation's graph (Supplemental Material: the
+// largest cluster of randomly occupied sites, whose Binder ratio locates the
+// chimera percolation threshold).  Every site is occupied independently with
+// probability p: the Philox word for site i of sample n is compared with
+// floor(p 2^32); the occupied sites are split into connected components by
+// breadth-first search, and the largest component's size is reported.
+void orc_percolation_smax(const orc_sim* s, double p, uint32_t sample0, uint32_t n_samples, int32_t* out) {
+  const uint64_t thr = (uint64_t)std::floor(p * 4294967296.0);
+  const uint32_t key[2] = {s->p.seed, s->p.instance_key};
+  std::vector<char> occupied(s->N);
+  std::vector<int32_t> label;
+  std::vector<int32_t> size(s->N);
+  for (uint32_t n = 0; n < n_samples; ++n) {
+    for (int i = 0; i < s->N; ++i) {
+      const uint32_t ctr[4] = {sample0 + n, (uint32_t)(i / 4), 0u, (uint32_t)kPerc};
+      uint32_t r[4];
+      philox(ctr, key, r);
+      occupied[i] = (uint64_t)r[i % 4] < thr;
+    }
+    label_components(s, occupied, label);
+    std::fill(size.begin(), size.end(), 0);
+    int32_t best = 0;
+    for (int i = 0; i < s->N; ++i)
+      if (label[i] >= 0) best = std::max(best, ++size[label[i]]);
+    out[n] = best;
+  }
 }
 
 uint64_t orc_metro_accept_count(const orc_sim* s, int32_t k, int64_t dE) {

@@ -120,6 +120,13 @@ void orc_bonds(const orc_sim* s, int32_t* bonds_ij, int64_t* j_raw);
    cluster sites after step 2a). */
 void orc_get_observables(const orc_sim* s, int64_t* sums, int64_t* counts);
 
+/* Site percolation on this simulation's graph: for samples n = sample0 ..
+   sample0 + n_samples - 1, site i is occupied iff word i mod 4 of
+   Philox4x32-10 with counter (n, i / 4, 0, 4) and key (seed, instance_key)
+   is below floor(p 2^32); out[n - sample0] = size of the largest connected
+   cluster of occupied sites. */
+void orc_percolation_smax(const orc_sim* s, double p, uint32_t sample0, uint32_t n_samples, int32_t* out);
+
 /* Metropolis acceptance as a 2^-32 fraction for a raw energy change dE
    at temperature index k: returns the number of u in [0, 2^32) accepted. */
 uint64_t orc_metro_accept_count(const orc_sim* s, int32_t k, int64_t dE_raw);

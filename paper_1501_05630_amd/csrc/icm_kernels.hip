@@ -56,7 +56,7 @@ __device__ __forceinline__ Words4 philox4x32_10(uint32_t x0, uint32_t x1, uint32
   return r;
 }
 
-enum : uint32_t { kStreamMetro = 0, kStreamInit = 1, kStreamIcm = 2, kStreamPt = 3 };
+enum : uint32_t { kStreamMetro = 0, kStreamInit = 1, kStreamIcm = 2, kStreamPt = 3, kStreamPerc = 4 };
 
 // ----------------------------------------------------------------------------
 // wavefront helpers (wave64)
@@ -1461,6 +1461,68 @@ __global__ void energy_kernel(const uint32_t* spins, const uint16_t* nbr, const 
   if (threadIdx.x == 0) energy[w] = part[0] / 2;
 }
 
+// ----------------------------------------------------------------------------
+// Site percolation (the chimera threshold study of the Supplemental Material):
+// each sample occupies every site independently with probability p and
+// reports the size of its largest cluster of occupied sites.  One wave per
+// sample (workgroups of 64 lanes, a grid-stride loop over samples): site i is
+// occupied iff word i mod 4 of Philox(sample, i / 4, 0, 4) is below
+// floor(p 2^32); union-find over the bonds between occupied sites (hooking to
+// the smaller root), the component sizes by LDS atomics at the roots, then a
+// wave maximum.  LDS: parent and size arrays of N ints.
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const int y = __shfl_xor(v, o, 64);
+    v = y > v ? y : v;
+  }
+  return v;
+}
+
+__global__ void __launch_bounds__(64) percolation_kernel(const uint16_t* __restrict__ nbr, int N, int deg,
+                                                         unsigned long long thr, uint32_t sample0,
+                                                         uint32_t n_samples, uint32_t seed, uint32_t key,
+                                                         int32_t* __restrict__ smax) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  int* parent = (int*)lds;  // -1: empty site
+  int* size = parent + N;
+  const int lane = lane_id();
+  for (uint32_t s = blockIdx.x; s < n_samples; s += gridDim.x) {
+    const uint32_t sample = sample0 + s;
+    for (int q = lane; 4 * q < N; q += 64) {
+      const Words4 u = philox4x32_10(sample, (uint32_t)q, 0u, kStreamPerc, seed, key);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int i = 4 * q + b;
+        if (i < N) {
+          parent[i] = (unsigned long long)u.w[b] < thr ? i : -1;
+          size[i] = 0;
+        }
+      }
+    }
+    wave_sync();
+    // each bond once, from its smaller end; an empty site never changes, an
+    // occupied one always holds a site index
+    for (int i = lane; i < N; i += 64) {
+      if (uf_load(parent, i) < 0) continue;
+      for (int d = 0; d < deg; ++d) {
+        const int j = nbr[i * deg + d];
+        if (j > i && uf_load(parent, j) >= 0) uf_union(parent, i, j);
+      }
+    }
+    wave_sync();
+    for (int i = lane; i < N; i += 64)
+      if (uf_load(parent, i) >= 0) atomicAdd(&size[uf_find(parent, i)], 1);
+    wave_sync();
+    int m = 0;
+    for (int i = lane; i < N; i += 64) m = size[i] > m ? size[i] : m;
+    m = wave_max(m);
+    if (lane == 0) smax[s] = m;
+    wave_sync();
+  }
+}
+
 }  // namespace icm
 
 // ----------------------------------------------------------------------------
@@ -1520,6 +1582,18 @@ int icmk_launch_scatter(uint32_t* spins, const int8_t* src, int N, int Wq, int W
   const int n = Wq * N;
   hipLaunchKernelGGL(icm::scatter_spins_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, spins,
                      src, N, Wq, W);
+  return (int)hipGetLastError();
+}
+
+int icmk_launch_percolation(const uint16_t* nbr, int N, int deg, unsigned long long thr, uint32_t sample0,
+                            uint32_t n_samples, uint32_t seed, uint32_t key, int32_t* smax, int n_blocks,
+                            hipStream_t stream) {
+  if (n_samples == 0) return 0;
+  if (N < 1 || N > icm::kMaxSites || n_blocks < 1) return (int)hipErrorInvalidValue;
+  const size_t lds = 8u * (size_t)N;  // at most 32 KiB
+  const uint32_t g = n_samples < (uint32_t)n_blocks ? n_samples : (uint32_t)n_blocks;
+  hipLaunchKernelGGL(icm::percolation_kernel, dim3(g), dim3(64), lds, stream, nbr, N, deg, thr, sample0,
+                     n_samples, seed, key, smax);
   return (int)hipGetLastError();
 }
 

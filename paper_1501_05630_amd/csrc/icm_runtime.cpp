@@ -34,6 +34,9 @@ int icmk_launch_scatter(uint32_t* spins, const int8_t* src, int N, int Wq, int W
                         hipStream_t stream);
 int icmk_launch_energy(const uint32_t* spins, const uint16_t* nbr, const void* coup, int N, int deg,
                        int Wp, int jkind, int jexp, int64_t* energy, hipStream_t stream);
+int icmk_launch_percolation(const uint16_t* nbr, int N, int deg, unsigned long long thr, uint32_t sample0,
+                            uint32_t n_samples, uint32_t seed, uint32_t key, int32_t* smax, int n_blocks,
+                            hipStream_t stream);
 }
 
 namespace {
@@ -986,6 +989,24 @@ int icm_init_states(icm_ctx* c, int32_t h) {
   KERNEL_OK(c, icmk_launch_energy(in->unit.spins, in->unit.nbr, in->unit.coup, in->N, in->deg, in->Wp,
                                   in->jkind, in->jexp, in->unit.energy, c->stream));
   HIP_OK(c, hipStreamSynchronize(c->stream));
+  return ICM_OK;
+}
+
+int icm_percolation_smax(icm_ctx* c, int32_t topology, int32_t L, double p, uint32_t sample0,
+                         uint32_t n_samples, uint32_t key, int32_t* smax) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (c->serving) return fail(c, ICM_E_BUSY, "the serving loop owns the context");
+  if (!(p >= 0.0 && p <= 1.0)) return fail(c, ICM_E_INVALID, "occupation probability outside [0, 1]");
+  if (n_samples > 0 && !smax) return fail(c, ICM_E_INVALID, "null output");
+  if ((uint64_t)sample0 + n_samples > (1ull << 32))
+    return fail(c, ICM_E_INVALID, "sample indices beyond 2^32");
+  Topology* T = get_topology(c, topology, L, rc);
+  if (!T) return fail(c, rc, "invalid topology or size");
+  // floor(p 2^32) is exact in double: p scaled by a power of two
+  const unsigned long long thr = (unsigned long long)std::floor(p * 4294967296.0);
+  KERNEL_OK(c, icmk_launch_percolation(T->d_nbr, T->N, T->deg, thr, sample0, n_samples, c->seed, key, smax,
+                                       16 * c->n_cus, c->stream));
   return ICM_OK;
 }
 

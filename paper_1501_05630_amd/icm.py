@@ -65,6 +65,7 @@ EXPORTS = {
     "icm_read_observables": (ctypes.c_int, [_P, _I32, _P, _P, _SZ]),
     "icm_read_walkers": (ctypes.c_int, [_P, _I32, _P, _SZ]),
     "icm_sweep_index": (_U32, [_P, _I32]),
+    "icm_percolation_smax": (ctypes.c_int, [_P, _I32, _I32, ctypes.c_double, _U32, _U32, _U32, _P]),
     "icm_serve_start": (ctypes.c_int, [_P, _I32]),
     "icm_serve_stop": (ctypes.c_int, [_P]),
     "icm_submit": (ctypes.c_int, [_P, ctypes.POINTER(InstanceDesc), _U32, ctypes.POINTER(_U64)]),
@@ -263,6 +264,21 @@ class Context:
     def icm_sweep_index(self, h):
         return int(self._lib.icm_sweep_index(self.h, h))
 
+    def icm_percolation_smax(self, topology, L, p, n_samples, sample0=0, key=0, out=None):
+        """Largest-cluster sizes of n_samples random site configurations
+        (icm_percolation_smax); returns a device int32 tensor [n_samples],
+        written on the context stream."""
+        t = self.torch
+        if out is None:
+            out = t.empty(n_samples, dtype=t.int32, device=self.arena.device)
+        if out.dtype != t.int32 or not out.is_contiguous() or out.numel() < n_samples \
+                or out.device != self.arena.device:
+            raise ValueError("out must be a contiguous int32 tensor on the context's device")
+        _check(self.h, self._lib.icm_percolation_smax(self.h, topology, L, float(p), sample0, n_samples, key,
+                                                      ctypes.c_void_p(out.data_ptr())),
+               "icm_percolation_smax")
+        return out
+
     def icm_arena_usage(self):
         used, total = _SZ(), _SZ()
         self._lib.icm_arena_usage(self.h, ctypes.byref(used), ctypes.byref(total))
@@ -334,3 +350,39 @@ def thermalization_bin(mean, se, complete, n_se=2.0):
         else:
             break
     return first
+
+
+def binder_ratio(smax):
+    """g = (3 - <s^4> / <s^2>^2) / 2 of the largest-cluster sizes of a set of
+    random configurations (the percolation Binder ratio of the Supplemental
+    Material; 1 when every configuration has the same s_max)."""
+    s = np.asarray(smax, dtype=np.float64)
+    m2, m4 = np.mean(s ** 2), np.mean(s ** 4)
+    return 0.5 * (3.0 - m4 / (m2 * m2))
+
+
+def binder_collapse(ps, sizes, g, se, p_c0, nu0, degree=3):
+    """Finite-size scaling of the percolation Binder ratio, g(p, N) =
+    G[N^(1/(2 nu)) (1/p - 1/p_c)] (the scaling form of the Supplemental
+    Material with sqrt(N) as the linear size): the (p_c, nu) for which one
+    polynomial of the scaling variable fits every size's curve best, by
+    weighted least squares.  ps [P]; sizes [S] (site counts N); g, se [S][P].
+    Returns (p_c, nu, chi2 per degree of freedom)."""
+    from scipy.optimize import minimize
+    ps = np.asarray(ps, dtype=np.float64)
+    g = np.asarray(g, dtype=np.float64)
+    se = np.asarray(se, dtype=np.float64)
+
+    def chi2(theta):
+        pc, nu = theta
+        if not (0 < pc < 1 and nu > 0.05):
+            return 1e30
+        x = np.concatenate([n ** (0.5 / nu) * (1.0 / ps - 1.0 / pc) for n in sizes])
+        y, w = g.reshape(-1), 1.0 / se.reshape(-1)
+        c = np.polyfit(x, y, degree, w=w)
+        return float(np.sum(((np.polyval(c, x) - y) * w) ** 2))
+
+    best = minimize(chi2, [p_c0, nu0], method="Nelder-Mead",
+                    options={"xatol": 1e-7, "fatol": 1e-9, "maxiter": 4000})
+    dof = g.size - (degree + 1) - 2
+    return float(best.x[0]), float(best.x[1]), best.fun / max(dof, 1)

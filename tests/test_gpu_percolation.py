@@ -1,0 +1,81 @@
+"""GPU parity of site percolation (icm_percolation_smax, through the C-ABI)
+against the CPU oracle: the largest-cluster size of every sample bit-exact,
+over the three topologies, sizes with ragged tails (N not a multiple of 4 or
+64 sites), occupation probabilities from empty to full, sample offsets, more
+samples than the grid holds, and, at the percolation study's largest sizes in
+its launch configuration, a spread of samples recomputed one by one."""
+import numpy as np
+import pytest
+
+import oracle as orc
+from paper_1501_05630_amd import icm, inputs
+
+pytestmark = pytest.mark.gpu
+SEED = inputs.MASTER_SEED
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = icm.Context(arena_bytes=256 << 20, seed=SEED)
+    yield c
+    c.close()
+
+
+def oracle_for(top, L, key):
+    kind, scale = ("int3", 3) if top == inputs.CHIMERA else ("pmJ", 1)
+    J = inputs.make_couplings(kind, top, L, inputs.make_rng(96, L))
+    return orc.Sim(top, L, J, [1.0], 2, 0, flags=0, seed=SEED, instance_key=key, j_scale=scale)
+
+
+CASES = [(inputs.SQUARE2D, 2), (inputs.SQUARE2D, 6), (inputs.SQUARE2D, 32), (inputs.SQUARE2D, 64),
+         (inputs.CUBIC3D, 2), (inputs.CUBIC3D, 6), (inputs.CUBIC3D, 10), (inputs.CUBIC3D, 16),
+         (inputs.CHIMERA, 1), (inputs.CHIMERA, 3), (inputs.CHIMERA, 7), (inputs.CHIMERA, 12),
+         (inputs.CHIMERA, 22)]
+
+
+@pytest.mark.parametrize("top,L", CASES)
+def test_smax_bit_exact(ctx, top, L):
+    key = 7 * L + top
+    o = oracle_for(top, L, key)
+    n = 400 if o.N <= 1024 else 120
+    for p in (0.0, 0.2, 0.3866, 0.5927, 1.0):
+        got = ctx.icm_percolation_smax(top, L, p, n, sample0=12345, key=key).cpu().numpy()
+        ref = o.percolation_smax(p, n, sample0=12345)
+        assert np.array_equal(got, ref), (p, np.flatnonzero(got != ref)[:5].tolist())
+
+
+def test_more_samples_than_the_grid(ctx):
+    # the grid holds 16 workgroups per compute unit; 9000 samples wrap around it
+    top, L, key = inputs.CHIMERA, 1, 3
+    o = oracle_for(top, L, key)
+    got = ctx.icm_percolation_smax(top, L, 0.45, 9000, sample0=0, key=key).cpu().numpy()
+    assert np.array_equal(got, o.percolation_smax(0.45, 9000, sample0=0))
+    # an offset batch continues the same sample sequence
+    tail = ctx.icm_percolation_smax(top, L, 0.45, 1000, sample0=8000, key=key).cpu().numpy()
+    assert np.array_equal(tail, got[8000:])
+
+
+def test_full_size_sampled(ctx):
+    # the study's largest sizes, 2^16 samples per launch: 64 samples spread over
+    # the launch, recomputed one at a time by the oracle
+    rng = np.random.default_rng(5)
+    for top, L, p in ((inputs.CHIMERA, 22, 0.3866), (inputs.SQUARE2D, 64, 0.5927), (inputs.CUBIC3D, 16, 0.3116)):
+        key = 1000 + top
+        got = ctx.icm_percolation_smax(top, L, p, 1 << 16, sample0=0, key=key).cpu().numpy()
+        o = oracle_for(top, L, key)
+        for s in rng.choice(1 << 16, size=64, replace=False):
+            assert got[s] == o.percolation_smax(p, 1, sample0=int(s))[0], (top, L, int(s))
+        # a property at any size: no cluster exceeds the graph
+        assert got.min() >= 0 and got.max() <= o.N
+
+
+def test_errors_and_empty_batch(ctx):
+    out = ctx.icm_percolation_smax(inputs.CHIMERA, 4, 0.5, 0)
+    assert out.numel() == 0
+    for bad in (-0.1, 1.5, float("nan")):
+        with pytest.raises(icm.IcmError):
+            ctx.icm_percolation_smax(inputs.CHIMERA, 4, bad, 8)
+    with pytest.raises(icm.IcmError):
+        ctx.icm_percolation_smax(inputs.SQUARE2D, 5, 0.5, 8)     # odd periodic side
+    with pytest.raises(icm.IcmError):
+        ctx.icm_percolation_smax(inputs.CHIMERA, 23, 0.5, 8)     # beyond 4096 sites
