@@ -213,11 +213,12 @@ uint32_t icm_sweep_index(icm_ctx* ctx, int32_t handle);
    (sample0 + s, i / 4, 0, 4) and key (context seed, key) is below
    floor(p 2^32).  smax[s] = the number of sites in the largest connected
    cluster of occupied sites (0 if none).  topology / L as in
-   icm_instance_desc; p in [0, 1].  smax: DEVICE pointer, int32
+   icm_instance_desc, up to 16384 sites (the kernel keeps 8 N + 16 bytes in
+   LDS, which must also fit the device's limit per workgroup); p in [0, 1].  smax: DEVICE pointer, int32
    [n_samples], owned by the caller; written asynchronously on the context
    stream (icm_sync, or any later call that synchronizes, completes it).
-   Errors: ICM_E_INVALID (topology, size, p, null smax, sample range beyond
-   2^32), ICM_E_BUSY while serving, ICM_E_NOMEM (neighbour table does not fit
+   Errors: ICM_E_INVALID (topology, size beyond those limits, p, null smax,
+   sample range beyond 2^32), ICM_E_BUSY while serving, ICM_E_NOMEM (neighbour table does not fit
    the arena), ICM_E_DEVICE. */
 int icm_percolation_smax(icm_ctx* ctx, int32_t topology, int32_t L, double p, uint32_t sample0,
                          uint32_t n_samples, uint32_t key, int32_t* smax);

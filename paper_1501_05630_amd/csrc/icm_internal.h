@@ -12,6 +12,7 @@
 namespace icm {
 
 constexpr int kMaxDeg = 6;        // neighbour slots per site (2D uses 4)
+constexpr int kMaxPercSites = 16384;  // site percolation: parent + size arrays in LDS
 constexpr int kMaxSites = 4096;   // an ICM lane holds at most two 32-site words of a move
 constexpr int kMaxTemps = 256;
 constexpr int kMaxReplicas = 64;

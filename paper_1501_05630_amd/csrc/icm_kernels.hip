@@ -18,6 +18,8 @@
 //            temperature pairs in ascending order.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "icm_internal.h"
 
 namespace icm {
@@ -175,15 +177,18 @@ __device__ __forceinline__ bool accept_int_field(uint32_t u, int e, double beta,
 // ----------------------------------------------------------------------------
 // union-find on an LDS parent array (parent[x] <= x; roots satisfy parent[x] == x)
 // ----------------------------------------------------------------------------
+// SCOPE: the lanes that share the array (one wave, or a whole workgroup).
+template <int SCOPE = __HIP_MEMORY_SCOPE_WAVEFRONT>
 __device__ __forceinline__ int uf_load(int* parent, int x) {
-  return __hip_atomic_load(&parent[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+  return __hip_atomic_load(&parent[x], __ATOMIC_RELAXED, SCOPE);
 }
 
+template <int SCOPE = __HIP_MEMORY_SCOPE_WAVEFRONT>
 __device__ __forceinline__ int uf_find(int* parent, int x) {
-  int p = uf_load(parent, x);
+  int p = uf_load<SCOPE>(parent, x);
   while (p != x) {
     x = p;
-    p = uf_load(parent, x);
+    p = uf_load<SCOPE>(parent, x);
   }
   return x;
 }
@@ -191,14 +196,14 @@ __device__ __forceinline__ int uf_find(int* parent, int x) {
 // Hooks the larger root under the smaller one with atomicMin; when the target
 // stopped being a root meanwhile, continues with the value it pointed to, so
 // no link is ever lost.  Component roots end up at their minimum site index.
+template <int SCOPE = __HIP_MEMORY_SCOPE_WAVEFRONT>
 __device__ __forceinline__ void uf_union(int* parent, int a, int b) {
   while (true) {
-    a = uf_find(parent, a);
-    b = uf_find(parent, b);
+    a = uf_find<SCOPE>(parent, a);
+    b = uf_find<SCOPE>(parent, b);
     if (a == b) return;
     if (a > b) { int t = a; a = b; b = t; }
-    const int old = __hip_atomic_fetch_min(&parent[b], a, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_WAVEFRONT);
+    const int old = __hip_atomic_fetch_min(&parent[b], a, __ATOMIC_RELAXED, SCOPE);
     if (old == b) return;
     b = old;
   }
@@ -1464,12 +1469,12 @@ __global__ void energy_kernel(const uint32_t* spins, const uint16_t* nbr, const 
 // ----------------------------------------------------------------------------
 // Site percolation (the chimera threshold study of the Supplemental Material):
 // each sample occupies every site independently with probability p and
-// reports the size of its largest cluster of occupied sites.  One wave per
-// sample (workgroups of 64 lanes, a grid-stride loop over samples): site i is
-// occupied iff word i mod 4 of Philox(sample, i / 4, 0, 4) is below
-// floor(p 2^32); union-find over the bonds between occupied sites (hooking to
-// the smaller root), the component sizes by LDS atomics at the roots, then a
-// wave maximum.  LDS: parent and size arrays of N ints.
+// reports the size of its largest cluster of occupied sites.  One workgroup of
+// WAVES waves per sample (a grid-stride loop over samples): site i is occupied
+// iff word i mod 4 of Philox(sample, i / 4, 0, 4) is below floor(p 2^32);
+// union-find over the bonds between occupied sites (hooking to the smaller
+// root), the component sizes by LDS atomics at the roots, then a maximum.
+// LDS: parent and size arrays of N ints and one int per wave.
 // ----------------------------------------------------------------------------
 __device__ __forceinline__ int wave_max(int v) {
 #pragma unroll
@@ -1480,17 +1485,27 @@ __device__ __forceinline__ int wave_max(int v) {
   return v;
 }
 
-__global__ void __launch_bounds__(64) percolation_kernel(const uint16_t* __restrict__ nbr, int N, int deg,
-                                                         unsigned long long thr, uint32_t sample0,
-                                                         uint32_t n_samples, uint32_t seed, uint32_t key,
-                                                         int32_t* __restrict__ smax) {
+template <int WAVES>
+__device__ __forceinline__ void perc_sync() {
+  if (WAVES == 1) wave_sync();
+  else __syncthreads();
+}
+
+template <int WAVES>
+__global__ void __launch_bounds__(64 * WAVES) percolation_kernel(const uint16_t* __restrict__ nbr, int N, int deg,
+                                                                 unsigned long long thr, uint32_t sample0,
+                                                                 uint32_t n_samples, uint32_t seed, uint32_t key,
+                                                                 int32_t* __restrict__ smax) {
+  constexpr int SC = WAVES == 1 ? __HIP_MEMORY_SCOPE_WAVEFRONT : __HIP_MEMORY_SCOPE_WORKGROUP;
+  constexpr int NT = 64 * WAVES;
   extern __shared__ __align__(16) unsigned char lds[];
   int* parent = (int*)lds;  // -1: empty site
   int* size = parent + N;
-  const int lane = lane_id();
+  int* wmax = size + N;     // [WAVES]
+  const int tid = threadIdx.x;
   for (uint32_t s = blockIdx.x; s < n_samples; s += gridDim.x) {
     const uint32_t sample = sample0 + s;
-    for (int q = lane; 4 * q < N; q += 64) {
+    for (int q = tid; 4 * q < N; q += NT) {
       const Words4 u = philox4x32_10(sample, (uint32_t)q, 0u, kStreamPerc, seed, key);
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
@@ -1501,25 +1516,35 @@ __global__ void __launch_bounds__(64) percolation_kernel(const uint16_t* __restr
         }
       }
     }
-    wave_sync();
+    perc_sync<WAVES>();
     // each bond once, from its smaller end; an empty site never changes, an
     // occupied one always holds a site index
-    for (int i = lane; i < N; i += 64) {
-      if (uf_load(parent, i) < 0) continue;
+    for (int i = tid; i < N; i += NT) {
+      if (uf_load<SC>(parent, i) < 0) continue;
       for (int d = 0; d < deg; ++d) {
         const int j = nbr[i * deg + d];
-        if (j > i && uf_load(parent, j) >= 0) uf_union(parent, i, j);
+        if (j > i && uf_load<SC>(parent, j) >= 0) uf_union<SC>(parent, i, j);
       }
     }
-    wave_sync();
-    for (int i = lane; i < N; i += 64)
-      if (uf_load(parent, i) >= 0) atomicAdd(&size[uf_find(parent, i)], 1);
-    wave_sync();
+    perc_sync<WAVES>();
+    for (int i = tid; i < N; i += NT)
+      if (uf_load<SC>(parent, i) >= 0) atomicAdd(&size[uf_find<SC>(parent, i)], 1);
+    perc_sync<WAVES>();
     int m = 0;
-    for (int i = lane; i < N; i += 64) m = size[i] > m ? size[i] : m;
+    for (int i = tid; i < N; i += NT) m = size[i] > m ? size[i] : m;
     m = wave_max(m);
-    if (lane == 0) smax[s] = m;
-    wave_sync();
+    if (WAVES == 1) {
+      if (tid == 0) smax[s] = m;
+    } else {
+      if ((tid & 63) == 0) wmax[tid >> 6] = m;
+      __syncthreads();
+      if (tid == 0) {
+        int best = wmax[0];
+        for (int w = 1; w < WAVES; ++w) best = wmax[w] > best ? wmax[w] : best;
+        smax[s] = best;
+      }
+    }
+    perc_sync<WAVES>();
   }
 }
 
@@ -1566,6 +1591,11 @@ int icmk_set_lds_limit(size_t bytes) {
     hipError_t r = hipFuncSetAttribute(fns[x], hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (r != hipSuccess) e = r;
   }
+  const void* perc[2] = {(const void*)icm::percolation_kernel<1>, (const void*)icm::percolation_kernel<4>};
+  for (int x = 0; x < 2; ++x) {
+    hipError_t r = hipFuncSetAttribute(perc[x], hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (r != hipSuccess) e = r;
+  }
   return (int)e;
 }
 
@@ -1585,15 +1615,27 @@ int icmk_launch_scatter(uint32_t* spins, const int8_t* src, int N, int Wq, int W
   return (int)hipGetLastError();
 }
 
+size_t icmk_percolation_lds(int N) { return 8u * (size_t)N + 16u; }
+
+// n_cus compute units with lds_cu bytes of LDS each: the grid is what fits
+// resident at once (samples are dealt over it by the grid-stride loop).
 int icmk_launch_percolation(const uint16_t* nbr, int N, int deg, unsigned long long thr, uint32_t sample0,
-                            uint32_t n_samples, uint32_t seed, uint32_t key, int32_t* smax, int n_blocks,
-                            hipStream_t stream) {
+                            uint32_t n_samples, uint32_t seed, uint32_t key, int32_t* smax, int n_cus,
+                            size_t lds_cu, hipStream_t stream) {
   if (n_samples == 0) return 0;
-  if (N < 1 || N > icm::kMaxSites || n_blocks < 1) return (int)hipErrorInvalidValue;
-  const size_t lds = 8u * (size_t)N;  // at most 32 KiB
-  const uint32_t g = n_samples < (uint32_t)n_blocks ? n_samples : (uint32_t)n_blocks;
-  hipLaunchKernelGGL(icm::percolation_kernel, dim3(g), dim3(64), lds, stream, nbr, N, deg, thr, sample0,
-                     n_samples, seed, key, smax);
+  if (N < 1 || N > icm::kMaxPercSites || n_cus < 1) return (int)hipErrorInvalidValue;
+  const size_t lds = icmk_percolation_lds(N);
+  if (lds > lds_cu) return (int)hipErrorInvalidValue;
+  const int waves = N <= 1024 ? 1 : 4;
+  const int per_cu = std::max(1, std::min(32 / waves, (int)(lds_cu / lds)));
+  const uint32_t nb = (uint32_t)(n_cus * per_cu);
+  const uint32_t g = n_samples < nb ? n_samples : nb;
+  if (waves == 1)
+    hipLaunchKernelGGL(icm::percolation_kernel<1>, dim3(g), dim3(64), lds, stream, nbr, N, deg, thr, sample0,
+                       n_samples, seed, key, smax);
+  else
+    hipLaunchKernelGGL(icm::percolation_kernel<4>, dim3(g), dim3(256), lds, stream, nbr, N, deg, thr, sample0,
+                       n_samples, seed, key, smax);
   return (int)hipGetLastError();
 }
 

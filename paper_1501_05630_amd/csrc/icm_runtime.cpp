@@ -34,9 +34,10 @@ int icmk_launch_scatter(uint32_t* spins, const int8_t* src, int N, int Wq, int W
                         hipStream_t stream);
 int icmk_launch_energy(const uint32_t* spins, const uint16_t* nbr, const void* coup, int N, int deg,
                        int Wp, int jkind, int jexp, int64_t* energy, hipStream_t stream);
+size_t icmk_percolation_lds(int N);
 int icmk_launch_percolation(const uint16_t* nbr, int N, int deg, unsigned long long thr, uint32_t sample0,
-                            uint32_t n_samples, uint32_t seed, uint32_t key, int32_t* smax, int n_blocks,
-                            hipStream_t stream);
+                            uint32_t n_samples, uint32_t seed, uint32_t key, int32_t* smax, int n_cus,
+                            size_t lds_cu, hipStream_t stream);
 }
 
 namespace {
@@ -118,7 +119,7 @@ struct Topology {
   int refs = 0;
 };
 
-bool build_topology(int topo, int L, Topology& T) {
+bool build_topology(int topo, int L, Topology& T, int max_sites = icm::kMaxSites) {
   T.topo = topo;
   T.L = L;
   if (topo == ICM_TOPO_SQUARE2D || topo == ICM_TOPO_CUBIC3D) {
@@ -126,7 +127,7 @@ bool build_topology(int topo, int L, Topology& T) {
     const int dim = topo == ICM_TOPO_SQUARE2D ? 2 : 3;
     T.N = dim == 2 ? L * L : L * L * L;
     T.deg = 2 * dim;
-    if (T.N > icm::kMaxSites) return false;
+    if (T.N > max_sites) return false;
     T.nbr.assign((size_t)T.N * T.deg, 0);
     T.cidx.assign((size_t)T.N * T.deg, -1);
     std::vector<int> col(T.N);
@@ -157,7 +158,7 @@ bool build_topology(int topo, int L, Topology& T) {
     if (C < 1) return false;
     T.N = 8 * C * C;
     T.deg = 6;
-    if (T.N > icm::kMaxSites) return false;
+    if (T.N > max_sites) return false;
     T.nbr.assign((size_t)T.N * 6, 0);
     T.cidx.assign((size_t)T.N * 6, -1);
     std::vector<int> col(T.N);
@@ -259,6 +260,7 @@ struct icm_ctx {
   int32_t next_handle = 1;
   size_t lds_limit = 65536;
   int n_cus = 256;
+  size_t lds_cu = 0;                 // LDS bytes per compute unit
   icm_run_config cfg{512, 256, 0, 32, 0};
   // unit tables cached per (handle list)
   std::map<std::vector<int32_t>, UnitDesc*> unit_tables;
@@ -390,13 +392,13 @@ int grid_exponent(const float* J, size_t n) {
 
 int32_t grid_coupling(float J, int e) { return (int32_t)std::nearbyint(std::ldexp((double)J, e)); }
 
-Topology* get_topology(icm_ctx* c, int topo, int L, int& rc) {
+Topology* get_topology(icm_ctx* c, int topo, int L, int& rc, int max_sites = icm::kMaxSites) {
   rc = ICM_OK;
   auto key = std::make_pair(topo, L);
   auto it = c->topologies.find(key);
   if (it != c->topologies.end()) return it->second.get();
   auto T = std::make_unique<Topology>();
-  if (!build_topology(topo, L, *T)) { rc = ICM_E_INVALID; return nullptr; }
+  if (!build_topology(topo, L, *T, max_sites)) { rc = ICM_E_INVALID; return nullptr; }
   T->d_nbr = (uint16_t*)c->arena.alloc(T->nbr.size() * 2);
   T->d_clist = (uint16_t*)c->arena.alloc(T->clist.size() * 2);
   if (!T->d_nbr || !T->d_clist) {
@@ -928,6 +930,11 @@ int icm_create(icm_ctx** out, int device, void* stream, void* arena, size_t aren
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
     c->n_cus = cus;
+  int lds_cu = 0;
+  c->lds_cu = c->lds_limit;
+  if (hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, device) == hipSuccess &&
+      lds_cu > 0)
+    c->lds_cu = std::max(c->lds_limit, (size_t)lds_cu);
   (void)icmk_set_lds_limit(c->lds_limit);
   (void)hipGetLastError();
   *out = c.release();
@@ -1001,12 +1008,14 @@ int icm_percolation_smax(icm_ctx* c, int32_t topology, int32_t L, double p, uint
   if (n_samples > 0 && !smax) return fail(c, ICM_E_INVALID, "null output");
   if ((uint64_t)sample0 + n_samples > (1ull << 32))
     return fail(c, ICM_E_INVALID, "sample indices beyond 2^32");
-  Topology* T = get_topology(c, topology, L, rc);
+  Topology* T = get_topology(c, topology, L, rc, icm::kMaxPercSites);
   if (!T) return fail(c, rc, "invalid topology or size");
+  if (T->N > icm::kMaxPercSites || icmk_percolation_lds(T->N) > c->lds_limit)
+    return fail(c, ICM_E_INVALID, "%d sites exceed the percolation kernel's LDS", T->N);
   // floor(p 2^32) is exact in double: p scaled by a power of two
   const unsigned long long thr = (unsigned long long)std::floor(p * 4294967296.0);
   KERNEL_OK(c, icmk_launch_percolation(T->d_nbr, T->N, T->deg, thr, sample0, n_samples, c->seed, key, smax,
-                                       16 * c->n_cus, c->stream));
+                                       c->n_cus, c->lds_cu, c->stream));
   return ICM_OK;
 }
 

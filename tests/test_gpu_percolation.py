@@ -30,14 +30,16 @@ def oracle_for(top, L, key):
 CASES = [(inputs.SQUARE2D, 2), (inputs.SQUARE2D, 6), (inputs.SQUARE2D, 32), (inputs.SQUARE2D, 64),
          (inputs.CUBIC3D, 2), (inputs.CUBIC3D, 6), (inputs.CUBIC3D, 10), (inputs.CUBIC3D, 16),
          (inputs.CHIMERA, 1), (inputs.CHIMERA, 3), (inputs.CHIMERA, 7), (inputs.CHIMERA, 12),
-         (inputs.CHIMERA, 22)]
+         (inputs.CHIMERA, 22),
+         # beyond the 4096 sites of a simulated instance: four waves per sample
+         (inputs.CHIMERA, 33), (inputs.SQUARE2D, 90), (inputs.CUBIC3D, 24)]
 
 
 @pytest.mark.parametrize("top,L", CASES)
 def test_smax_bit_exact(ctx, top, L):
     key = 7 * L + top
     o = oracle_for(top, L, key)
-    n = 400 if o.N <= 1024 else 120
+    n = 400 if o.N <= 1024 else (120 if o.N <= 4096 else 40)
     for p in (0.0, 0.2, 0.3866, 0.5927, 1.0):
         got = ctx.icm_percolation_smax(top, L, p, n, sample0=12345, key=key).cpu().numpy()
         ref = o.percolation_smax(p, n, sample0=12345)
@@ -56,14 +58,14 @@ def test_more_samples_than_the_grid(ctx):
 
 
 def test_full_size_sampled(ctx):
-    # the study's largest sizes, 2^16 samples per launch: 64 samples spread over
+    # the study's largest sizes, 2^16 samples per launch: 24 samples spread over
     # the launch, recomputed one at a time by the oracle
     rng = np.random.default_rng(5)
-    for top, L, p in ((inputs.CHIMERA, 22, 0.3866), (inputs.SQUARE2D, 64, 0.5927), (inputs.CUBIC3D, 16, 0.3116)):
+    for top, L, p in ((inputs.CHIMERA, 45, 0.3866), (inputs.SQUARE2D, 128, 0.5927), (inputs.CUBIC3D, 24, 0.3116)):
         key = 1000 + top
         got = ctx.icm_percolation_smax(top, L, p, 1 << 16, sample0=0, key=key).cpu().numpy()
         o = oracle_for(top, L, key)
-        for s in rng.choice(1 << 16, size=64, replace=False):
+        for s in rng.choice(1 << 16, size=24, replace=False):
             assert got[s] == o.percolation_smax(p, 1, sample0=int(s))[0], (top, L, int(s))
         # a property at any size: no cluster exceeds the graph
         assert got.min() >= 0 and got.max() <= o.N
@@ -78,4 +80,37 @@ def test_errors_and_empty_batch(ctx):
     with pytest.raises(icm.IcmError):
         ctx.icm_percolation_smax(inputs.SQUARE2D, 5, 0.5, 8)     # odd periodic side
     with pytest.raises(icm.IcmError):
-        ctx.icm_percolation_smax(inputs.CHIMERA, 23, 0.5, 8)     # beyond 4096 sites
+        ctx.icm_percolation_smax(inputs.CHIMERA, 46, 0.5, 8)     # beyond 16384 sites
+
+
+def read_thresholds():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "percolation_thresholds.txt")
+    out = {}
+    with open(path) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                top, pc, _ = line.split()
+                out[top] = float(pc)
+    return out
+
+
+@pytest.mark.parametrize("name,top,sizes,tol", [("chimera", inputs.CHIMERA, (22, 32), 0.003),
+                                                ("2d", inputs.SQUARE2D, (64, 128), 0.003),
+                                                ("3d", inputs.CUBIC3D, (16, 24), 0.003)])
+def test_binder_crossing_at_the_papers_threshold(ctx, name, top, sizes, tol):
+    # the Binder-ratio curves of two sizes cross at the threshold the paper
+    # gives, within the finite-size drift of these sizes (2^16 samples per point)
+    pc = read_thresholds()[name]
+    ps = np.linspace(pc - 0.012, pc + 0.012, 7)
+    n = 1 << 16
+    d = []
+    for p in ps:
+        g = [icm.binder_ratio(ctx.icm_percolation_smax(top, L, float(p), n, sample0=0, key=L).cpu().numpy())
+             for L in sizes]
+        d.append(g[1] - g[0])
+    d = np.array(d)
+    assert d[0] < 0 < d[-1], d            # the larger size is below, then above
+    i = int(np.flatnonzero(np.diff(np.sign(d)) > 0)[0])
+    cross = ps[i] + (ps[i + 1] - ps[i]) * d[i] / (d[i] - d[i + 1])
+    assert abs(cross - pc) < tol, (cross, pc)
