@@ -204,6 +204,20 @@ int icm_read_observables(icm_ctx* ctx, int32_t handle, int64_t* sums, int64_t* c
 int icm_read_walkers(icm_ctx* ctx, int32_t handle, int32_t* out, size_t cap);
 uint32_t icm_sweep_index(icm_ctx* ctx, int32_t handle);
 
+/* Replaces the K temperatures of an instance (same K; finite, > 0, strictly
+   ascending), for annealing schedules: the paper proposes adding the cluster
+   moves at every temperature step of simulated annealing (introduction), and
+   hopping through a degenerate ground-state manifold with cluster moves at
+   very low temperature (discussion of Fig. 4).  The walkers keep their spins,
+   temperature labels, energies and sweep counter; walker (k, r) continues at
+   the new T_k.  Ordered after earlier work on the context stream; returns
+   when the new tables are on the device.  Integer couplings with PT: the
+   PT acceptance table keeps the length it was created with, so a pair of
+   temperatures closer than any pair at creation is ICM_E_INVALID.
+   Errors: ICM_E_INVALID, ICM_E_NOTFOUND, ICM_E_BUSY while serving,
+   ICM_E_DEVICE. */
+int icm_set_temperatures(icm_ctx* ctx, int32_t handle, const double* temps);
+
 /* Site percolation on a topology, the study behind the paper's chimera
    percolation threshold (Supplemental Material: the relative size of the
    largest cluster as order parameter, its Binder ratio

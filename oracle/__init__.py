@@ -82,6 +82,8 @@ def _load():
     lib.orc_metro_accept_count.restype = ctypes.c_uint64
     lib.orc_percolation_smax.argtypes = [P, ctypes.c_double, U32, U32, P]
     lib.orc_percolation_smax.restype = None
+    lib.orc_set_temperatures.argtypes = [P, P]
+    lib.orc_set_temperatures.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -225,6 +227,12 @@ class Sim:
 
     def metro_accept_count(self, k, dE_raw):
         return int(self._lib.orc_metro_accept_count(self._h, k, int(dE_raw)))
+
+    def set_temperatures(self, temps):
+        t = np.ascontiguousarray(temps, dtype=np.float64)
+        assert t.shape == (self.K,)
+        if self._lib.orc_set_temperatures(self._h, _ptr(t)) != 0:
+            raise ValueError("invalid temperatures")
 
     def percolation_smax(self, p, n_samples, sample0=0):
         """Largest-cluster sizes [n_samples] of random site configurations on

@@ -519,6 +519,18 @@ void orc_get_observables(const orc_sim* s, int64_t* sums, int64_t* counts) {
   for (int b = 0; b < ORC_OBS_BINS; ++b) counts[b] = s->obs_count.empty() ? 0 : s->obs_count[b];
 }
 
+// New temperatures for the same K slots (simulated annealing with cluster
+// moves at every temperature step, introduction): only the inverse
+// temperatures change; spins, labels, energies and the sweep counter stay.
+int orc_set_temperatures(orc_sim* s, const double* temps) {
+  for (int k = 0; k < s->K; ++k) {
+    if (!(temps[k] > 0.0) || !std::isfinite(temps[k])) return -1;
+    if (k > 0 && !(temps[k] > temps[k - 1])) return -1;
+  }
+  for (int k = 0; k < s->K; ++k) s->beta[k] = 1.0 / temps[k];
+  return 0;
+}
+
 // Site percolation on the simulation's graph (Supplemental Material: the
 // largest cluster of randomly occupied sites, whose Binder ratio locates the
 // chimera percolation threshold).  Every site is occupied independently with

@@ -120,6 +120,10 @@ void orc_bonds(const orc_sim* s, int32_t* bonds_ij, int64_t* j_raw);
    cluster sites after step 2a). */
 void orc_get_observables(const orc_sim* s, int64_t* sums, int64_t* counts);
 
+/* Replaces the K temperatures (finite, > 0, strictly ascending); everything
+   else carries on.  Returns 0, or -1 on invalid temperatures. */
+int orc_set_temperatures(orc_sim* s, const double* temps);
+
 /* Site percolation on this simulation's graph: for samples n = sample0 ..
    sample0 + n_samples - 1, site i is occupied iff word i mod 4 of
    Philox4x32-10 with counter (n, i / 4, 0, 4) and key (seed, instance_key)

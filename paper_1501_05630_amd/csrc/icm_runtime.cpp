@@ -999,6 +999,60 @@ int icm_init_states(icm_ctx* c, int32_t h) {
   return ICM_OK;
 }
 
+int icm_set_temperatures(icm_ctx* c, int32_t h, const double* temps) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (c->serving) return fail(c, ICM_E_BUSY, "the serving loop owns the context");
+  Instance* in = find(c, h);
+  if (!in) return fail(c, ICM_E_NOTFOUND, "unknown handle %d", h);
+  if (!temps) return fail(c, ICM_E_INVALID, "null temperatures");
+  const int K = in->K;
+  for (int k = 0; k < K; ++k) {
+    if (!(temps[k] > 0.0) || !std::isfinite(temps[k]))
+      return fail(c, ICM_E_INVALID, "temperatures must be finite and > 0");
+    if (k > 0 && !(temps[k] > temps[k - 1]))
+      return fail(c, ICM_E_INVALID, "temperatures must be strictly ascending");
+  }
+  UnitDesc& U = in->unit;
+  std::vector<uint32_t> thr, ptthr;
+  if (in->jkind == ICM_J_INT8) {
+    // the same tables as at creation, over the instance's local-field bound
+    thr.assign((size_t)K * in->HM, 0);
+    for (int k = 0; k < K; ++k) {
+      const double beta = 1.0 / temps[k];
+      thr[(size_t)k * in->HM] = 4294967295u;
+      for (int e = 1; e < in->HM; ++e)
+        thr[(size_t)k * in->HM + e] = threshold_of(-(beta * (double)(2 * e)) / (double)in->jscale);
+    }
+    if (in->ptlen > 0) {
+      // the PT table keeps its length: every gap past it must have a zero threshold
+      ptthr.assign((size_t)(K - 1) * in->ptlen, 0);
+      for (int k = 0; k + 1 < K; ++k) {
+        const double dbeta = 1.0 / temps[k] - 1.0 / temps[k + 1];
+        if (threshold_of(-(dbeta * (double)(in->ptlen + 1)) / (double)in->jscale) != 0)
+          return fail(c, ICM_E_INVALID, "temperatures %d, %d too close for the instance's PT table", k, k + 1);
+        for (int D = 1; D <= in->ptlen; ++D)
+          ptthr[(size_t)k * in->ptlen + D - 1] = threshold_of(-(dbeta * (double)D) / (double)in->jscale);
+      }
+    }
+  }
+  std::vector<double> beta(K);
+  std::vector<float> bl2e(K);
+  for (int k = 0; k < K; ++k) {
+    beta[k] = 1.0 / temps[k];
+    bl2e[k] = (float)(beta[k] / std::log(2.0));
+  }
+  if (!thr.empty())
+    HIP_OK(c, hipMemcpyAsync((void*)U.thr, thr.data(), thr.size() * 4, hipMemcpyHostToDevice, c->stream));
+  if (!ptthr.empty())
+    HIP_OK(c, hipMemcpyAsync((void*)U.ptthr, ptthr.data(), ptthr.size() * 4, hipMemcpyHostToDevice, c->stream));
+  HIP_OK(c, hipMemcpyAsync((void*)U.beta, beta.data(), (size_t)K * 8, hipMemcpyHostToDevice, c->stream));
+  HIP_OK(c, hipMemcpyAsync((void*)U.bl2e, bl2e.data(), (size_t)K * 4, hipMemcpyHostToDevice, c->stream));
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  in->temps.assign(temps, temps + K);
+  return ICM_OK;
+}
+
 int icm_percolation_smax(icm_ctx* c, int32_t topology, int32_t L, double p, uint32_t sample0,
                          uint32_t n_samples, uint32_t key, int32_t* smax) {
   int rc = check_ctx(c);

@@ -66,6 +66,7 @@ EXPORTS = {
     "icm_read_walkers": (ctypes.c_int, [_P, _I32, _P, _SZ]),
     "icm_sweep_index": (_U32, [_P, _I32]),
     "icm_percolation_smax": (ctypes.c_int, [_P, _I32, _I32, ctypes.c_double, _U32, _U32, _U32, _P]),
+    "icm_set_temperatures": (ctypes.c_int, [_P, _I32, _P]),
     "icm_serve_start": (ctypes.c_int, [_P, _I32]),
     "icm_serve_stop": (ctypes.c_int, [_P]),
     "icm_submit": (ctypes.c_int, [_P, ctypes.POINTER(InstanceDesc), _U32, ctypes.POINTER(_U64)]),
@@ -263,6 +264,12 @@ class Context:
 
     def icm_sweep_index(self, h):
         return int(self._lib.icm_sweep_index(self.h, h))
+
+    def icm_set_temperatures(self, h, temps):
+        t = np.ascontiguousarray(temps, dtype=np.float64)
+        if t.shape != (self.meta[h]["K"],):
+            raise ValueError("one temperature per temperature slot of the instance")
+        _check(self.h, self._lib.icm_set_temperatures(self.h, h, _ptr(t)), "icm_set_temperatures")
 
     def icm_percolation_smax(self, topology, L, p, n_samples, sample0=0, key=0, out=None):
         """Largest-cluster sizes of n_samples random site configurations
