@@ -51,6 +51,9 @@ def parse():
                          "sweeps instead (PT vs PT + ICM per topology and size)")
     ap.add_argument("--table1-instances", type=int, default=128, help="disorder instances per size")
     ap.add_argument("--table1-topologies", default="2d,chimera,3d")
+    ap.add_argument("--anneal", type=int, default=0,
+                    help="run simulated annealing with and without cluster moves for this many sweeps instead")
+    ap.add_argument("--anneal-instances", type=int, default=256)
     ap.add_argument("--percolation", type=int, default=0,
                     help="run the site-percolation Binder study with this many samples per (size, p) instead")
     return ap.parse_args()
@@ -127,9 +130,23 @@ def cpu_baseline(name, spec, seconds):
     with cf.ThreadPoolExecutor(max_workers=cores) as ex:
         res = list(ex.map(job, picks))
     dt = time.perf_counter() - t0
+    # one thread alone: a quarter of one instance's sweeps
+    o, N1 = sim(picks[0])
+    s1 = max(2, sweeps // 4)
+    t1 = time.perf_counter()
+    o.run(s1)
+    dt1 = time.perf_counter() - t1
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": sum(r[1] for r in res) / dt, "unit": "spin-flip attempts/s", "cores": cores,
             "kind": "oracle", "icm_moves_per_s": sum(r[0] for r in res) / dt,
-            "sample": f"{n_inst} instances x {sweeps} sweeps of {name}, one oracle per thread"}
+            "single_thread_value": S * N1 * s1 / dt1, "cpu_model": model, "host_cpus": os.cpu_count(),
+            "sample": f"{n_inst} instances x {sweeps} sweeps of {name}, one oracle per thread; "
+                      f"single thread: {s1} sweeps of one instance"}
 
 
 def serve_request(x, rng):
@@ -416,8 +433,102 @@ def run_percolation(args):
     return out
 
 
+def run_anneal(args):
+    """Simulated annealing as a ground-state heuristic with and without
+    isoenergetic cluster moves at every temperature step (the introduction's
+    proposal), on the same chimera instances and schedule: the fraction of
+    replicas that end at the lowest energy any method found and the mean
+    residual energy per spin; then zero-temperature dynamics from the annealed
+    states, with and without cluster moves, counting the distinct
+    lowest-energy configurations visited (hopping through a degenerate
+    ground-state manifold, discussion of Fig. 4)."""
+    import numpy as np
+    import torch
+
+    from paper_1501_05630_amd import icm, inputs
+    C, R, steps = 8, 16, 64
+    M = args.anneal_instances
+    per_step = max(1, args.anneal // steps)
+    schedule = np.geomspace(3.0, 0.1, steps)
+    N = inputs.n_sites(inputs.CHIMERA, C)
+    Js = [inputs.pm_j_couplings(inputs.CHIMERA, C, inputs.make_rng(8, b)) for b in range(M)]
+    out = {"metric": "annealing: success fraction and residual energy, SA vs SA + ICM",
+           "instances": M, "topology": "chimera", "C": C, "N": N, "replicas": R,
+           "schedule": {"t_start": 3.0, "t_end": 0.1, "steps": steps, "sweeps_per_step": per_step}}
+    ctx = icm.Context(arena_bytes=2 << 30, seed=inputs.MASTER_SEED)
+    ctx.icm_set_run_config(threads=args.threads, sweeps_per_launch=per_step, use_graph=1, icm_slots=args.icm_slots)
+    finals, states = {}, {}
+    for mode, kc in (("sa", 0), ("sa_icm", 1)):
+        hs = [ctx.icm_add_instance(inputs.CHIMERA, C, J, [3.0], R, kc, flags=icm.FLAG_2A, instance_key=b,
+                                   j_scale=1) for b, J in enumerate(Js)]
+        for h in hs:
+            ctx.icm_init_states(h)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for T in schedule:
+            for h in hs:
+                ctx.icm_set_temperatures(h, [T])
+            ctx.icm_run(hs, per_step)
+        ctx.icm_sync()
+        wall = time.perf_counter() - t0
+        finals[mode] = np.array([ctx.icm_read_energies(h)[0][0] for h in hs])       # [M][R], units of J
+        states[mode] = [ctx.icm_read_states(h)[0] for h in hs]
+        for h in hs:
+            ctx.icm_remove_instance(h)
+        out[mode] = {"wall_s": wall}
+        print(f"anneal {mode}: {M} instances in {wall:.1f} s", file=sys.stderr, flush=True)
+    # reference: parallel tempering with cluster moves, 2^14 sweeps, coldest walkers
+    temps = inputs.geometric_temps(0.1, 3.0, 30)
+    hs = [ctx.icm_add_instance(inputs.CHIMERA, C, J, temps, 2, inputs.icm_cutoff(temps),
+                               flags=icm.FLAG_2A | icm.FLAG_PT, instance_key=b, j_scale=1) for b, J in enumerate(Js)]
+    for h in hs:
+        ctx.icm_init_states(h)
+    ctx.icm_set_run_config(threads=args.threads, sweeps_per_launch=256, use_graph=1, icm_slots=args.icm_slots)
+    ctx.icm_run(hs, 1 << 14)
+    ctx.icm_sync()
+    pt_best = np.array([ctx.icm_read_energies(h)[0].min() for h in hs])
+    for h in hs:
+        ctx.icm_remove_instance(h)
+    best = np.minimum(pt_best, np.minimum(finals["sa"].min(axis=1), finals["sa_icm"].min(axis=1)))
+    out["reference"] = "lowest energy of SA, SA + ICM and 2^14 sweeps of PT + ICM (30 temperatures)"
+    for mode in ("sa", "sa_icm"):
+        f = finals[mode]
+        out[mode].update({"success_fraction": float(np.mean(f == best[:, None])),
+                          "instances_solved": float(np.mean((f == best[:, None]).any(axis=1))),
+                          "residual_per_spin": float(np.mean(f - best[:, None]) / N)})
+    out["pt_icm_reaches_best"] = float(np.mean(pt_best == best))
+    # zero temperature from the SA + ICM states
+    for mode, kc in (("t0_metropolis", 0), ("t0_icm", 1)):
+        hs = [ctx.icm_add_instance(inputs.CHIMERA, C, J, [1e-3], R, kc, flags=icm.FLAG_2A, instance_key=b,
+                                   j_scale=1) for b, J in enumerate(Js)]
+        seen = [set() for _ in hs]
+        for h, st in zip(hs, states["sa_icm"]):
+            ctx.icm_set_states(h, st.reshape(1, R, N))
+        ctx.icm_set_run_config(threads=args.threads, sweeps_per_launch=16, use_graph=1, icm_slots=args.icm_slots)
+        for _ in range(16):
+            ctx.icm_run(hs, 16)
+            for b, h in enumerate(hs):
+                e = ctx.icm_read_energies(h)[0][0]
+                st = ctx.icm_read_states(h)[0]
+                for r in np.flatnonzero(e == best[b]):
+                    x = st[r] if st[r][0] > 0 else -st[r]
+                    seen[b].add(x.tobytes())
+        for h in hs:
+            ctx.icm_remove_instance(h)
+        out[mode] = {"sweeps": 256, "distinct_ground_states_mean": float(np.mean([len(s) for s in seen])),
+                     "instances_with_several": float(np.mean([len(s) > 1 for s in seen]))}
+    ctx.close()
+    return out
+
+
 def main():
     args = parse()
+    if args.anneal:
+        if args.gpus != 1:
+            print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+            sys.exit(2)
+        print(json.dumps(run_anneal(args)), flush=True)
+        return
     if args.percolation:
         if args.gpus != 1:
             print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
