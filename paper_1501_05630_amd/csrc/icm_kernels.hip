@@ -118,6 +118,32 @@ __device__ __forceinline__ int wave_exclusive_scan(int v) {
   return x - v;
 }
 
+// NV per-lane values v[0..NV-1] (NV a power of two) summed over the wave at
+// once: each butterfly stage halves the values a lane holds (it keeps the sum
+// for one half of the indices and hands the other half to its partner), so
+// after log2 NV stages lane l holds a partial sum for index l mod NV, which
+// the remaining stages complete.  Returns, in every lane, the wave total for
+// index lane mod NV.  Exact for integers and for doubles holding integers.
+template <int NV, typename T>
+__device__ __forceinline__ T transpose_sum(T (&v)[NV]) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int s = 0; (1 << s) < NV; ++s) {
+    const int m = 1 << s;
+    const bool hi = (lane & m) != 0;
+#pragma unroll
+    for (int j = 0; j < (NV >> (s + 1)); ++j) {
+      const T keep = hi ? v[2 * j + 1] : v[2 * j];
+      const T send = hi ? v[2 * j] : v[2 * j + 1];
+      v[j] = keep + __shfl_xor(send, m, 64);
+    }
+  }
+  T r = v[0];
+#pragma unroll
+  for (int m = NV; m < 64; m <<= 1) r += __shfl_xor(r, m, 64);
+  return r;
+}
+
 // Orders this wave's LDS accesses around the call (lanes of one wave exchange
 // data through LDS between ICM phases).
 __device__ __forceinline__ void wave_sync() {
@@ -215,6 +241,28 @@ template <>
 struct EnergyT<0> { using T = int; };
 template <>
 struct EnergyT<1> { using T = double; };
+
+// Adds a wave's accepted energy changes to the WPT walkers' energies: acc[b] is
+// a lane's sum of e = s_i h_i over its accepted flips of walker b (dE = 2 e in
+// field units; float couplings: units of 2^-jexp, and |acc| < 2^31 because a
+// lane takes at most 32 sites of a colour).  Integer sums throughout.
+template <int JK, int WPT>
+__device__ __forceinline__ void flush_energy(int (&acc)[WPT], typename EnergyT<JK>::T* en, int jexp) {
+  const int lane = lane_id();
+  if constexpr (JK) {
+    double v[WPT];
+#pragma unroll
+    for (int b = 0; b < WPT; ++b) v[b] = (double)acc[b];
+    const double tot = transpose_sum<WPT>(v);  // integers below 2^53: exact in any order
+    if (lane < WPT && tot != 0.0) atomicAdd(&en[lane], ldexp(tot, 1 - jexp));
+  } else {
+    int v[WPT];
+#pragma unroll
+    for (int b = 0; b < WPT; ++b) v[b] = acc[b];
+    const int tot = transpose_sum<WPT>(v);
+    if (lane < WPT && tot != 0) atomicAdd(&en[lane], 2 * tot);
+  }
+}
 
 __device__ __forceinline__ uint32_t bit_of(uint32_t word, int pos) { return (word >> pos) & 1u; }
 
@@ -721,7 +769,7 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
         const int tb = (int)(((long long)ntasks * wave) / nwaves);
         const int te = (int)(((long long)ntasks * (wave + 1)) / nwaves);
         int cur_q = -1;
-        E_t acc[WPT];
+        int acc[WPT];  // per lane: sum of e over its accepted flips (dE = 2 e in field units)
         int tq[WPT], rowb[WPT];
         double bq[WPT];
         float lq[WPT];
@@ -731,13 +779,9 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
         for (int task = tb; task < te; ++task, (++chunk == nchunk ? (chunk = 0, ++qt) : 0)) {
           if (qt != cur_q) {
             if (cur_q >= 0) {
+              flush_energy<JK, WPT>(acc, energy + WPT * cur_q, U.jexp);
 #pragma unroll
-              for (int b = 0; b < WPT; ++b) {
-                E_t v = wave_sum(acc[b]);
-                if (JK) v = (E_t)ldexp((double)v, -U.jexp);  // units of 2^-jexp -> energy
-                if (lane == b && v != (E_t)0) atomicAdd(&energy[WPT * cur_q + b], v);
-                acc[b] = 0;
-              }
+              for (int b = 0; b < WPT; ++b) acc[b] = 0;
             }
             cur_q = qt;
 #pragma unroll
@@ -795,7 +839,7 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
                 const int e = Jsum - 2 * m;  // dE = e 2^(1 - jexp)
                 if (accept_int_field(u[b >> 2].w[b & 3], e, bq[b], lq[b], jq2)) {
                   flip |= 1u << b;
-                  acc[b] += (E_t)(2 * e);
+                  acc[b] += e;
                 }
               }
             } else {
@@ -819,7 +863,7 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
                 const int e = Jsum - 2 * m;  // dE = 2e
                 if (e <= 0 || u[b >> 2].w[b & 3] < thr[rowb[b] + e]) {
                   flip |= 1u << b;
-                  acc[b] += (E_t)(2 * e);
+                  acc[b] += e;
                 }
               }
             }
@@ -827,14 +871,7 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
             metro_cnt += __popc(flip);
           }
         }
-        if (cur_q >= 0) {
-#pragma unroll
-          for (int b = 0; b < WPT; ++b) {
-            E_t v = wave_sum(acc[b]);
-            if (JK) v = (E_t)ldexp((double)v, -U.jexp);
-            if (lane == b && v != (E_t)0) atomicAdd(&energy[WPT * cur_q + b], v);
-          }
-        }
+        if (cur_q >= 0) flush_energy<JK, WPT>(acc, energy + WPT * cur_q, U.jexp);
         __syncthreads();
       }
       {
