@@ -945,23 +945,35 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
             // (no stores in the loop, so its loads can all be in flight at once)
             int n = 0;
             uint32_t mw0 = 0, mw1 = 0, aw0 = 0, aw1 = 0;
-            for (int s2 = 0; s2 * 64 < N; ++s2) {
-              const int i = s2 * 64 + lane;
-              uint32_t qb = 0, ab = 0;
-              if (i < N) {
-                ab = bit_of(rowa[i], pa);
-                qb = ab ^ bit_of(rowb[i], pb) ^ gx;
+            for (int s0 = 0; s0 * 64 < N; s0 += 4) {
+              // four rows of 64 sites: all loads first (clamped to the last
+              // site, whose bits past N are dropped below), then the ballots
+              uint32_t va[4], vb[4];
+#pragma unroll
+              for (int u = 0; u < 4; ++u) {
+                const int i = min((s0 + u) * 64 + lane, N - 1);
+                va[u] = rowa[i];
+                vb[u] = rowb[i];
               }
-              const unsigned long long bq = __ballot(qb), ba = __ballot(ab);
-              n += __popcll(bq);
-              const int w0 = (2 * s2) & 63;  // words 2 s2, 2 s2 + 1 go to lanes w0, w0 + 1
-              const bool lo = lane == w0, hi = lane == w0 + 1;
-              if (2 * s2 < 64) {
-                mw0 = lo ? (uint32_t)bq : (hi ? (uint32_t)(bq >> 32) : mw0);
-                aw0 = lo ? (uint32_t)ba : (hi ? (uint32_t)(ba >> 32) : aw0);
-              } else {
-                mw1 = lo ? (uint32_t)bq : (hi ? (uint32_t)(bq >> 32) : mw1);
-                aw1 = lo ? (uint32_t)ba : (hi ? (uint32_t)(ba >> 32) : aw1);
+#pragma unroll
+              for (int u = 0; u < 4; ++u) {
+                const int s2 = s0 + u;
+                if (s2 * 64 >= N) break;
+                const bool in = s2 * 64 + lane < N;
+                const uint32_t ab = in ? bit_of(va[u], pa) : 0u;
+                const uint32_t qb = in ? (ab ^ bit_of(vb[u], pb) ^ gx) : 0u;
+                const unsigned long long bq = __ballot(qb), ba = __ballot(ab);
+                n += __popcll(bq);
+                // words 2 s2 and 2 s2 + 1 go to lanes w0 and w0 + 1
+                const int w0 = (2 * s2) & 63;
+                const bool lo = lane == w0, hi = lane == w0 + 1;
+                if (2 * s2 < 64) {
+                  mw0 = lo ? (uint32_t)bq : (hi ? (uint32_t)(bq >> 32) : mw0);
+                  aw0 = lo ? (uint32_t)ba : (hi ? (uint32_t)(ba >> 32) : aw0);
+                } else {
+                  mw1 = lo ? (uint32_t)bq : (hi ? (uint32_t)(bq >> 32) : mw1);
+                  aw1 = lo ? (uint32_t)ba : (hi ? (uint32_t)(ba >> 32) : aw1);
+                }
               }
             }
             n = uniform(n);
