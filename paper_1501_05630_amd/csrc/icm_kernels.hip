@@ -108,13 +108,17 @@ __device__ __forceinline__ double wave_sum(double v) {
   return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
 }
 
+// Prefix sums over the wave by DPP: shifts by 1, 2, 4, 8 within each 16-lane
+// row (zeros shifted in) give the rows' inclusive scans, then each row's last
+// lane is broadcast into the rows after it (row_bcast 15 and 31).
 __device__ __forceinline__ int wave_exclusive_scan(int v) {
   int x = v;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    int y = __shfl_up(x, o, 64);
-    if (lane_id() >= o) x += y;
-  }
+  x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xF, 0xF, false);  // row_shr:1
+  x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xF, 0xF, false);  // row_shr:2
+  x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xF, 0xF, false);  // row_shr:4
+  x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xF, 0xF, false);  // row_shr:8
+  x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xA, 0xF, false);  // row_bcast:15 into rows 1, 3
+  x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xC, 0xF, false);  // row_bcast:31 into rows 2, 3
   return x - v;
 }
 
@@ -265,6 +269,14 @@ __device__ __forceinline__ void flush_energy(int (&acc)[WPT], typename EnergyT<J
 }
 
 __device__ __forceinline__ uint32_t bit_of(uint32_t word, int pos) { return (word >> pos) & 1u; }
+
+// acc + a b for signed 24-bit a and b (one v_mad_i32_i24; the compiler would
+// turn a multiply by a 0/-1 value into selects)
+__device__ __forceinline__ int mad_i24(int a, int b, int acc) {
+  int r;
+  asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(acc));
+  return r;
+}
 
 // Spin (+1/-1) of byte b of an int8 quad word.
 __device__ __forceinline__ int spin_of(uint32_t word, int b) {
@@ -831,12 +843,13 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
 #pragma unroll
               for (int b = 0; b < WPT; ++b) {
                 if (tq[b] >= K) continue;
-                // the bit extracted sign-extended (0 or -1) masks J_d
-                int m = 0;
+                // the bit extracted sign-extended (0 or -1) times J_d (24-bit
+                // integers): mn = -sum_d J_d x_d
+                int mn = 0;
 #pragma unroll
                 for (int d = 0; d < DEG; ++d)
-                  m += Ji[d] & __builtin_amdgcn_sbfe((int)xw[d], (unsigned)(sh + b), 1u);
-                const int e = Jsum - 2 * m;  // dE = e 2^(1 - jexp)
+                  mn = mad_i24(__builtin_amdgcn_sbfe((int)xw[d], (unsigned)(sh + b), 1u), Ji[d], mn);
+                const int e = Jsum + 2 * mn;  // dE = e 2^(1 - jexp)
                 if (accept_int_field(u[b >> 2].w[b & 3], e, bq[b], lq[b], jq2)) {
                   flip |= 1u << b;
                   acc[b] += e;
@@ -856,11 +869,11 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
 #pragma unroll
               for (int b = 0; b < WPT; ++b) {
                 if (tq[b] >= K) continue;
-                int m = 0;
+                int mn = 0;
 #pragma unroll
                 for (int d = 0; d < DEG; ++d)
-                  m += Ji[d] & __builtin_amdgcn_sbfe((int)xw[d], (unsigned)(sh + b), 1u);
-                const int e = Jsum - 2 * m;  // dE = 2e
+                  mn = mad_i24(__builtin_amdgcn_sbfe((int)xw[d], (unsigned)(sh + b), 1u), Ji[d], mn);
+                const int e = Jsum + 2 * mn;  // dE = 2e
                 if (e <= 0 || u[b >> 2].w[b & 3] < thr[rowb[b] + e]) {
                   flip |= 1u << b;
                   acc[b] += e;
@@ -979,48 +992,59 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
             n = uniform(n);
             const bool twoa = (flags & kFlag2a) && 2 * n > N;
             // step 2a: reverse the second replica (the q-mask complements);
-            // the cluster and frontier start empty
-            for (int w = lane, k2 = 0; w < nw; w += 64, ++k2) {
+            // the cluster and frontier start empty.  Lane l's mask words
+            // (l and l + 64) stay in registers for the seed search.
+#pragma unroll
+            for (int k2 = 0; k2 < 2; ++k2) {
+              const int w = lane + 64 * k2;
               uint32_t mword = k2 ? mw1 : mw0;
               if (twoa) {
                 const int rem_bits = N - 32 * w;
-                const uint32_t valid = rem_bits >= 32 ? ~0u : ((1u << rem_bits) - 1u);
+                const uint32_t valid = rem_bits >= 32 ? ~0u : (rem_bits > 0 ? (1u << rem_bits) - 1u : 0u);
                 mword = ~mword & valid;
               }
-              mc[2 * w] = mword;
-              mc[2 * w + 1] = 0;
-              aw[w] = k2 ? aw1 : aw0;
-              f0[w] = 0;
+              if (k2) mw1 = mword; else mw0 = mword;
+              if (w < nw) {
+                mc[2 * w] = mword;
+                mc[2 * w + 1] = 0;
+                aw[w] = k2 ? aw1 : aw0;
+                f0[w] = 0;
+              }
             }
             if (twoa) n = N - n;
-            wave_sync();
             int seedsite = -1;
             if (n > 0) {
-              // step 2b: the idx-th q = -1 site in ascending order seeds the cluster
+              // step 2b: the idx-th q = -1 site in ascending order seeds the
+              // cluster, found from a wave prefix of the words' popcounts
               int rem = (int)(((unsigned long long)icmu[mv] * (unsigned long long)n) >> 32);
-              for (int w0 = 0; w0 < nw; w0 += 64) {
-                const int w = w0 + lane;
-                const uint32_t word = w < nw ? mc[2 * w] : 0u;
+              for (int k2 = 0; 64 * k2 < nw; ++k2) {
+                const uint32_t word = lane + 64 * k2 < nw ? (k2 ? mw1 : mw0) : 0u;
                 const int c = __popc(word);
                 const int excl = wave_exclusive_scan(c);
                 const int tot = __builtin_amdgcn_readlane(excl + c, 63);
                 if (rem < tot) {
-                  if (rem >= excl && rem < excl + c) {
+                  const bool mine = rem >= excl && rem < excl + c;
+                  int pos = 0;
+                  if (mine) {
                     uint32_t x = word;
                     for (int r2 = rem - excl; r2 > 0; --r2) x &= x - 1u;
-                    const int pos = __builtin_ctz(x);
-                    f0[w] = 1u << pos;
-                    mc[2 * w + 1] = 1u << pos;
-                    info[kInSeed] = 32 * w + pos;
+                    pos = __builtin_ctz(x);
                   }
+                  const int src = (int)__builtin_ctzll(__ballot(mine));
+                  seedsite = 32 * (64 * k2 + src) + __builtin_amdgcn_readlane(pos, src);
                   break;
                 }
                 rem -= tot;
               }
-              wave_sync();
-              seedsite = uniform(info[kInSeed]);
+              // the same wave stored the words above, so these land after them
+              if (lane == 0) {
+                f0[seedsite >> 5] = 1u << (seedsite & 31);
+                mc[2 * (seedsite >> 5) + 1] = 1u << (seedsite & 31);
+                info[kInSeed] = seedsite;
+              }
             }
             if (record) {
+              wave_sync();
               // full labelling for the readout: union-find over the q = -1
               // subgraph, roots hooked towards the smaller index, path compression
               int* parent = (int*)(lds + lay.parent) + slot * N;
