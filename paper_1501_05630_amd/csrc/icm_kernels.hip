@@ -239,6 +239,33 @@ __device__ __forceinline__ void uf_union(int* parent, int a, int b) {
   }
 }
 
+// Sum over the set bits b of bb of +-J for the bond in slot d of site
+// 32 w + b (J in the coupling table's integer units): -J where replica a is
+// anti-aligned across the bond (anti bit set).  Four bits per round, so their
+// coupling loads are in flight together (the address of a spent round is site
+// 32 w, always valid, and its value is dropped).  One word: at most 32 sites x
+// 6 slots of 24-bit values, within an int.
+template <int JK, int DEG>
+__device__ __forceinline__ int boundary_sum(uint32_t bb, uint32_t anti, int w, int d, const int32_t* cf,
+                                            const int8_t* cj) {
+  int s = 0;
+  while (bb) {
+    int jv[4], pos[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const bool ok = bb != 0u;
+      pos[u] = ok ? __builtin_ctz(bb) : 0;
+      bb &= bb - 1u;
+      const int x = (32 * w + pos[u]) * DEG + d;
+      const int v = JK ? cf[x] : (int)cj[x];
+      jv[u] = ok ? v : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s += ((anti >> pos[u]) & 1u) ? -jv[u] : jv[u];
+  }
+  return s;
+}
+
 template <int JK>
 struct EnergyT;
 template <>
@@ -933,6 +960,17 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
         // moves are dealt round-robin over the ICM waves, so every wave gets a
         // mix of cold (small clusters) and warm temperatures
         for (int mbase = wave; mbase < nmoves; mbase += iwaves * P) {
+          // the walkers, gauge parity and seed draw of the wave's moves, read
+          // at once (lane g for move g) ahead of their set-ups
+          int la = 0, lb = 0, lgx = 0;
+          uint32_t lu = 0;
+          if (lane < P && mbase + lane * iwaves < nmoves) {
+            const int mvl = mbase + lane * iwaves, kl = mvl / half, pl = mvl - kl * half;
+            la = at[kl * R + 2 * pl];
+            lb = at[kl * R + 2 * pl + 1];
+            lgx = gauge[la] ^ gauge[lb];
+            lu = icmu[mvl];
+          }
           // ---- set-up, one move at a time with the full wave ----
 #pragma unroll 1
           for (int g = 0; g < P; ++g) {
@@ -947,12 +985,11 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
               if (lane == 0) { info[kInMv] = -1; info[kInN] = 0; }
               continue;
             }
-            const int k = mv / half, p = mv - k * half;
-            const int a = at[k * R + 2 * p], b = at[k * R + 2 * p + 1];
+            const int a = __builtin_amdgcn_readlane(la, g), b = __builtin_amdgcn_readlane(lb, g);
             const uint32_t* rowa = sp + (a >> 5) * N;
             const uint32_t* rowb = sp + (b >> 5) * N;
             const int pa = a & 31, pb = b & 31;
-            const uint32_t gx = (uint32_t)(gauge[a] ^ gauge[b]);
+            const uint32_t gx = (uint32_t)__builtin_amdgcn_readlane(lgx, g);
             // q_i = -1 <=> the replicas differ at i; 64 sites per ballot.  Lane l
             // keeps words l and l + 64 of the mask and of replica a in registers
             // (no stores in the loop, so its loads can all be in flight at once)
@@ -1016,7 +1053,8 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
             if (n > 0) {
               // step 2b: the idx-th q = -1 site in ascending order seeds the
               // cluster, found from a wave prefix of the words' popcounts
-              int rem = (int)(((unsigned long long)icmu[mv] * (unsigned long long)n) >> 32);
+              const uint32_t um = (uint32_t)__builtin_amdgcn_readlane((int)lu, g);
+              int rem = (int)(((unsigned long long)um * (unsigned long long)n) >> 32);
               for (int k2 = 0; 64 * k2 < nw; ++k2) {
                 const uint32_t word = lane + 64 * k2 < nw ? (k2 ? mw1 : mw0) : 0u;
                 const int c = __popc(word);
@@ -1176,6 +1214,7 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
           }
           // ---- bonds leaving the cluster, then the flips ----
           E_t dEa = 0;
+          int ib = 0;  // one word per lane: the lane's boundary sum fits an int
           int csize = 0;
           {
             const int ga = ginfo[kInA], gb = ginfo[kInB];
@@ -1195,18 +1234,7 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
               for (int d = 0; d < 6; ++d) {
                 uint32_t bb = cw & ~cd[d];
                 const uint32_t anti = awd ^ ad[d];
-                while (bb) {
-                  const int bpos = __builtin_ctz(bb);
-                  bb &= bb - 1u;
-                  const int x = (32 * li + bpos) * DEG + d;
-                  if (JK) {
-                    const double J = (double)cf[x];
-                    dEa += ((anti >> bpos) & 1u) ? -J : J;
-                  } else {
-                    const int J = cj[x];
-                    dEa += ((anti >> bpos) & 1u) ? -J : J;
-                  }
-                }
+                ib += boundary_sum<JK, DEG>(bb, anti, li, d, cf, cj);
               }
               for (uint32_t fl = cw; fl; fl &= fl - 1u) {
                 const int i = 32 * li + __builtin_ctz(fl);
@@ -1246,18 +1274,7 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
                 const uint32_t exist = d < 4 ? ~0u : (d == 4 ? (cs.m[1] | cs.m[3]) : (cs.m[0] | cs.m[2]));
                 uint32_t bb = cw & ~nb & exist;
                 const uint32_t anti = awd ^ na;
-                while (bb) {
-                  const int bpos = __builtin_ctz(bb);
-                  bb &= bb - 1u;
-                  const int x = (32 * li + bpos) * DEG + d;
-                  if (JK) {
-                    const double J = (double)cf[x];
-                    dEa += ((anti >> bpos) & 1u) ? -J : J;
-                  } else {
-                    const int J = cj[x];
-                    dEa += ((anti >> bpos) & 1u) ? -J : J;
-                  }
-                }
+                ib += boundary_sum<JK, DEG>(bb, anti, li, d, cf, cj);
               }
               for (uint32_t fl = cw; fl; fl &= fl - 1u) {
                 const int i = 32 * li + __builtin_ctz(fl);
@@ -1283,18 +1300,7 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
                 const uint32_t na = reg_term(awd, lane, s0, m0) | reg_term(awd, lane, s1, m1);
                 uint32_t bb = cw & ~nb;
                 const uint32_t anti = awd ^ na;
-                while (bb) {
-                  const int bpos = __builtin_ctz(bb);
-                  bb &= bb - 1u;
-                  const int x = (32 * li + bpos) * DEG + d;
-                  if (JK) {
-                    const double J = (double)cf[x];
-                    dEa += ((anti >> bpos) & 1u) ? -J : J;
-                  } else {
-                    const int J = cj[x];
-                    dEa += ((anti >> bpos) & 1u) ? -J : J;
-                  }
-                }
+                ib += boundary_sum<JK, DEG>(bb, anti, li, d, cf, cj);
               }
               for (uint32_t fl = cw; fl; fl &= fl - 1u) {
                 const int i = 32 * li + __builtin_ctz(fl);
@@ -1372,6 +1378,7 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
               }
             }
           }
+          dEa += (E_t)ib;
           // per-group sums: DPP row sums are 16-lane sums, groups are 1, 2 or 4 rows
           {
             E_t rows[4];
@@ -1386,21 +1393,23 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
               for (int r2 = 0; r2 < 4; ++r2) rows[r2] = (E_t)__builtin_amdgcn_readlane(iv, 16 * r2);
             }
             const int sites = wave_sum(csize);
-            if (lane == 0) {
-              const int rpg = 4 / P;  // DPP rows per group
-              for (int g = 0; g < P; ++g) {
-                const int* inf = (const int*)((uint32_t*)(lds + lay.slots) + (wave * P + g) * sw +
-                                              2 * (nw + 2) + 3 * nw);
-                if (inf[kInMv] < 0 || inf[kInN] == 0) continue;
-                E_t sum = 0;
-                for (int r2 = g * rpg; r2 < (g + 1) * rpg; ++r2) sum += rows[r2];
+            if (lane < P) {
+              // lane g updates the two walkers of move g (distinct walkers)
+              const int g = lane, rpg = 4 / P;  // DPP rows per group
+              const int* inf = (const int*)((uint32_t*)(lds + lay.slots) + (wave * P + g) * sw +
+                                            2 * (nw + 2) + 3 * nw);
+              E_t sum = 0;
+#pragma unroll
+              for (int r2 = 0; r2 < 4; ++r2)
+                if (r2 / rpg == g) sum += rows[r2];
+              if (inf[kInMv] >= 0 && inf[kInN] != 0) {
                 // float couplings: sums in units of 2^-jexp (exact scaling)
                 if (JK) sum = (E_t)ldexp((double)sum, -U.jexp);
                 energy[inf[kInA]] += (E_t)2 * sum;
                 energy[inf[kInB]] -= (E_t)2 * sum;
               }
-              if (sites) atomicAdd(&stats[kStatIcmSites], (unsigned long long)sites);
             }
+            if (lane == 0 && sites) atomicAdd(&stats[kStatIcmSites], (unsigned long long)sites);
           }
           wave_sync();
         }
