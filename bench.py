@@ -262,7 +262,7 @@ def run_thermalization(args):
         ctx.icm_run(hs, args.thermalization)
         ctx.icm_sync()
         wall = time.perf_counter() - t0
-        unit = 2.0 ** -32 if spec["kind"] == "gauss" else 1.0 / spec["j_scale"]
+        unit = icm.OBS_ENERGY_UNIT_FLOAT if spec["kind"] == "gauss" else 1.0 / spec["j_scale"]
         deltas = []
         for h, (temps, N, nb) in zip(hs, meta):
             sums, counts = ctx.icm_read_observables(h)
@@ -336,7 +336,7 @@ def run_table1(args):
                     if L2 != L:
                         continue
                     sums, counts = ctx.icm_read_observables(h)
-                    d.append(icm.delta_per_bin(sums, counts, temps, N, nb, 2.0 ** -32)[2][:, 0])
+                    d.append(icm.delta_per_bin(sums, counts, temps, N, nb, icm.OBS_ENERGY_UNIT_FLOAT)[2][:, 0])
                     p.append(icm.cluster_fraction_per_bin(sums, counts, N))
                 complete = [int(c) == (1 << b) for b, c in enumerate(counts)]
                 last = max(b for b in range(len(complete)) if complete[b])
@@ -633,6 +633,15 @@ def main():
                           "frac": achieved_gbs / HBM_PEAK_GBS,
                           "bytes_per_attempt": bytes_per_sweep / attempts_per_sweep},
     }
+    # the cluster moves' own accounting: a move reads both replicas' N spins and
+    # writes the |C| flipped sites in both (2 N + 2 <|C|> bytes as int8)
+    st = [ctx.icm_read_stats(h) for h in hs]
+    moves = sum(x["icm_moves"] for x in st)
+    if moves:
+        mean_c = sum(x["icm_cluster_sites"] for x in st) / moves
+        out["icm"] = {"mean_cluster_sites": mean_c,
+                      "nontrivial_fraction": sum(x["icm_nontrivial"] for x in st) / moves,
+                      "bytes_per_move": 2 * sum(sizes) / len(sizes) + 2 * mean_c}
     if not args.no_per_instance:
         # plain per-instance launches over a sample spread evenly over the batch
         k = min(args.per_instance_sample, n_inst)

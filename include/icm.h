@@ -191,7 +191,10 @@ int icm_read_stats(icm_ctx* ctx, int32_t handle, icm_stats* out);
    logarithmic time bins: a step that ends at sweep count t (t = 1, 2, ...)
    lands in bin floor(log2 t).  Requires ICM_FLAG_MEASURE.
    sums [ICM_OBS_BINS][K][R/2][ICM_OBS_FIELDS], int64:
-     0: E_a + E_b in raw energy units (see icm_read_energies),
+     0: E_a + E_b, in units of 1/j_scale for integer couplings and of 2^-20
+        for float couplings (exact: their energies are multiples of the
+        coupling grid; coarser than the 2^-32 of icm_read_energies so that a
+        bin of up to ~2^29 steps at 4096 sites stays within int64),
      1: sum over bonds of q_i q_j = N_b q_l (q_i = s_a,i s_b,i),
      2: (sum_i q_i)^2,
      3: min(n, N - n), n = sites with q_i = -1: the potential cluster sites

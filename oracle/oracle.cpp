@@ -447,7 +447,11 @@ void measure(orc_sim* s, uint32_t t_after) {
       int64_t link = 0;
       for (const Bond& e : s->bonds) link += q[e.i] * q[e.j];
       int64_t* o = &s->obs[(((size_t)bin * s->K + k) * (s->R / 2) + p) * ORC_OBS_FIELDS];
-      o[0] += s->energy[a] + s->energy[b];
+      // float couplings: in units of 2^-20 (every energy is a multiple of
+      // 2^-jexp with jexp <= 20, so the division is exact), which keeps a
+      // bin's sum within int64 for bins of up to ~2^29 steps at N = 4096
+      const int64_t e2 = s->energy[a] + s->energy[b];
+      o[0] += s->p.jkind == ORC_J_F32 ? e2 / 4096 : e2;
       o[1] += link;
       o[2] += qsum * qsum;
       const int64_t nminus = ((int64_t)s->N - qsum) / 2;

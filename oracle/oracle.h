@@ -114,7 +114,8 @@ void orc_bonds(const orc_sim* s, int32_t* bonds_ij, int64_t* j_raw);
 /* Observable sums [ORC_OBS_BINS][K][R/2][ORC_OBS_FIELDS] and sample counts
    [ORC_OBS_BINS], accumulated since the last orc_init_hot / orc_set_states.  A step that ends at sweep count t (t = 1, 2, ...) lands in
    bin floor(log2 t).  Fields per pair of chains (2p, 2p+1) at temperature k:
-   0: E_a + E_b (raw energy units), 1: sum over bonds of q_i q_j = N_b - 2 D
+   0: E_a + E_b (units of 1/j_scale for integer couplings, 2^-20 for float
+   couplings), 1: sum over bonds of q_i q_j = N_b - 2 D
    (D = bonds whose ends have different site overlaps q_i = s_a,i s_b,i),
    2: (sum_i q_i)^2, 3: min(n, N - n) for n sites with q_i = -1 (the potential
    cluster sites after step 2a). */

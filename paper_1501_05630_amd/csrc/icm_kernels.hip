@@ -661,8 +661,10 @@ __device__ __noinline__ void measure_step(uint32_t t_end, int N, int K, int R, i
     const int D = wave_sum(diff);
     if (lane == 0) {
       int64_t* o = obs + (((size_t)bin * K + k) * half + p) * kObsFields;
-      const int64_t ea = JK ? (int64_t)((double)energy[a] * 0x1p32) : (int64_t)energy[a];
-      const int64_t eb = JK ? (int64_t)((double)energy[b] * 0x1p32) : (int64_t)energy[b];
+      // float couplings in units of 2^-20 (energies are multiples of 2^-jexp,
+      // jexp <= 20: exact), so long bins stay within int64
+      const int64_t ea = JK ? (int64_t)((double)energy[a] * 0x1p20) : (int64_t)energy[a];
+      const int64_t eb = JK ? (int64_t)((double)energy[b] * 0x1p20) : (int64_t)energy[b];
       const int64_t q = (int64_t)N - 2 * n;
       o[0] += ea + eb;
       o[1] += (int64_t)nbonds - 2 * D;

@@ -19,6 +19,7 @@ TOPO_SQUARE2D, TOPO_CUBIC3D, TOPO_CHIMERA = 0, 1, 2
 J_INT8, J_F32 = 0, 1
 FLAG_2A, FLAG_PT, FLAG_RECORD_LABELS, FLAG_SKIP_METRO, FLAG_MEASURE = 1, 2, 4, 8, 16
 OBS_BINS, OBS_FIELDS = 32, 4
+OBS_ENERGY_UNIT_FLOAT = 2.0 ** -20   # observable field 0 for float couplings
 
 _P = ctypes.c_void_p
 _I32, _U32, _U64, _SZ = ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_size_t

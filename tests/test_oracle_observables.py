@@ -35,7 +35,7 @@ def bin_counts(t0, n):
 
 
 @pytest.mark.parametrize("top,L,kind,scale", [(inputs.SQUARE2D, 4, "pmJ", 1), (inputs.CUBIC3D, 2, "pmJ", 1),
-                                              (inputs.CHIMERA, 2, "int3", 3)])
+                                              (inputs.CHIMERA, 2, "int3", 3), (inputs.CUBIC3D, 4, "gauss", 1)])
 def test_frozen_states_give_closed_forms(top, L, kind, scale):
     rng = inputs.make_rng(90, L * 10 + top)
     J = inputs.make_couplings(kind, top, L, rng)
@@ -70,9 +70,15 @@ def test_frozen_states_give_closed_forms(top, L, kind, scale):
         assert sums[:, k, p, 1].sum() == link * total, (k, p)
         assert sums[:, k, p, 2].sum() == q2 * total, (k, p)
         assert sums[:, k, p, 3].sum() == ncl * total, (k, p)
-        ea = exact.energy(top, L, np.asarray(J, np.float64) / scale, st[k, 2 * p])
-        eb = exact.energy(top, L, np.asarray(J, np.float64) / scale, st[k, 2 * p + 1])
-        assert sums[:, k, p, 0].sum() == round((ea + eb) * scale) * total, (k, p)
+        # integer couplings: units of 1/j_scale; float couplings: J on its
+        # 2^-20 grid, energies in units of 2^-20
+        if kind == "gauss":
+            Jq, unit = np.rint(np.asarray(J, np.float64) * 2.0 ** 20) * 2.0 ** -20, 2.0 ** 20
+        else:
+            Jq, unit = np.asarray(J, np.float64) / scale, scale
+        ea = exact.energy(top, L, Jq, st[k, 2 * p])
+        eb = exact.energy(top, L, Jq, st[k, 2 * p + 1])
+        assert sums[:, k, p, 0].sum() == round((ea + eb) * unit) * total, (k, p)
 
 
 def exact_pair_observables(top, L, J, temps):
@@ -120,8 +126,8 @@ def test_link_and_spin_overlap_match_exact_enumeration():
         assert abs(ql[k] - ref[k, 1]) < 4 * se[k, 1] / Nb + 1e-9, (k, ql[k], ref[k, 1])
         assert abs(q2[k] - ref[k, 2]) < 4 * se[k, 2] + 1e-9, (k, q2[k], ref[k, 2])
         assert abs(m[k, 3] - ref[k, 3]) < 4 * se[k, 3] + 1e-9, (k, m[k, 3], ref[k, 3])
-        e = m[k, 0] * 2.0 ** -32 / 2        # raw units of the 2^-32 grid, two replicas
-        assert abs(e - ref[k, 0]) < 4 * se[k, 0] * 2.0 ** -32 / 2 + 1e-9, (k, e, ref[k, 0])
+        e = m[k, 0] * 2.0 ** -20 / 2        # float couplings: units of 2^-20, two replicas
+        assert abs(e - ref[k, 0]) < 4 * se[k, 0] * 2.0 ** -20 / 2 + 1e-9, (k, e, ref[k, 0])
 
 
 def test_delta_vanishes_for_gaussian_disorder_exactly_averaged():
@@ -151,7 +157,7 @@ def test_delta_helper_reproduces_eq_1_and_2_from_the_sums():
     s.init_hot()
     s.run(12)
     sums, counts = s.observables()
-    e_ql, e, delta = icm.delta_per_bin(sums, counts, temps, s.N, 2 * s.N, 2.0 ** -32)
+    e_ql, e, delta = icm.delta_per_bin(sums, counts, temps, s.N, 2 * s.N, icm.OBS_ENERGY_UNIT_FLOAT)
     st = s.states()
     bonds = exact.bond_list(top, L, np.asarray(J, np.float64))
     for k, T in enumerate(temps):
