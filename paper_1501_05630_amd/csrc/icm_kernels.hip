@@ -1064,11 +1064,19 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
                 const int tot = __builtin_amdgcn_readlane(excl + c, 63);
                 if (rem < tot) {
                   const bool mine = rem >= excl && rem < excl + c;
+                  // position of the (rem - excl)-th set bit of the word, by halving
                   int pos = 0;
-                  if (mine) {
+                  {
+                    int kk = rem - excl;
                     uint32_t x = word;
-                    for (int r2 = rem - excl; r2 > 0; --r2) x &= x - 1u;
-                    pos = __builtin_ctz(x);
+#pragma unroll
+                    for (int h = 16; h >= 1; h >>= 1) {
+                      const int ch = __popc(x & ((1u << h) - 1u));
+                      const bool up = kk >= ch;
+                      kk = up ? kk - ch : kk;
+                      x = up ? x >> h : x;
+                      pos = up ? pos + h : pos;
+                    }
                   }
                   const int src = (int)__builtin_ctzll(__ballot(mine));
                   seedsite = 32 * (64 * k2 + src) + __builtin_amdgcn_readlane(pos, src);
