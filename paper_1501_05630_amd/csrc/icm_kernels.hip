@@ -1583,8 +1583,10 @@ __device__ __forceinline__ void perc_sync() {
   else __syncthreads();
 }
 
-template <int WAVES>
-__global__ void __launch_bounds__(64 * WAVES) percolation_kernel(const uint16_t* __restrict__ nbr, int N, int deg,
+// A site's DEG neighbours are fetched together (from the cached table) before
+// its unions, so their latencies overlap.
+template <int WAVES, int DEG>
+__global__ void __launch_bounds__(64 * WAVES) percolation_kernel(const uint16_t* __restrict__ nbr, int N,
                                                                  unsigned long long thr, uint32_t sample0,
                                                                  uint32_t n_samples, uint32_t seed, uint32_t key,
                                                                  int32_t* __restrict__ smax) {
@@ -1613,8 +1615,12 @@ __global__ void __launch_bounds__(64 * WAVES) percolation_kernel(const uint16_t*
     // occupied one always holds a site index
     for (int i = tid; i < N; i += NT) {
       if (uf_load<SC>(parent, i) < 0) continue;
-      for (int d = 0; d < deg; ++d) {
-        const int j = nbr[i * deg + d];
+      int jn[DEG];
+#pragma unroll
+      for (int d = 0; d < DEG; ++d) jn[d] = nbr[i * DEG + d];
+#pragma unroll
+      for (int d = 0; d < DEG; ++d) {
+        const int j = jn[d];
         if (j > i && uf_load<SC>(parent, j) >= 0) uf_union<SC>(parent, i, j);
       }
     }
@@ -1683,8 +1689,9 @@ int icmk_set_lds_limit(size_t bytes) {
     hipError_t r = hipFuncSetAttribute(fns[x], hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (r != hipSuccess) e = r;
   }
-  const void* perc[2] = {(const void*)icm::percolation_kernel<1>, (const void*)icm::percolation_kernel<4>};
-  for (int x = 0; x < 2; ++x) {
+  const void* perc[4] = {(const void*)icm::percolation_kernel<1, 4>, (const void*)icm::percolation_kernel<1, 6>,
+                         (const void*)icm::percolation_kernel<4, 4>, (const void*)icm::percolation_kernel<4, 6>};
+  for (int x = 0; x < 4; ++x) {
     hipError_t r = hipFuncSetAttribute(perc[x], hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (r != hipSuccess) e = r;
   }
@@ -1715,19 +1722,22 @@ int icmk_launch_percolation(const uint16_t* nbr, int N, int deg, unsigned long l
                             uint32_t n_samples, uint32_t seed, uint32_t key, int32_t* smax, int n_cus,
                             size_t lds_cu, hipStream_t stream) {
   if (n_samples == 0) return 0;
-  if (N < 1 || N > icm::kMaxPercSites || n_cus < 1) return (int)hipErrorInvalidValue;
+  if (N < 1 || N > icm::kMaxPercSites || n_cus < 1 || (deg != 4 && deg != 6)) return (int)hipErrorInvalidValue;
   const size_t lds = icmk_percolation_lds(N);
   if (lds > lds_cu) return (int)hipErrorInvalidValue;
   const int waves = N <= 1024 ? 1 : 4;
   const int per_cu = std::max(1, std::min(32 / waves, (int)(lds_cu / lds)));
   const uint32_t nb = (uint32_t)(n_cus * per_cu);
   const uint32_t g = n_samples < nb ? n_samples : nb;
-  if (waves == 1)
-    hipLaunchKernelGGL(icm::percolation_kernel<1>, dim3(g), dim3(64), lds, stream, nbr, N, deg, thr, sample0,
-                       n_samples, seed, key, smax);
-  else
-    hipLaunchKernelGGL(icm::percolation_kernel<4>, dim3(g), dim3(256), lds, stream, nbr, N, deg, thr, sample0,
-                       n_samples, seed, key, smax);
+#define ICM_PERC(W, D)                                                                                   \
+  hipLaunchKernelGGL((icm::percolation_kernel<W, D>), dim3(g), dim3(64 * W), lds, stream, nbr, N, thr,   \
+                     sample0, n_samples, seed, key, smax)
+  if (waves == 1) {
+    if (deg == 4) ICM_PERC(1, 4); else ICM_PERC(1, 6);
+  } else {
+    if (deg == 4) ICM_PERC(4, 4); else ICM_PERC(4, 6);
+  }
+#undef ICM_PERC
   return (int)hipGetLastError();
 }
 
