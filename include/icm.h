@@ -230,7 +230,7 @@ int icm_set_temperatures(icm_ctx* ctx, int32_t handle, const double* temps);
    (sample0 + s, i / 4, 0, 4) and key (context seed, key) is below
    floor(p 2^32).  smax[s] = the number of sites in the largest connected
    cluster of occupied sites (0 if none).  topology / L as in
-   icm_instance_desc, up to 16384 sites (the kernel keeps 8 N + 16 bytes in
+   icm_instance_desc, up to 16384 sites (the kernel keeps 8 N + 64 bytes in
    LDS, which must also fit the device's limit per workgroup); p in [0, 1].  smax: DEVICE pointer, int32
    [n_samples], owned by the caller; written asynchronously on the context
    stream (icm_sync, or any later call that synchronizes, completes it).

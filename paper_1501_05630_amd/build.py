@@ -19,7 +19,8 @@ def hipcc():
 
 def build(verbose: bool = False) -> str:
     os.makedirs(OUT_DIR, exist_ok=True)
-    srcs = [os.path.join(CSRC, "icm_kernels.hip"), os.path.join(CSRC, "icm_runtime.cpp")]
+    srcs = [os.path.join(CSRC, "icm_kernels.hip"), os.path.join(CSRC, "percolation_kernels.hip"),
+            os.path.join(CSRC, "icm_runtime.cpp")]
     cmd = [hipcc(), "-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-shared",
            "-Wall", "-Wno-unused-result", *DEVICE_FLAGS, *srcs, "-o", LIB + ".tmp", "-lpthread"]
     if verbose:

@@ -20,52 +20,14 @@
 
 #include <algorithm>
 
-#include "icm_internal.h"
+#include "icm_device.h"
 
 namespace icm {
 
-// ----------------------------------------------------------------------------
-// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32->64
-// multiplies by the Philox constants with the key added through xor; the key is
-// bumped by the golden-ratio Weyl increments between rounds.
-// ----------------------------------------------------------------------------
-struct Words4 {
-  uint32_t w[4];
-};
-
-__device__ __forceinline__ Words4 philox4x32_10(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3,
-                                                uint32_t key0, uint32_t key1) {
-  // The round keys are recomputed by scalar adds at every call: opaque to the
-  // optimiser here, so it does not hold all twenty of them in scalar registers
-  // across the sweep loop.
-  asm volatile("" : "+s"(key0), "+s"(key1));
-#pragma unroll
-  for (int round = 0; round < 10; ++round) {
-    const uint64_t m0 = (uint64_t)0xD2511F53u * x0;
-    const uint64_t m1 = (uint64_t)0xCD9E8D57u * x2;
-    // three-way xor in one v_bitop3_b32 (truth table 0x96)
-    const uint32_t y0 = __builtin_amdgcn_bitop3_b32((uint32_t)(m1 >> 32), x1, key0, 0x96);
-    const uint32_t y2 = __builtin_amdgcn_bitop3_b32((uint32_t)(m0 >> 32), x3, key1, 0x96);
-    x1 = (uint32_t)m1;
-    x3 = (uint32_t)m0;
-    x0 = y0;
-    x2 = y2;
-    key0 += 0x9E3779B9u;
-    key1 += 0xBB67AE85u;
-  }
-  Words4 r;
-  r.w[0] = x0; r.w[1] = x1; r.w[2] = x2; r.w[3] = x3;
-  return r;
-}
-
-enum : uint32_t { kStreamMetro = 0, kStreamInit = 1, kStreamIcm = 2, kStreamPt = 3, kStreamPerc = 4 };
 
 // ----------------------------------------------------------------------------
 // wavefront helpers (wave64)
 // ----------------------------------------------------------------------------
-__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
-// wave index, known to the compiler as uniform (kept in a scalar register)
-__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
 // Sum over the 64 lanes of a wave (all lanes active), returned to every lane.
 // DPP: butterfly inside each quad, then half-row and row mirrors give every
@@ -148,13 +110,6 @@ __device__ __forceinline__ T transpose_sum(T (&v)[NV]) {
   return r;
 }
 
-// Orders this wave's LDS accesses around the call (lanes of one wave exchange
-// data through LDS between ICM phases).
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
@@ -204,40 +159,6 @@ __device__ __forceinline__ bool accept_int_field(uint32_t u, int e, double beta,
   return accept_exact(u, (double)e * jq2, beta);
 }
 
-// ----------------------------------------------------------------------------
-// union-find on an LDS parent array (parent[x] <= x; roots satisfy parent[x] == x)
-// ----------------------------------------------------------------------------
-// SCOPE: the lanes that share the array (one wave, or a whole workgroup).
-template <int SCOPE = __HIP_MEMORY_SCOPE_WAVEFRONT>
-__device__ __forceinline__ int uf_load(int* parent, int x) {
-  return __hip_atomic_load(&parent[x], __ATOMIC_RELAXED, SCOPE);
-}
-
-template <int SCOPE = __HIP_MEMORY_SCOPE_WAVEFRONT>
-__device__ __forceinline__ int uf_find(int* parent, int x) {
-  int p = uf_load<SCOPE>(parent, x);
-  while (p != x) {
-    x = p;
-    p = uf_load<SCOPE>(parent, x);
-  }
-  return x;
-}
-
-// Hooks the larger root under the smaller one with atomicMin; when the target
-// stopped being a root meanwhile, continues with the value it pointed to, so
-// no link is ever lost.  Component roots end up at their minimum site index.
-template <int SCOPE = __HIP_MEMORY_SCOPE_WAVEFRONT>
-__device__ __forceinline__ void uf_union(int* parent, int a, int b) {
-  while (true) {
-    a = uf_find<SCOPE>(parent, a);
-    b = uf_find<SCOPE>(parent, b);
-    if (a == b) return;
-    if (a > b) { int t = a; a = b; b = t; }
-    const int old = __hip_atomic_fetch_min(&parent[b], a, __ATOMIC_RELAXED, SCOPE);
-    if (old == b) return;
-    b = old;
-  }
-}
 
 // Sum over the set bits b of bb of +-J for the bond in slot d of site
 // 32 w + b (J in the coupling table's integer units): -J where replica a is
@@ -1558,93 +1479,6 @@ __global__ void energy_kernel(const uint32_t* spins, const uint16_t* nbr, const 
   if (threadIdx.x == 0) energy[w] = part[0] / 2;
 }
 
-// ----------------------------------------------------------------------------
-// Site percolation (the chimera threshold study of the Supplemental Material):
-// each sample occupies every site independently with probability p and
-// reports the size of its largest cluster of occupied sites.  One workgroup of
-// WAVES waves per sample (a grid-stride loop over samples): site i is occupied
-// iff word i mod 4 of Philox(sample, i / 4, 0, 4) is below floor(p 2^32);
-// union-find over the bonds between occupied sites (hooking to the smaller
-// root), the component sizes by LDS atomics at the roots, then a maximum.
-// LDS: parent and size arrays of N ints and one int per wave.
-// ----------------------------------------------------------------------------
-__device__ __forceinline__ int wave_max(int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    const int y = __shfl_xor(v, o, 64);
-    v = y > v ? y : v;
-  }
-  return v;
-}
-
-template <int WAVES>
-__device__ __forceinline__ void perc_sync() {
-  if (WAVES == 1) wave_sync();
-  else __syncthreads();
-}
-
-// A site's DEG neighbours are fetched together (from the cached table) before
-// its unions, so their latencies overlap.
-template <int WAVES, int DEG>
-__global__ void __launch_bounds__(64 * WAVES) percolation_kernel(const uint16_t* __restrict__ nbr, int N,
-                                                                 unsigned long long thr, uint32_t sample0,
-                                                                 uint32_t n_samples, uint32_t seed, uint32_t key,
-                                                                 int32_t* __restrict__ smax) {
-  constexpr int SC = WAVES == 1 ? __HIP_MEMORY_SCOPE_WAVEFRONT : __HIP_MEMORY_SCOPE_WORKGROUP;
-  constexpr int NT = 64 * WAVES;
-  extern __shared__ __align__(16) unsigned char lds[];
-  int* parent = (int*)lds;  // -1: empty site
-  int* size = parent + N;
-  int* wmax = size + N;     // [WAVES]
-  const int tid = threadIdx.x;
-  for (uint32_t s = blockIdx.x; s < n_samples; s += gridDim.x) {
-    const uint32_t sample = sample0 + s;
-    for (int q = tid; 4 * q < N; q += NT) {
-      const Words4 u = philox4x32_10(sample, (uint32_t)q, 0u, kStreamPerc, seed, key);
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const int i = 4 * q + b;
-        if (i < N) {
-          parent[i] = (unsigned long long)u.w[b] < thr ? i : -1;
-          size[i] = 0;
-        }
-      }
-    }
-    perc_sync<WAVES>();
-    // each bond once, from its smaller end; an empty site never changes, an
-    // occupied one always holds a site index
-    for (int i = tid; i < N; i += NT) {
-      if (uf_load<SC>(parent, i) < 0) continue;
-      int jn[DEG];
-#pragma unroll
-      for (int d = 0; d < DEG; ++d) jn[d] = nbr[i * DEG + d];
-#pragma unroll
-      for (int d = 0; d < DEG; ++d) {
-        const int j = jn[d];
-        if (j > i && uf_load<SC>(parent, j) >= 0) uf_union<SC>(parent, i, j);
-      }
-    }
-    perc_sync<WAVES>();
-    for (int i = tid; i < N; i += NT)
-      if (uf_load<SC>(parent, i) >= 0) atomicAdd(&size[uf_find<SC>(parent, i)], 1);
-    perc_sync<WAVES>();
-    int m = 0;
-    for (int i = tid; i < N; i += NT) m = size[i] > m ? size[i] : m;
-    m = wave_max(m);
-    if (WAVES == 1) {
-      if (tid == 0) smax[s] = m;
-    } else {
-      if ((tid & 63) == 0) wmax[tid >> 6] = m;
-      __syncthreads();
-      if (tid == 0) {
-        int best = wmax[0];
-        for (int w = 1; w < WAVES; ++w) best = wmax[w] > best ? wmax[w] : best;
-        smax[s] = best;
-      }
-    }
-    perc_sync<WAVES>();
-  }
-}
 
 }  // namespace icm
 
@@ -1689,12 +1523,6 @@ int icmk_set_lds_limit(size_t bytes) {
     hipError_t r = hipFuncSetAttribute(fns[x], hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (r != hipSuccess) e = r;
   }
-  const void* perc[4] = {(const void*)icm::percolation_kernel<1, 4>, (const void*)icm::percolation_kernel<1, 6>,
-                         (const void*)icm::percolation_kernel<4, 4>, (const void*)icm::percolation_kernel<4, 6>};
-  for (int x = 0; x < 4; ++x) {
-    hipError_t r = hipFuncSetAttribute(perc[x], hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    if (r != hipSuccess) e = r;
-  }
   return (int)e;
 }
 
@@ -1714,32 +1542,6 @@ int icmk_launch_scatter(uint32_t* spins, const int8_t* src, int N, int Wq, int W
   return (int)hipGetLastError();
 }
 
-size_t icmk_percolation_lds(int N) { return 8u * (size_t)N + 16u; }
-
-// n_cus compute units with lds_cu bytes of LDS each: the grid is what fits
-// resident at once (samples are dealt over it by the grid-stride loop).
-int icmk_launch_percolation(const uint16_t* nbr, int N, int deg, unsigned long long thr, uint32_t sample0,
-                            uint32_t n_samples, uint32_t seed, uint32_t key, int32_t* smax, int n_cus,
-                            size_t lds_cu, hipStream_t stream) {
-  if (n_samples == 0) return 0;
-  if (N < 1 || N > icm::kMaxPercSites || n_cus < 1 || (deg != 4 && deg != 6)) return (int)hipErrorInvalidValue;
-  const size_t lds = icmk_percolation_lds(N);
-  if (lds > lds_cu) return (int)hipErrorInvalidValue;
-  const int waves = N <= 1024 ? 1 : 4;
-  const int per_cu = std::max(1, std::min(32 / waves, (int)(lds_cu / lds)));
-  const uint32_t nb = (uint32_t)(n_cus * per_cu);
-  const uint32_t g = n_samples < nb ? n_samples : nb;
-#define ICM_PERC(W, D)                                                                                   \
-  hipLaunchKernelGGL((icm::percolation_kernel<W, D>), dim3(g), dim3(64 * W), lds, stream, nbr, N, thr,   \
-                     sample0, n_samples, seed, key, smax)
-  if (waves == 1) {
-    if (deg == 4) ICM_PERC(1, 4); else ICM_PERC(1, 6);
-  } else {
-    if (deg == 4) ICM_PERC(4, 4); else ICM_PERC(4, 6);
-  }
-#undef ICM_PERC
-  return (int)hipGetLastError();
-}
 
 int icmk_launch_energy(const uint32_t* spins, const uint16_t* nbr, const void* coup, int N, int deg,
                        int Wp, int jkind, int jexp, int64_t* energy, hipStream_t stream) {

@@ -28,6 +28,7 @@ int icmk_launch_sweep(const icm::UnitDesc* d_units, int n_units, int jkind, int 
                       uint32_t n_sweeps, int threads, int icm_slots, size_t lds_bytes,
                       hipStream_t stream);
 int icmk_set_lds_limit(size_t bytes);
+int icmk_set_percolation_lds_limit(size_t bytes);
 int icmk_launch_init(uint32_t* spins, int N, int Wq, int W, uint32_t seed, uint32_t key,
                      hipStream_t stream);
 int icmk_launch_scatter(uint32_t* spins, const int8_t* src, int N, int Wq, int W,
@@ -936,6 +937,7 @@ int icm_create(icm_ctx** out, int device, void* stream, void* arena, size_t aren
       lds_cu > 0)
     c->lds_cu = std::max(c->lds_limit, (size_t)lds_cu);
   (void)icmk_set_lds_limit(c->lds_limit);
+  (void)icmk_set_percolation_lds_limit(c->lds_limit);
   (void)hipGetLastError();
   *out = c.release();
   return ICM_OK;

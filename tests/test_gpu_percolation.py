@@ -27,11 +27,14 @@ def oracle_for(top, L, key):
     return orc.Sim(top, L, J, [1.0], 2, 0, flags=0, seed=SEED, instance_key=key, j_scale=scale)
 
 
+# The launch takes 1, 2, 4, 8 or 16 waves per sample by size (the fewest that
+# fill a compute unit within its LDS); every width is covered, with ragged N.
 CASES = [(inputs.SQUARE2D, 2), (inputs.SQUARE2D, 6), (inputs.SQUARE2D, 32), (inputs.SQUARE2D, 64),
-         (inputs.CUBIC3D, 2), (inputs.CUBIC3D, 6), (inputs.CUBIC3D, 10), (inputs.CUBIC3D, 16),
+         (inputs.CUBIC3D, 2), (inputs.CUBIC3D, 6), (inputs.CUBIC3D, 10), (inputs.CUBIC3D, 12),
+         (inputs.CUBIC3D, 16),
          (inputs.CHIMERA, 1), (inputs.CHIMERA, 3), (inputs.CHIMERA, 7), (inputs.CHIMERA, 12),
-         (inputs.CHIMERA, 22),
-         # beyond the 4096 sites of a simulated instance: four waves per sample
+         (inputs.CHIMERA, 15), (inputs.CHIMERA, 22),
+         # beyond the 4096 sites of a simulated instance: sixteen waves per sample
          (inputs.CHIMERA, 33), (inputs.SQUARE2D, 90), (inputs.CUBIC3D, 24)]
 
 
