@@ -629,7 +629,9 @@ def main():
                    "L": list(spec["sides"]) if uneven else spec["L"],
                    "N": sorted(set(sizes)) if uneven else sizes[0], "temps": spec["n_temps"],
                    "replicas": spec["n_replicas"], "icm_temps": moves_per_sweep[0] * 2 // spec["n_replicas"],
-                   "sweeps_per_step": spsw, "threads": args.threads,
+                   "sweeps_per_step": spsw,
+                   "threads": sorted({icm.launch_threads(n, args.threads) for n in sizes}),
+                   "threads_requested": args.threads,
                    "icm_slots": args.icm_slots, "graph": bool(args.graph),
                    "parallelism": "single GPU, one workgroup per instance"},
         "icm_moves_per_s": icm_moves / secs,

@@ -116,6 +116,15 @@ def coupling_kind(couplings):
     return J_F32 if np.asarray(couplings).dtype.kind == "f" else J_INT8
 
 
+def launch_threads(n_sites, threads):
+    """Threads per workgroup that icm_run launches for units of n_sites sites
+    when icm_run_config.threads is `threads`: size classes above 512, 1024 and
+    2048 sites take at least 512, 1024 and 1024 threads (the rule the header
+    states for icm_run_config.threads)."""
+    floor = 0 if n_sites <= 512 else (512 if n_sites <= 1024 else 1024)
+    return max(int(threads), floor)
+
+
 def make_desc(topology, L, couplings, temps, n_replicas, icm_ntemps,
               flags=FLAG_2A | FLAG_PT, instance_key=0, j_scale=1, jkind=None):
     """InstanceDesc plus the numpy buffers it points into (keep both alive)."""

@@ -37,3 +37,16 @@ def test_algorithmic_counts_of_the_bench_workload():
     assert bench.algorithmic_ops_per_attempt(6, "int3") == 26
     assert bench.algorithmic_ops_per_move(512) == 1024
     assert abs(bench.VALU_PEAK_TOPS - 39.3216) < 1e-9
+
+
+def test_launch_threads_follows_the_size_classes():
+    # icm_run_config.threads applies to units of up to 512 sites; the classes
+    # above take at least 512 (<= 1024 sites) and 1024 threads
+    from paper_1501_05630_amd import icm
+    assert icm.launch_threads(512, 256) == 256
+    assert icm.launch_threads(513, 256) == 512
+    assert icm.launch_threads(1024, 256) == 512
+    assert icm.launch_threads(1024, 1024) == 1024
+    assert icm.launch_threads(1152, 256) == 1024
+    assert icm.launch_threads(4096, 512) == 1024
+    assert icm.launch_threads(64, 512) == 512
