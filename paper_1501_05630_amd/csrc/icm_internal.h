@@ -55,6 +55,8 @@ struct UnitDesc {
   uint32_t flags, seed, key;
   int32_t topo, L;          // lattice kind (ICM_TOPO_*) and side / cells per side
   int32_t jexp;             // float couplings: grid exponent (J = coup 2^-jexp)
+  int32_t jpl;              // int8 couplings with cluster moves held in registers: bit planes of J
+                            // (two's complement width of the couplings), else 0
 };
 
 constexpr uint32_t kFlag2a = 1, kFlagPt = 2, kFlagRecord = 4, kFlagSkipMetro = 8, kFlagMeasure = 16;
@@ -66,8 +68,8 @@ ICM_HD uint32_t align16(uint32_t x) { return (x + 15u) & ~15u; }
 // Spins are bit-packed in LDS: word (g, i) holds walkers 32g..32g+31 at site i,
 // bit set = spin down.
 struct LdsLayout {
-  uint32_t sp, nbr, clist, coup, tau, at, gauge, energy, thr, beta, bl2e, dbl2e, ptu, icmu, terms, slots,
-      parent, meas, stats, total;
+  uint32_t sp, nbr, clist, coup, tau, at, gauge, energy, thr, beta, bl2e, dbl2e, ptu, icmu, terms, jplanes,
+      slots, parent, meas, stats, total;
 };
 
 // Neighbour relation of the lattice as bit shifts of a site bitset (for the
@@ -95,10 +97,23 @@ ICM_HD int slots_reserved(int N, int slots) {
 
 ICM_HD int bit_words(int Wq) { return (4 * Wq + 31) / 32; }
 
+// Bit planes kept for int8 couplings j in [jmin, jmax]: the two's complement
+// width, when cluster moves run with their bitsets in registers (at most 64
+// words, one per lane); 0 otherwise.
+ICM_HD int coupling_planes(int jkind, int Kc, int N, int jmin, int jmax) {
+  if (jkind != 0 || Kc <= 0 || site_words(N) > 64) return 0;
+  int p = 1;
+  while (jmin < -(1 << (p - 1)) || jmax > (1 << (p - 1)) - 1) ++p;
+  return p;
+}
+
 // tables = 1: neighbour table, colour lists and couplings are copied into LDS;
 // tables = 0: they are read from global memory (for units too large otherwise).
+// jpl: bit planes of the int8 couplings kept for the cluster moves' boundary
+// sums (word [(w deg + d) jpl + k] = bit k of J over the 32 sites of word w,
+// slot d), 0 for none.
 ICM_HD LdsLayout lds_layout(int N, int deg, int Wq, int K, int R, int HM, int jkind, int slots,
-                            int tables, int extras, int Kc) {
+                            int tables, int extras, int Kc, int jpl) {
   // extras: bit 0 = ICM labels recorded, bit 1 = observables measured
   const int record = extras & 1, measure = extras & 2;
   LdsLayout L{};
@@ -121,6 +136,7 @@ ICM_HD LdsLayout lds_layout(int N, int deg, int Wq, int K, int R, int HM, int jk
   L.ptu = o;     o = align16(o + 4u * (K > 1 ? K - 1 : 1) * R);
   L.icmu = o;    o = align16(o + 4u * (Kc > 0 ? Kc * (R / 2) : 1));
   L.terms = o;   o = align16(o + (Kc > 0 ? 4u * kMaxTerms * (1 + site_words(N)) : 0u));
+  L.jplanes = o; o = align16(o + 4u * (uint32_t)jpl * deg * site_words(N));
   L.slots = o;   o = align16(o + 4u * slot_words(N) * ns);
   L.parent = o;  o = align16(o + (record ? 4u * N * ns : 0u));
   L.meas = o;    o = align16(o + (measure ? 4u * site_words(N) * 16u : 0u));  // q-mask words per wave

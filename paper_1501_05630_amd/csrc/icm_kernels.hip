@@ -187,6 +187,21 @@ __device__ __forceinline__ int boundary_sum(uint32_t bb, uint32_t anti, int w, i
   return s;
 }
 
+// The same sum for int8 couplings from their bit planes (pl: the jpl plane
+// words of this word and slot, two's complement): sum over a bit set M of J
+// is sum_k w_k popc(M & plane_k), w_k = 2^k and -2^(jpl-1) for the sign
+// plane; a handful of operations whatever the number of bits.
+__device__ __forceinline__ int boundary_sum_planes(uint32_t bb, uint32_t anti, const uint32_t* pl, int jpl) {
+  const uint32_t mp = bb & ~anti, mm = bb & anti;
+  int s = 0;
+  for (int k = 0; k < jpl; ++k) {
+    const uint32_t p = pl[k];
+    const int c = (int)__popc(mp & p) - (int)__popc(mm & p);
+    s += c * (k + 1 == jpl ? -(1 << k) : (1 << k));
+  }
+  return s;
+}
+
 template <int JK>
 struct EnergyT;
 template <>
@@ -611,7 +626,8 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
   const int N = U.N, Nc = U.Nc, W = U.W, Wq = U.Wq, K = U.K, R = U.R, Kc = U.Kc, HM = U.HM;
   const int Wp = 4 * Wq, G = bit_words(Wq);
   const LdsLayout lay = lds_layout(N, DEG, Wq, K, R, HM, JK, icm_slots, TL,
-                                   ((U.flags & kFlagRecord) ? 1 : 0) | ((U.flags & kFlagMeasure) ? 2 : 0), Kc);
+                                   ((U.flags & kFlagRecord) ? 1 : 0) | ((U.flags & kFlagMeasure) ? 2 : 0), Kc,
+                                   JK ? 0 : U.jpl);
 
   uint32_t* sp = (uint32_t*)(lds + lay.sp);
   // TL: tables in LDS; otherwise read-only global memory (cached in L1/L2)
@@ -690,6 +706,24 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
         if (i < N && term_holds(U.topo, U.L, t, i)) bits |= 1u << b;
       }
       tmask[x] = bits;
+    }
+    if (!JK && U.jpl > 0) {
+      // bit planes of the couplings: plane k of (word w, slot d) holds bit k
+      // (two's complement, jpl bits) of J over the sites 32 w .. 32 w + 31
+      const int jpl = U.jpl;
+      uint32_t* pl = (uint32_t*)(lds + lay.jplanes);
+      const int8_t* gj = (const int8_t*)U.coup;
+      for (int x = tid; x < nw * DEG; x += nthr) {
+        const int w = x / DEG, d = x - w * DEG;
+        uint32_t planes[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int b = 0; b < 32; ++b) {
+          const int i = 32 * w + b;
+          const uint32_t j = i < N ? (uint32_t)(uint8_t)gj[i * DEG + d] : 0u;
+#pragma unroll
+          for (int k = 0; k < 8; ++k) planes[k] |= ((j >> k) & 1u) << b;
+        }
+        for (int k = 0; k < jpl; ++k) pl[x * jpl + k] = planes[k];
+      }
     }
     const int ns = slots_reserved(N, icm_slots), sw = slot_words(N);
     uint32_t* sl0 = (uint32_t*)(lds + lay.slots);
@@ -1152,6 +1186,9 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
             uint32_t* rowa = sp + (ga >> 5) * N;
             uint32_t* rowb = sp + (gb >> 5) * N;
             const uint32_t fa = 1u << (ga & 31), fb = 1u << (gb & 31);
+            const int jpl = JK ? 0 : U.jpl;
+            const uint32_t* jplw = (const uint32_t*)(lds + lay.jplanes);
+            const int jw = min(li, nw - 1);  // lanes past the last word have no bits
             if (cube8) {
               // boundary bonds per direction d: i in the cluster, its d-neighbour
               // not (then outside the q-mask); anti-aligned in replica a where
@@ -1165,7 +1202,8 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
               for (int d = 0; d < 6; ++d) {
                 uint32_t bb = cw & ~cd[d];
                 const uint32_t anti = awd ^ ad[d];
-                ib += boundary_sum<JK, DEG>(bb, anti, li, d, cf, cj);
+                ib += (!JK && jpl > 0) ? boundary_sum_planes(bb, anti, jplw + (jw * DEG + d) * jpl, jpl)
+                                      : boundary_sum<JK, DEG>(bb, anti, li, d, cf, cj);
               }
               for (uint32_t fl = cw; fl; fl &= fl - 1u) {
                 const int i = 32 * li + __builtin_ctz(fl);
@@ -1205,7 +1243,8 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
                 const uint32_t exist = d < 4 ? ~0u : (d == 4 ? (cs.m[1] | cs.m[3]) : (cs.m[0] | cs.m[2]));
                 uint32_t bb = cw & ~nb & exist;
                 const uint32_t anti = awd ^ na;
-                ib += boundary_sum<JK, DEG>(bb, anti, li, d, cf, cj);
+                ib += (!JK && jpl > 0) ? boundary_sum_planes(bb, anti, jplw + (jw * DEG + d) * jpl, jpl)
+                                      : boundary_sum<JK, DEG>(bb, anti, li, d, cf, cj);
               }
               for (uint32_t fl = cw; fl; fl &= fl - 1u) {
                 const int i = 32 * li + __builtin_ctz(fl);
@@ -1231,7 +1270,8 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
                 const uint32_t na = reg_term(awd, lane, s0, m0) | reg_term(awd, lane, s1, m1);
                 uint32_t bb = cw & ~nb;
                 const uint32_t anti = awd ^ na;
-                ib += boundary_sum<JK, DEG>(bb, anti, li, d, cf, cj);
+                ib += (!JK && jpl > 0) ? boundary_sum_planes(bb, anti, jplw + (jw * DEG + d) * jpl, jpl)
+                                      : boundary_sum<JK, DEG>(bb, anti, li, d, cf, cj);
               }
               for (uint32_t fl = cw; fl; fl &= fl - 1u) {
                 const int i = 32 * li + __builtin_ctz(fl);

@@ -225,6 +225,7 @@ struct Instance {
   int N = 0, deg = 0, K = 0, R = 0, W = 0, Wq = 0, Wp = 0, Kc = 0, HM = 0, ptlen = 0;
   int jkind = 0, jscale = 1;
   int jexp = 0;                      // float couplings: grid exponent
+  int jpl = 0;                       // int8 couplings: bit planes for the cluster moves
   uint32_t flags = 0, key = 0;
   std::vector<double> temps;
   uint32_t sweep_host = 0;
@@ -236,7 +237,7 @@ struct Instance {
   size_t lds_bytes_at(int slots, int tables) const {
     return icm::lds_layout(N, deg, Wq, K, R, HM, jkind, slots, tables,
                            ((flags & ICM_FLAG_RECORD_LABELS) ? 1 : 0) | ((flags & ICM_FLAG_MEASURE) ? 2 : 0),
-                           Kc).total;
+                           Kc, jpl).total;
   }
 };
 
@@ -557,6 +558,15 @@ int add_instance_impl(icm_ctx* c, const icm_instance_desc* d, int32_t* out) {
   in->jexp = d->jkind == ICM_J_F32
                   ? grid_exponent((const float*)d->couplings, (size_t)coupling_count(d->topology, d->L))
                   : 0;
+  if (d->jkind == ICM_J_INT8) {
+    int jmin = 0, jmax = 0;
+    const int8_t* j8 = (const int8_t*)d->couplings;
+    for (size_t x = 0; x < (size_t)coupling_count(d->topology, d->L); ++x) {
+      jmin = std::min(jmin, (int)j8[x]);
+      jmax = std::max(jmax, (int)j8[x]);
+    }
+    in->jpl = icm::coupling_planes(0, in->Kc, in->N, jmin, jmax);
+  }
   in->flags = d->flags;
   in->key = d->instance_key;
   in->temps.assign(d->temps, d->temps + d->n_temps);
@@ -605,6 +615,7 @@ int add_instance_impl(icm_ctx* c, const icm_instance_desc* d, int32_t* out) {
   U.flags = in->flags;
   U.topo = T->topo;
   U.jexp = in->jexp;
+  U.jpl = in->jpl;
   U.L = T->L;
   U.seed = c->seed;
   U.key = in->key;
