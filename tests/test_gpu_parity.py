@@ -180,6 +180,29 @@ def test_each_cluster_search_layout_bit_exact(ctx, top, L, kind, K, R):
     ctx.icm_remove_instance(h)
 
 
+@pytest.mark.parametrize("top,L,jlo,jhi,scale", [
+    (inputs.CHIMERA, 6, -128, 127, 64),   # full int8 range: eight bit planes
+    (inputs.CUBIC3D, 8, -16, 15, 8),      # five planes, the 8^3 register layout
+    (inputs.SQUARE2D, 12, -100, 37, 32),  # asymmetric range: eight planes
+])
+def test_wide_integer_couplings_bit_exact(ctx, top, L, jlo, jhi, scale):
+    # integer couplings beyond +-3: the cluster moves' boundary sums take the
+    # couplings as two's-complement bit planes (as many as their width), so
+    # wide and asymmetric ranges, with both extremes present, must agree too
+    rng = inputs.make_rng(79, L * 10 + top)
+    J = inputs.make_couplings("int3", top, L, rng)
+    nz = J != 0
+    J = np.where(nz, rng.integers(jlo, jhi + 1, size=J.shape), 0).astype(np.int8)
+    flat = np.flatnonzero(nz)
+    J.flat[flat[0]], J.flat[flat[1]] = jlo, jhi
+    temps = inputs.geometric_temps(0.3, 2.0, 6)
+    h, o = make_pair(ctx, top, L, J, temps, 4, 4, icm.FLAG_2A | icm.FLAG_PT, key=17, j_scale=scale)
+    ctx.icm_init_states(h)
+    o.init_hot()
+    run_both(ctx, h, o, [1, 10], f"wide J top={top} L={L} [{jlo}, {jhi}]")
+    ctx.icm_remove_instance(h)
+
+
 def test_batched_per_instance_and_graph_agree(ctx):
     rng = inputs.make_rng(73, 0)
     specs = [(inputs.SQUARE2D, 8, "pmJ", 1, 16, 2), (inputs.CUBIC3D, 4, "gauss", 1, 10, 4),
