@@ -82,6 +82,8 @@ def _load():
     lib.orc_metro_accept_count.restype = ctypes.c_uint64
     lib.orc_percolation_smax.argtypes = [P, ctypes.c_double, U32, U32, P]
     lib.orc_percolation_smax.restype = None
+    lib.orc_icm_step.argtypes = [P, I32, I32, U32]
+    lib.orc_icm_step.restype = ctypes.c_int
     lib.orc_set_temperatures.argtypes = [P, P]
     lib.orc_set_temperatures.restype = ctypes.c_int
     _lib = lib
@@ -172,7 +174,7 @@ class Sim:
         return out
 
     def energy_unit(self):
-        return 1.0 / self.j_scale if self.jkind == J_INT8 else 2.0 ** -32
+        return 1.0 / self.j_scale if self.jkind == J_INT8 else 2.0 ** -40
 
     def energies(self):
         return self.energies_raw().astype(np.float64) * self.energy_unit()
@@ -206,6 +208,11 @@ class Sim:
         if rc != 0:
             raise ValueError("no ICM at this (k, pair)")
         return lab, int(seed.value), int(nm.value)
+
+    def icm_step(self, k, p, u):
+        """Steps 2a and 2b alone for pair p at temperature k with seed word u."""
+        if self._lib.orc_icm_step(self._h, k, p, int(u) & 0xFFFFFFFF) != 0:
+            raise ValueError("no ICM at this (k, pair)")
 
     def energy_raw(self, spins):
         s = np.ascontiguousarray(spins, dtype=np.int8)

@@ -72,16 +72,20 @@ struct orc_sim {
   std::vector<int64_t> obs;                // [32][K][R/2][4] observable sums
   std::vector<int64_t> obs_count;          // [32] samples per time bin
   std::vector<int32_t> last_seed, last_nminus;
-  int jexp = 0;                            // float couplings: grid 2^-jexp
+  // float couplings: the energy field of the observables, summed exactly in
+  // units of 2^-40 per [32][K][R/2] (a long bin can pass int64)
+  std::vector<__int128> obs_e;
 };
 
 namespace {
 
-// Float couplings are represented on the grid 2^-e, e the largest exponent
-// <= 20 for which every |J| 2^e rounds to at most 2^23 - 1 (e = 20 whenever
-// all |J| < 8): then every coupling is an integer multiple of 2^-e that a
-// signed 24-bit integer holds, and local fields and energy changes are exact
-// integer sums.  Raw energies are kept in units of 2^-32: raw = rint(J 2^e) 2^(32-e).
+// Float couplings are read exactly: the paper's model takes Gaussian J with no
+// stated precision, and the caller hands over float32 values, so the oracle
+// keeps each one as an integer multiple of 2^-40 (raw = J 2^40).  Every float32
+// with |J| >= 2^-17 is such a multiple (its last mantissa bit is worth at least
+// 2^-40); smaller ones move by at most 2^-41.  Local fields, energy changes and
+// energies are then exact integer sums in units of 2^-40 (|J| <= 64 keeps every
+// energy of up to 2^16 bonds within int64).
 int64_t n_couplings(const orc_params& p) {
   if (p.topology == ORC_SQUARE2D) return (int64_t)p.L * p.L * 2;
   if (p.topology == ORC_CUBIC3D) return (int64_t)p.L * p.L * p.L * 3;
@@ -89,19 +93,9 @@ int64_t n_couplings(const orc_params& p) {
   return p.n_edges;
 }
 
-int grid_exponent(const orc_params& p) {
-  double m = 0.0;
-  const int64_t n = n_couplings(p);
-  for (int64_t x = 0; x < n; ++x) m = std::max(m, std::fabs((double)((const float*)p.couplings)[x]));
-  int e = 20;
-  while (e > -32 && std::nearbyint(std::ldexp(m, e)) > 8388607.0) --e;
-  return e;
-}
-
-int64_t coupling_raw(const orc_params& p, int jexp, int64_t idx) {
+int64_t coupling_raw(const orc_params& p, int64_t idx) {
   if (p.jkind == ORC_J_INT8) return ((const int8_t*)p.couplings)[idx];
-  const double q = std::nearbyint(std::ldexp((double)((const float*)p.couplings)[idx], jexp));
-  return (int64_t)std::ldexp(q, 32 - jexp);
+  return (int64_t)std::nearbyint(std::ldexp((double)((const float*)p.couplings)[idx], 40));
 }
 
 bool coupling_valid(const orc_params& p, int64_t idx) {
@@ -139,7 +133,7 @@ int build_graph(orc_sim* s) {
                     x + L * y + L * L * ((z + 1) % L)};
       for (int d = 0; d < dim; ++d) {
         if (!coupling_valid(p, (int64_t)i * dim + d)) return -1;
-        add_bond(s, i, fwd[d], coupling_raw(p, s->jexp, (int64_t)i * dim + d));
+        add_bond(s, i, fwd[d], coupling_raw(p, (int64_t)i * dim + d));
       }
     }
     return 0;
@@ -157,14 +151,14 @@ int build_graph(orc_sim* s) {
           if (!coupling_valid(p, (int64_t)cell * 24 + e)) return -1;
         for (int u = 0; u < 4; ++u)
           for (int v = 4; v < 8; ++v)
-            add_bond(s, base + u, base + v, coupling_raw(p, s->jexp, (int64_t)cell * 24 + u * 4 + (v - 4)));
+            add_bond(s, base + u, base + v, coupling_raw(p, (int64_t)cell * 24 + u * 4 + (v - 4)));
         for (int u = 0; u < 4; ++u) {
-          int64_t raw = coupling_raw(p, s->jexp, (int64_t)cell * 24 + 16 + u);
+          int64_t raw = coupling_raw(p, (int64_t)cell * 24 + 16 + u);
           if (row + 1 < C) add_bond(s, base + u, 8 * ((row + 1) * C + col) + u, raw);
           else if (raw != 0) return -1;
         }
         for (int u = 4; u < 8; ++u) {
-          int64_t raw = coupling_raw(p, s->jexp, (int64_t)cell * 24 + 20 + (u - 4));
+          int64_t raw = coupling_raw(p, (int64_t)cell * 24 + 20 + (u - 4));
           if (col + 1 < C) add_bond(s, base + u, 8 * (row * C + col + 1) + u, raw);
           else if (raw != 0) return -1;
         }
@@ -181,7 +175,7 @@ int build_graph(orc_sim* s) {
       if (i < 0 || j < 0 || i >= s->N || j >= s->N || i == j) return -1;
       if (s->colour[i] == s->colour[j]) return -1;  // checkerboard needs a proper 2-colouring
       if (!coupling_valid(p, e)) return -1;
-      add_bond(s, i, j, coupling_raw(p, s->jexp, e));
+      add_bond(s, i, j, coupling_raw(p, e));
     }
     return 0;
   }
@@ -217,7 +211,7 @@ bool metro_accept(const orc_sim* s, int k, int64_t dE, uint32_t u) {
     uint32_t thr = clamp_threshold(std::exp(-(beta * (double)dE) / (double)s->p.j_scale));
     return u < thr;
   }
-  double p = std::exp(-(beta * std::ldexp((double)dE, -32)));
+  double p = std::exp(-(beta * std::ldexp((double)dE, -40)));
   return std::ldexp((double)u, -32) < p;
 }
 
@@ -262,8 +256,9 @@ void label_components(const orc_sim* s, const std::vector<char>& mask, std::vect
   }
 }
 
-// Steps 2a and 2b for the pair of chains (2p, 2p+1) at temperature k.
-void icm_move(orc_sim* s, int k, int p, uint32_t t) {
+// Steps 2a and 2b for the pair of chains (2p, 2p+1) at temperature k, the
+// seed drawn from the word u.
+void icm_move_with(orc_sim* s, int k, int p, uint32_t u) {
   int a = s->walker_at[k * s->R + 2 * p], b = s->walker_at[k * s->R + 2 * p + 1];
   int8_t* sa = &s->spin[(size_t)a * s->N];
   int8_t* sb = &s->spin[(size_t)b * s->N];
@@ -285,7 +280,6 @@ void icm_move(orc_sim* s, int k, int p, uint32_t t) {
   if (n == 0) { label.assign(s->N, -1); s->last_seed[slot] = -1; return; }
   // 2b: a uniformly chosen q = -1 site seeds the cluster: idx = floor(u n / 2^32)
   // picks the idx-th mask site in ascending site order.
-  uint32_t u = draw(s, (uint32_t)slot, t, 0u, kIcm, 0);
   int idx = (int)(((uint64_t)u * (uint64_t)n) >> 32);
   int seed = -1;
   for (int i = 0, seen = 0; i < s->N; ++i)
@@ -301,6 +295,11 @@ void icm_move(orc_sim* s, int k, int p, uint32_t t) {
   s->energy[b] = energy_of(s, sb);
   s->stats.icm_nontrivial++;
   s->stats.icm_cluster_sites += (uint64_t)size;
+}
+
+void icm_move(orc_sim* s, int k, int p, uint32_t t) {
+  const uint32_t slot = (uint32_t)(k * (s->R / 2) + p);
+  icm_move_with(s, k, p, draw(s, slot, t, 0u, kIcm, 0));
 }
 
 // Step 3: parallel tempering between neighbouring temperatures,
@@ -320,7 +319,7 @@ void pt_step(orc_sim* s, uint32_t t) {
           uint32_t thr = clamp_threshold(std::exp(-(dbeta * (double)D) / (double)s->p.j_scale));
           accept = u < thr;
         } else {
-          double p = std::exp(-(dbeta * std::ldexp((double)D, -32)));
+          double p = std::exp(-(dbeta * std::ldexp((double)D, -40)));
           accept = std::ldexp((double)u, -32) < p;
         }
       }
@@ -361,7 +360,6 @@ int orc_create(const orc_params* p, orc_sim** out) {
       if (!std::isfinite(J) || std::fabs(J) > 64.0f) { delete s; return -1; }
     }
   }
-  if (p->jkind == ORC_J_F32) s->jexp = grid_exponent(*p);
   if (build_graph(s) != 0) { delete s; return -1; }
   s->K = p->n_temps; s->R = p->n_replicas; s->W = s->K * s->R; s->Kc = p->icm_ntemps;
   s->beta.resize(s->K);
@@ -404,6 +402,7 @@ void orc_init_hot(orc_sim* s) {
   }
   s->sweep = 0;
   s->obs.clear();
+  s->obs_e.clear();
   s->obs_count.clear();
 }
 
@@ -416,6 +415,7 @@ void orc_set_states(orc_sim* s, const int8_t* spins, uint32_t sweep0) {
   }
   s->sweep = sweep0;
   s->obs.clear();
+  s->obs_e.clear();
   s->obs_count.clear();
 }
 
@@ -428,8 +428,10 @@ void orc_set_states(orc_sim* s, const int8_t* spins, uint32_t sweep0) {
 // is this count over N), summed per logarithmic time bin.  E(q_l) of Eq. 1 and
 // Delta of Eq. 2 follow from these sums and the bin counts.
 void measure(orc_sim* s, uint32_t t_after) {
+  const size_t pairs = (size_t)s->K * (s->R / 2);
   if (s->obs.empty()) {
-    s->obs.assign((size_t)ORC_OBS_BINS * s->K * (s->R / 2) * ORC_OBS_FIELDS, 0);
+    s->obs.assign((size_t)ORC_OBS_BINS * pairs * ORC_OBS_FIELDS, 0);
+    s->obs_e.assign((size_t)ORC_OBS_BINS * pairs, 0);
     s->obs_count.assign(ORC_OBS_BINS, 0);
   }
   int bin = 0;
@@ -446,12 +448,11 @@ void measure(orc_sim* s, uint32_t t_after) {
       }
       int64_t link = 0;
       for (const Bond& e : s->bonds) link += q[e.i] * q[e.j];
-      int64_t* o = &s->obs[(((size_t)bin * s->K + k) * (s->R / 2) + p) * ORC_OBS_FIELDS];
-      // float couplings: in units of 2^-20 (every energy is a multiple of
-      // 2^-jexp with jexp <= 20, so the division is exact), which keeps a
-      // bin's sum within int64 for bins of up to ~2^29 steps at N = 4096
+      const size_t slot = ((size_t)bin * s->K + k) * (s->R / 2) + p;
+      int64_t* o = &s->obs[slot * ORC_OBS_FIELDS];
       const int64_t e2 = s->energy[a] + s->energy[b];
-      o[0] += s->p.jkind == ORC_J_F32 ? e2 / 4096 : e2;
+      if (s->p.jkind == ORC_J_F32) s->obs_e[slot] += e2;  // units of 2^-40, reported in 2^-20
+      else o[0] += e2;
       o[1] += link;
       o[2] += qsum * qsum;
       const int64_t nminus = ((int64_t)s->N - qsum) / 2;
@@ -518,8 +519,16 @@ void orc_bonds(const orc_sim* s, int32_t* ij, int64_t* raw) {
 }
 
 void orc_get_observables(const orc_sim* s, int64_t* sums, int64_t* counts) {
-  const size_t n = (size_t)ORC_OBS_BINS * s->K * (s->R / 2) * ORC_OBS_FIELDS;
+  const size_t pairs = (size_t)s->K * (s->R / 2);
+  const size_t n = (size_t)ORC_OBS_BINS * pairs * ORC_OBS_FIELDS;
   for (size_t x = 0; x < n; ++x) sums[x] = s->obs.empty() ? 0 : s->obs[x];
+  if (s->p.jkind == ORC_J_F32 && !s->obs.empty())
+    for (size_t slot = 0; slot < (size_t)ORC_OBS_BINS * pairs; ++slot) {
+      // the bin's exact sum in units of 2^-40, rounded half up to a multiple of
+      // 2^-20 (exact whenever every energy is a multiple of 2^-20)
+      const __int128 v = s->obs_e[slot] + ((__int128)1 << 19);
+      sums[slot * ORC_OBS_FIELDS] = (int64_t)(v >> 20);
+    }
   for (int b = 0; b < ORC_OBS_BINS; ++b) counts[b] = s->obs_count.empty() ? 0 : s->obs_count[b];
 }
 
@@ -563,12 +572,18 @@ void orc_percolation_smax(const orc_sim* s, double p, uint32_t sample0, uint32_t
   }
 }
 
+int orc_icm_step(orc_sim* s, int32_t k, int32_t p, uint32_t u) {
+  if (k < 0 || k >= s->Kc || p < 0 || p >= s->R / 2) return -1;
+  icm_move_with(s, k, p, u);
+  return 0;
+}
+
 uint64_t orc_metro_accept_count(const orc_sim* s, int32_t k, int64_t dE) {
   if (dE <= 0) return 1ull << 32;
   double beta = s->beta[k];
   if (s->p.jkind == ORC_J_INT8)
     return clamp_threshold(std::exp(-(beta * (double)dE) / (double)s->p.j_scale));
-  double p = std::exp(-(beta * std::ldexp((double)dE, -32)));
+  double p = std::exp(-(beta * std::ldexp((double)dE, -40)));
   double x = std::ldexp(p, 32);  // accepted u satisfy u < x
   double c = std::ceil(x);
   return (uint64_t)c;

@@ -105,8 +105,8 @@ void orc_get_stats(const orc_sim* s, orc_stats* out);
 int orc_get_labels(const orc_sim* s, int32_t k, int32_t p, int32_t* labels,
                    int32_t* seed, int32_t* n_minus);
 
-/* Energy (raw units: 1/j_scale for INT8, 2^-32 for F32) of one spin
-   configuration [N]. */
+/* Energy (raw units: 1/j_scale for INT8; 2^-40 for F32, whose couplings are
+   kept exactly as multiples of 2^-40) of one spin configuration [N]. */
 int64_t orc_energy(const orc_sim* s, const int8_t* spins);
 /* The coupling of each bond as the oracle stores it, raw units, [n_bonds],
    with the endpoints in bonds_ij [n_bonds][2]. */
@@ -114,8 +114,9 @@ void orc_bonds(const orc_sim* s, int32_t* bonds_ij, int64_t* j_raw);
 /* Observable sums [ORC_OBS_BINS][K][R/2][ORC_OBS_FIELDS] and sample counts
    [ORC_OBS_BINS], accumulated since the last orc_init_hot / orc_set_states.  A step that ends at sweep count t (t = 1, 2, ...) lands in
    bin floor(log2 t).  Fields per pair of chains (2p, 2p+1) at temperature k:
-   0: E_a + E_b (units of 1/j_scale for integer couplings, 2^-20 for float
-   couplings), 1: sum over bonds of q_i q_j = N_b - 2 D
+   0: E_a + E_b (units of 1/j_scale for integer couplings; for float
+   couplings the bin's exact sum rounded to a multiple of 2^-20, exact when
+   every energy is one), 1: sum over bonds of q_i q_j = N_b - 2 D
    (D = bonds whose ends have different site overlaps q_i = s_a,i s_b,i),
    2: (sum_i q_i)^2, 3: min(n, N - n) for n sites with q_i = -1 (the potential
    cluster sites after step 2a). */
@@ -131,6 +132,12 @@ int orc_set_temperatures(orc_sim* s, const double* temps);
    is below floor(p 2^32); out[n - sample0] = size of the largest connected
    cluster of occupied sites. */
 void orc_percolation_smax(const orc_sim* s, double p, uint32_t sample0, uint32_t n_samples, int32_t* out);
+
+/* Steps 2a and 2b alone for the pair of chains (2p, 2p+1) at temperature k,
+   with u as the seed's random word (the word a step would draw), on the
+   current state: the move a simulation step makes, for tests that enumerate
+   every seed.  Returns 0, or -1 if (k, p) has no ICM. */
+int orc_icm_step(orc_sim* s, int32_t k, int32_t p, uint32_t u);
 
 /* Metropolis acceptance as a 2^-32 fraction for a raw energy change dE
    at temperature index k: returns the number of u in [0, 2^32) accepted. */

@@ -42,8 +42,8 @@ def test_gaussian_acceptance_matches_high_precision_exp():
     rng = np.random.default_rng(3)
     for k, T in enumerate(temps):
         for dE in rng.random(50) * 6:
-            raw = int(round(dE * 2 ** 32))
-            x = (-(Decimal(1) / Decimal(float(T))) * (Decimal(raw) / Decimal(2) ** 32)).exp() * Decimal(2) ** 32
+            raw = int(round(dE * 2 ** 40))
+            x = (-(Decimal(1) / Decimal(float(T))) * (Decimal(raw) / Decimal(2) ** 40)).exp() * Decimal(2) ** 32
             assert abs(s.metro_accept_count(k, raw) - x) <= 1.000001
 
 

@@ -70,15 +70,21 @@ def test_frozen_states_give_closed_forms(top, L, kind, scale):
         assert sums[:, k, p, 1].sum() == link * total, (k, p)
         assert sums[:, k, p, 2].sum() == q2 * total, (k, p)
         assert sums[:, k, p, 3].sum() == ncl * total, (k, p)
-        # integer couplings: units of 1/j_scale; float couplings: J on its
-        # 2^-20 grid, energies in units of 2^-20
+        # integer couplings: units of 1/j_scale; float couplings: the exact
+        # sum (J as given, units of 2^-40) of every bin rounded half up to a
+        # multiple of 2^-20
         if kind == "gauss":
-            Jq, unit = np.rint(np.asarray(J, np.float64) * 2.0 ** 20) * 2.0 ** -20, 2.0 ** 20
+            Jq = np.asarray(J, np.float64)
+            e2 = exact.energy(top, L, Jq, st[k, 2 * p]) + exact.energy(top, L, Jq, st[k, 2 * p + 1])
+            x = int(e2 * 2.0 ** 40)
+            assert x == e2 * 2.0 ** 40
+            want = sum((int(c) * x + (1 << 19)) >> 20 for c in counts)
+            assert sums[:, k, p, 0].sum() == want, (k, p)
         else:
-            Jq, unit = np.asarray(J, np.float64) / scale, scale
-        ea = exact.energy(top, L, Jq, st[k, 2 * p])
-        eb = exact.energy(top, L, Jq, st[k, 2 * p + 1])
-        assert sums[:, k, p, 0].sum() == round((ea + eb) * unit) * total, (k, p)
+            Jq = np.asarray(J, np.float64) / scale
+            ea = exact.energy(top, L, Jq, st[k, 2 * p])
+            eb = exact.energy(top, L, Jq, st[k, 2 * p + 1])
+            assert sums[:, k, p, 0].sum() == round((ea + eb) * scale) * total, (k, p)
 
 
 def exact_pair_observables(top, L, J, temps):
@@ -149,7 +155,7 @@ def test_delta_vanishes_for_gaussian_disorder_exactly_averaged():
 def test_delta_helper_reproduces_eq_1_and_2_from_the_sums():
     # delta_per_bin (used on the device sums) against a direct evaluation of
     # E(q_l) and <H/N> from the oracle's per-bin sums on frozen states
-    from paper_1501_05630_amd import icm
+    from paper_1501_05630_amd import analysis
     top, L = inputs.SQUARE2D, 4
     J = inputs.gaussian_couplings(top, L, inputs.make_rng(93, 0))
     temps = inputs.geometric_temps(0.6, 1.2, 2)
@@ -157,7 +163,7 @@ def test_delta_helper_reproduces_eq_1_and_2_from_the_sums():
     s.init_hot()
     s.run(12)
     sums, counts = s.observables()
-    e_ql, e, delta = icm.delta_per_bin(sums, counts, temps, s.N, 2 * s.N, icm.OBS_ENERGY_UNIT_FLOAT)
+    e_ql, e, delta = analysis.delta_per_bin(sums, counts, temps, s.N, 2 * s.N, analysis.OBS_ENERGY_UNIT_FLOAT)
     st = s.states()
     bonds = exact.bond_list(top, L, np.asarray(J, np.float64))
     for k, T in enumerate(temps):
@@ -171,7 +177,7 @@ def test_delta_helper_reproduces_eq_1_and_2_from_the_sums():
             assert abs(delta[b, k] - (ref_eql - ref_e)) < 1e-6
     # the cluster-site fraction helper: on frozen states every sample is
     # min(n, N - n) / N of the held pair
-    p = icm.cluster_fraction_per_bin(sums, counts, s.N)
+    p = analysis.cluster_fraction_per_bin(sums, counts, s.N)
     for k in range(len(temps)):
         n = int(np.sum(st[k, 0] != st[k, 1]))
         for b in np.flatnonzero(counts):
@@ -179,13 +185,13 @@ def test_delta_helper_reproduces_eq_1_and_2_from_the_sums():
 
 
 def test_thermalization_bin_reads_the_first_bin_that_stays_at_zero():
-    from paper_1501_05630_amd import icm
+    from paper_1501_05630_amd import analysis
     se = np.full(8, 0.1)
     full = [True] * 8
-    assert icm.thermalization_bin(np.array([-3, -2, -1, -0.5, -0.15, -0.1, 0.05, -0.02]), se, full) == 4
+    assert analysis.thermalization_bin(np.array([-3, -2, -1, -0.5, -0.15, -0.1, 0.05, -0.02]), se, full) == 4
     # a later excursion resets the start; the last bin off zero means not yet
-    assert icm.thermalization_bin(np.array([-3, -0.1, 0.0, -0.5, -0.1, 0.0, 0.0, 0.0]), se, full) == 4
-    assert icm.thermalization_bin(np.array([-3, -0.1, 0.0, 0.0, 0.0, 0.0, 0.0, -0.9]), se, full) is None
+    assert analysis.thermalization_bin(np.array([-3, -0.1, 0.0, -0.5, -0.1, 0.0, 0.0, 0.0]), se, full) == 4
+    assert analysis.thermalization_bin(np.array([-3, -0.1, 0.0, 0.0, 0.0, 0.0, 0.0, -0.9]), se, full) is None
     # incomplete bins are skipped
     part = [True] * 7 + [False]
-    assert icm.thermalization_bin(np.array([-3, -2, -0.1, 0, 0, 0, 0, -5.0]), se, part) == 2
+    assert analysis.thermalization_bin(np.array([-3, -2, -0.1, 0, 0, 0, 0, -5.0]), se, part) == 2

@@ -1,4 +1,6 @@
 """Oracle pins: graphs, couplings and the Hamiltonian (model paragraph)."""
+from fractions import Fraction
+
 import numpy as np
 import pytest
 
@@ -57,11 +59,10 @@ def test_energy_matches_layout_formula_and_spin_reversal(top, L):
             assert raw == s.energy_raw(-spins)
             ref = exact.energy(top, L, J, spins)
             if kind == "gauss":
-                # raw is in 2^-32 units of J rounded to the 2^-20 grid: exact
-                # against the formula on the rounded couplings
-                Jq = np.rint(np.asarray(J, np.float64) * 2.0 ** 20) * 2.0 ** -20
-                assert raw * 2.0 ** -32 == exact.energy(top, L, Jq, spins)
-                assert abs(raw * 2.0 ** -32 - ref) < s.n_bonds * 2.0 ** -21
+                # float couplings are kept exactly, as multiples of 2^-40: the
+                # raw energy is the formula's value on the float32 couplings
+                # themselves (at these sizes the float64 sum is exact too)
+                assert raw * 2.0 ** -40 == ref
             else:
                 assert raw == round(ref)
 
@@ -115,34 +116,52 @@ def test_chimera_rejects_couplings_off_the_grid():
         make(inputs.CHIMERA, 2, J)
 
 
-def test_gaussian_couplings_sit_on_the_2_pow_minus_20_grid():
-    # every |J| < 8: J is rounded to the nearest multiple of 2^-20 (a signed
-    # 24-bit integer), raw energies stay in units of 2^-32
+def test_gaussian_couplings_are_kept_exactly():
+    # the model's Gaussian J reach the oracle as float32 values and are used
+    # as given: every bond's raw coupling is J 2^40 with no rounding (float32
+    # with |J| >= 2^-17 are multiples of 2^-40), including values near the
+    # bound |J| <= 64 and values far from any coarse grid
     rng = inputs.make_rng(98, 0)
     J = inputs.gaussian_couplings(inputs.SQUARE2D, 4, rng)
-    s = make(inputs.SQUARE2D, 4, J)
-    ij, raw = s.bonds()
-    ref = [b[2] for b in exact.bond_list(inputs.SQUARE2D, 4, J)]
-    for r, j in zip(raw, ref):
-        assert r % (1 << 12) == 0
-        assert r * 2.0 ** -32 == np.rint(float(j) * 2.0 ** 20) * 2.0 ** -20
-        assert abs(r * 2.0 ** -32 - float(j)) <= 2.0 ** -21
-
-
-def test_large_gaussian_couplings_move_to_a_coarser_grid():
-    # one |J| = 40: 40 * 2^17 = 5242880 fits 24 signed bits, 40 * 2^18 does not
-    J = inputs.gaussian_couplings(inputs.SQUARE2D, 4, inputs.make_rng(98, 1))
-    J[3, 1] = np.float32(40.0)
+    J[0, 0] = np.float32(63.99999)
+    J[1, 1] = np.float32(-40.0)
+    J[2, 0] = np.float32(1.0 + 2.0 ** -23)          # the last mantissa bit of a unit value
+    J[3, 1] = np.float32(3.0 * 2.0 ** -17)          # the smallest binade that is exact
     s = make(inputs.SQUARE2D, 4, J)
     _, raw = s.bonds()
-    assert all(r % (1 << 15) == 0 for r in raw)
-    assert any(r % (1 << 16) != 0 for r in raw)
-    assert 40 * 2 ** 32 in list(raw)
+    ref = [b[2] for b in exact.bond_list(inputs.SQUARE2D, 4, J)]
+    for r, j in zip(raw, ref):
+        assert Fraction(int(r), 1 << 40) == Fraction(float(j))
+    assert int(raw[0]) == int(Fraction(float(np.float32(63.99999))) * (1 << 40))
 
 
-def test_brute_force_ground_state_of_ferromagnet_is_uniform():
-    top, L = inputs.SQUARE2D, 4
-    s = make(top, L, ones(top, L))
-    E = exact.all_energies(s.N, exact.bond_list(top, L, ones(top, L)))
-    assert E.min() == -s.n_bonds
-    assert np.count_nonzero(E == E.min()) == 2
+def test_tiny_gaussian_couplings_round_to_the_nearest_2_pow_minus_40():
+    # below 2^-17 a float32 has bits finer than 2^-40: the nearest multiple
+    J = np.ones((16, 2), dtype=np.float32)
+    J[5, 0] = np.float32(1.2345678e-7)
+    s = make(inputs.SQUARE2D, 4, J)
+    ij, raw = s.bonds()
+    x = [int(r) for (i, j), r in zip(ij, raw) if (i, j) == (5, 6)][0]
+    exact_scaled = Fraction(float(J[5, 0])) * (1 << 40)
+    assert abs(Fraction(x) - exact_scaled) <= Fraction(1, 2)
+
+
+def test_float_energy_change_is_exact_and_symmetric():
+    # the energies of a state and of its single-spin flips differ by exactly
+    # 2 s_i h_i on the raw couplings (integer sums in units of 2^-40)
+    rng = inputs.make_rng(98, 2)
+    J = inputs.gaussian_couplings(inputs.CUBIC3D, 4, rng)
+    s = make(inputs.CUBIC3D, 4, J)
+    ij, raw = s.bonds()
+    spins = np.where(rng.random(s.N) < 0.5, 1, -1).astype(np.int8)
+    E0 = s.energy_raw(spins)
+    for i in range(0, s.N, 7):
+        h = 0
+        for (a, b), r in zip(ij, raw):
+            if a == i:
+                h += int(r) * int(spins[b])
+            elif b == i:
+                h += int(r) * int(spins[a])
+        y = spins.copy()
+        y[i] = -y[i]
+        assert s.energy_raw(y) - E0 == 2 * int(spins[i]) * h
