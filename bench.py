@@ -1,13 +1,18 @@
 """Throughput of PT + isoenergetic cluster moves on one MI355X.
 
-A step is one fused sweep block (sweeps_per_step simulation steps: Metropolis
-sweep, ICM at the cold temperatures, PT) over the whole batch of the workload:
-1024 3D L=8 Gaussian instances, 20 temperatures x 4 replicas (the batched
-3D workload).  Inputs are synthetic and resident in HBM before timing starts.
+A step is SWEEPS_PER_STEP simulation steps (Metropolis sweep, cluster moves at
+the cold temperatures, PT) over the whole batch of the workload -- by default
+1024 3D L=8 Gaussian instances, 20 temperatures x 4 replicas -- issued as
+launches of the fused sweep-block kernel replayed from a captured hipGraph.
+Inputs are synthetic and resident in HBM before timing starts.
 
-Prints one JSON line:  value = spin-flip attempts/s over the whole job; also
-ICM moves/s, the same measured with plain per-instance launches, the roofline
-of the fused kernel and the CPU oracle's rate on a bounded sample.
+Prints one JSON line: value = spin-flip attempts/s over the whole job; also
+cluster moves/s, the same kernels with plain per-instance launches, the
+roofline of the fused kernel (effective HBM: algorithmic bytes over the
+kernel's launch time; beside it the VALU issue fraction from measured
+instruction counts), a short served run (continuous batching of the serving
+mix: p50/p99 latency and attempts/s against per-instance launches of the same
+requests) and the CPU oracle's rate on a bounded sample.
 """
 import argparse
 import json
@@ -23,18 +28,31 @@ HBM_PEAK_GBS = 8000.0
 # non-packed 32-bit or FP64 operation per lane per cycle)
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
+# Launch shape of the headline line unless the autotuner finds a faster one:
+# 256 threads per workgroup, 16 cluster moves in flight per workgroup, tables
+# placed by the library (in LDS for this workload), 256-sweep launches
+# replayed from a captured graph, four launches per step.
+DEFAULT_LAUNCH = dict(threads=256, icm_slots=16, sweeps_per_launch=256, use_graph=1, table_placement=0)
+SWEEPS_PER_STEP = 1024
+
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=16)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="3d_L8_gauss_1024inst")
-    ap.add_argument("--sweeps-per-step", type=int, default=256)
-    ap.add_argument("--threads", type=int, default=256)
-    ap.add_argument("--icm-slots", type=int, default=16)
+    ap.add_argument("--sweeps-per-step", type=int, default=SWEEPS_PER_STEP)
+    ap.add_argument("--sweeps-per-launch", type=int, default=DEFAULT_LAUNCH["sweeps_per_launch"])
+    ap.add_argument("--threads", type=int, default=DEFAULT_LAUNCH["threads"])
+    ap.add_argument("--icm-slots", type=int, default=DEFAULT_LAUNCH["icm_slots"])
     ap.add_argument("--graph", type=int, default=1)
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the launch shape of the flags instead of autotuning it")
+    ap.add_argument("--tune-cache", default="", help="autotuner cache file (default: search every run)")
     ap.add_argument("--per-instance-sample", type=int, default=32)
+    ap.add_argument("--served-requests", type=int, default=160,
+                    help="requests of the short served run in the default line (0: none)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-instance", action="store_true")
@@ -65,20 +83,6 @@ def algorithmic_bytes_per_sweep(spec, N, n_bonds, jbytes):
     return 2 * S * N + n_bonds * jbytes
 
 
-def algorithmic_ops_per_attempt(deg, kind):
-    """Fewest VALU lane-operations one Metropolis attempt needs: a quarter of a
-    Philox4x32-10 block (10 rounds of two 32x32->64 multiplies and two 3-input
-    xors), one bit extract and one multiply-add per neighbour, the acceptance
-    (Gaussian: sign, scale by beta, exp, uniform conversion, compare; integer
-    couplings: sign, table index, compare) and the flip."""
-    return 10 + 2 * deg + (5 if kind == "gauss" else 3) + 1
-
-
-def algorithmic_ops_per_move(N):
-    """An ICM move forms the overlap at every site (compare, count): 2 N."""
-    return 2 * N
-
-
 # The sources the fused sweep kernel is compiled from.
 SWEEP_KERNEL_SOURCES = ("icm_kernels.hip", "icm_device.h", "icm_internal.h")
 
@@ -92,11 +96,24 @@ def kernel_source_digest():
     return h.hexdigest()[:16]
 
 
-# HBM bytes per launch of the fused kernel from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE passes over this bench's default launch, each scaled by what the
-# same counter reads for a plain 256 MiB device copy.  Only valid for the kernel
-# source it was measured on (digest); null otherwise.
-TRAFFIC = {"3d_L8_gauss_1024inst": {"kernel": "86c9f8d660f94792", "bytes_per_launch": 101415752}}
+def launch_tag(cfg):
+    return "t{threads}_s{icm_slots}_spl{sweeps_per_launch}".format(**cfg)
+
+
+# Counters of one launch of the fused kernel on a workload, from rocprofv3
+# --pmc runs of this bench (the summaries under profiles/): HBM bytes =
+# FETCH_SIZE + WRITE_SIZE, each scaled by what the counter reads for a plain
+# 256 MiB device copy, and SQ_INSTS_VALU (wave instructions).  Valid only for
+# the kernel source (digest) and launch shape they were measured on; the line
+# reports null otherwise.
+PROFILED = {}
+
+
+def profiled(name, cfg):
+    p = PROFILED.get(name)
+    if p and p["kernel"] == kernel_source_digest() and p["launch"] == launch_tag(cfg):
+        return p
+    return None
 
 
 def cpu_baseline(name, spec, seconds):
@@ -183,15 +200,41 @@ def serve_request(x, rng):
     return d, len(d["temps"]) * d["n_replicas"] * N
 
 
-def run_serving(args):
-    """Continuous batching under Poisson arrivals: p50/p99 latency and sweeps/s."""
+def serve_mix(n_requests, sweeps, block, load, arena_mib, n_sat=None, per_instance=0):
+    """Continuous batching of the serving mix: the saturated request rate (n_sat
+    requests submitted at once), then n_requests Poisson arrivals at `load`
+    times that rate: p50/p99 latency, sweeps/s and attempts/s.  With
+    per_instance > 0, the same kernels with plain per-instance launches on that
+    many requests of the mix (256 sweeps each) for comparison."""
     import numpy as np
+    import torch
 
     from paper_1501_05630_amd import icm, inputs
     rng = inputs.make_rng(4, 0)
-    reqs = [serve_request(x, rng) for x in range(args.serve)]
-    ctx = icm.Context(arena_bytes=args.arena_mib << 20, seed=inputs.MASTER_SEED)
-    ctx.icm_serve_start(args.serve_block)
+    reqs = [serve_request(x, rng) for x in range(n_requests)]
+    ctx = icm.Context(arena_bytes=arena_mib << 20, seed=inputs.MASTER_SEED)
+    out = {"requests": n_requests, "sweeps_per_request": sweeps, "block": block, "arena_mib": arena_mib}
+    if per_instance:
+        # plain per-instance launches: one request's instance per launch, no graph
+        pick = reqs[:per_instance]
+        hs = []
+        for d, _ in pick:
+            hs.append(ctx.icm_add_instance(**{k: v for k, v in d.items()}))
+            ctx.icm_init_states(hs[-1])
+        ctx.icm_set_run_config(sweeps_per_launch=256, use_graph=0)
+        ctx.icm_run_per_instance(hs, 256)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(ctx.stream)
+        ctx.icm_run_per_instance(hs, 256)
+        e1.record(ctx.stream)
+        torch.cuda.synchronize()
+        secs = e0.elapsed_time(e1) / 1e3
+        out["per_instance"] = {"attempts_per_s": sum(w for _, w in pick) * 256 / secs,
+                               "sample": f"{len(pick)} requests of the mix, 256 sweeps, one launch each"}
+        for h in hs:
+            ctx.icm_remove_instance(h)
+    ctx.icm_serve_start(block)
 
     def drain(tickets):
         lat = []
@@ -206,15 +249,18 @@ def run_serving(args):
             lat.append(us)
         return lat
 
-    # saturated rate: everything submitted at once
-    n_sat = max(8, args.serve // 4)
+    # saturated rate: a batch of requests submitted at once
+    n_sat = n_sat or max(8, n_requests // 4)
     t0 = time.perf_counter()
-    tickets = [(ctx.icm_submit(args.serve_sweeps, **d), (d, w)) for d, w in reqs[:n_sat]]
+    tickets = [(ctx.icm_submit(sweeps, **d), (d, w)) for d, w in reqs[:n_sat]]
     drain(tickets)
-    sat_rate = n_sat / (time.perf_counter() - t0)
+    sat_wall = time.perf_counter() - t0
+    sat_rate = n_sat / sat_wall
+    out["saturated_rate_per_s"] = sat_rate
+    out["saturated_attempts_per_s"] = sum(w for _, w in reqs[:n_sat]) * sweeps / sat_wall
     # Poisson arrivals at a fraction of the saturated rate
-    rate = args.serve_load * sat_rate
-    gaps = rng.exponential(1.0 / rate, size=args.serve)
+    rate = load * sat_rate
+    gaps = rng.exponential(1.0 / rate, size=n_requests)
     t0 = time.perf_counter()
     tickets = []
     next_t = t0
@@ -222,18 +268,25 @@ def run_serving(args):
         next_t += g
         while time.perf_counter() < next_t:
             time.sleep(0.0002)
-        tickets.append((ctx.icm_submit(args.serve_sweeps, **d), (d, w)))
+        tickets.append((ctx.icm_submit(sweeps, **d), (d, w)))
     lat = drain(tickets)
     wall = time.perf_counter() - t0
     ctx.icm_serve_stop()
     ctx.close()
-    attempts = sum(w for _, w in reqs) * args.serve_sweeps
+    attempts = sum(w for _, w in reqs) * sweeps
     lat = np.array(lat) / 1e3
-    return {"requests": args.serve, "sweeps_per_request": args.serve_sweeps,
-            "arrival_rate_per_s": rate, "saturated_rate_per_s": sat_rate,
-            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-            "sweeps_per_s": args.serve * args.serve_sweeps / wall,
-            "attempts_per_s": attempts / wall, "arena_mib": args.arena_mib}
+    out.update({"load": load, "arrival_rate_per_s": rate,
+                "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                "sweeps_per_s": n_requests * sweeps / wall, "attempts_per_s": attempts / wall})
+    if "per_instance" in out:
+        out["saturated_over_per_instance"] = out["saturated_attempts_per_s"] / out["per_instance"]["attempts_per_s"]
+    return out
+
+
+def run_serving(args):
+    """Continuous batching under Poisson arrivals: p50/p99 latency and sweeps/s."""
+    return serve_mix(args.serve, args.serve_sweeps, args.serve_block, args.serve_load, args.arena_mib,
+                     per_instance=12)
 
 
 def run_thermalization(args):
@@ -242,7 +295,7 @@ def run_thermalization(args):
     import numpy as np
     import torch
 
-    from paper_1501_05630_amd import icm, inputs
+    from paper_1501_05630_amd import analysis, icm, inputs
     name = args.workload
     spec = inputs.WORKLOADS[name]
     n_inst = spec["n_instances"]
@@ -269,11 +322,11 @@ def run_thermalization(args):
         ctx.icm_run(hs, args.thermalization)
         ctx.icm_sync()
         wall = time.perf_counter() - t0
-        unit = icm.OBS_ENERGY_UNIT_FLOAT if spec["kind"] == "gauss" else 1.0 / spec["j_scale"]
+        unit = analysis.OBS_ENERGY_UNIT_FLOAT if spec["kind"] == "gauss" else 1.0 / spec["j_scale"]
         deltas = []
         for h, (temps, N, nb) in zip(hs, meta):
             sums, counts = ctx.icm_read_observables(h)
-            deltas.append(icm.delta_per_bin(sums, counts, temps, N, nb, unit)[2])
+            deltas.append(analysis.delta_per_bin(sums, counts, temps, N, nb, unit)[2])
         d = np.array(deltas)                                   # [instances][bins][K]
         nbins = int(np.floor(np.log2(args.thermalization))) + 1
         mean = d[:, :nbins, :].mean(axis=0)
@@ -290,13 +343,13 @@ def run_table1(args):
     """The thermalization study at the paper's Table I parameters with fewer
     disorder instances and sweeps: per topology and size, Delta (Eq. 2) at the
     lowest temperature per time bin for PT alone and PT + ICM on the same
-    instances, the thermalization bin of each (icm.thermalization_bin), their
+    instances, the thermalization bin of each (analysis.thermalization_bin), their
     ratio, and the fraction p of potential cluster sites against T in the last
     complete bin."""
     import numpy as np
     import torch
 
-    from paper_1501_05630_amd import icm, inputs
+    from paper_1501_05630_amd import analysis, icm, inputs
     names = {"2d": "table1_2d_gauss", "chimera": "table1_chimera_gauss", "3d": "table1_3d_gauss"}
     M = args.table1_instances
     out = {"metric": "thermalization at the Table I parameters: Delta (Eq. 2) at T_min per time bin "
@@ -343,15 +396,15 @@ def run_table1(args):
                     if L2 != L:
                         continue
                     sums, counts = ctx.icm_read_observables(h)
-                    d.append(icm.delta_per_bin(sums, counts, temps, N, nb, icm.OBS_ENERGY_UNIT_FLOAT)[2][:, 0])
-                    p.append(icm.cluster_fraction_per_bin(sums, counts, N))
+                    d.append(analysis.delta_per_bin(sums, counts, temps, N, nb, analysis.OBS_ENERGY_UNIT_FLOAT)[2][:, 0])
+                    p.append(analysis.cluster_fraction_per_bin(sums, counts, N))
                 complete = [int(c) == (1 << b) for b, c in enumerate(counts)]
                 last = max(b for b in range(len(complete)) if complete[b])
                 d = np.array(d)                                   # [instances][bins]
                 d = d[:, :last + 1]
                 mean = d.mean(axis=0)
                 se = d.std(axis=0, ddof=1) / np.sqrt(len(d))
-                tb = icm.thermalization_bin(mean, se, complete)
+                tb = analysis.thermalization_bin(mean, se, complete)
                 per.setdefault(L, {"N": N})[mode] = {
                     "wall_s": wall, "delta_tmin": [float(x) for x in mean[:last + 1]],
                     "se_tmin": [float(x) for x in se[:last + 1]], "thermalized_bin": tb}
@@ -388,7 +441,7 @@ def run_percolation(args):
     import numpy as np
     import torch
 
-    from paper_1501_05630_amd import icm, inputs
+    from paper_1501_05630_amd import analysis, icm, inputs
     n = args.percolation
     ctx = icm.Context(arena_bytes=64 << 20, seed=inputs.MASTER_SEED)
     out = {"metric": "site percolation: Binder ratio g = (3 - <s^4>/<s^2>^2)/2 of the largest cluster",
@@ -413,9 +466,9 @@ def run_percolation(args):
                 e1.record(ctx.stream)
                 s = buf.cpu().numpy()
                 ms += e0.elapsed_time(e1)
-                gs.append(float(icm.binder_ratio(s)))
+                gs.append(float(analysis.binder_ratio(s)))
                 # standard error from 16 blocks of samples
-                blocks = [icm.binder_ratio(b) for b in np.array_split(s, 16)]
+                blocks = [analysis.binder_ratio(b) for b in np.array_split(s, 16)]
                 ses.append(float(np.std(blocks, ddof=1) / 4.0))
             g_all.append(np.array(gs))
             res[str(L)] = {"N": N, "g": gs, "se": ses,
@@ -432,7 +485,7 @@ def run_percolation(args):
                     break
             crossings.append({"sizes": [sides[a], sides[a + 1]], "p_cross": x})
         fit = [L for L in sides if L >= cfg["fit_from"]]
-        pc, nu, chi2 = icm.binder_collapse(ps, [res[str(L)]["N"] for L in fit], [res[str(L)]["g"] for L in fit],
+        pc, nu, chi2 = analysis.binder_collapse(ps, [res[str(L)]["N"] for L in fit], [res[str(L)]["g"] for L in fit],
                                            [res[str(L)]["se"] for L in fit], cfg["p_ref"], cfg["nu_ref"])
         out[name] = {"p": [float(x) for x in ps], "p_ref": cfg["p_ref"], "sizes": res, "crossings": crossings,
                      "collapse": {"sides": fit, "p_c": pc, "nu_sqrtN": nu, "chi2_per_dof": chi2}}
@@ -452,7 +505,7 @@ def run_anneal(args):
     import numpy as np
     import torch
 
-    from paper_1501_05630_amd import icm, inputs
+    from paper_1501_05630_amd import analysis, icm, inputs
     C, R, steps = 8, 16, 64
     M = args.anneal_instances
     per_step = max(1, args.anneal // steps)
@@ -567,7 +620,7 @@ def main():
     import numpy as np
     import torch
 
-    from paper_1501_05630_amd import icm, inputs
+    from paper_1501_05630_amd import analysis, icm, inputs
 
     name = args.workload
     spec = inputs.WORKLOADS[name]
@@ -587,8 +640,31 @@ def main():
                       inputs.CHIMERA: 16 * sp["L"] ** 2 + 8 * sp["L"] * (sp["L"] - 1)}[sp["topology"]])
     jbytes = 4 if spec["kind"] == "gauss" else 1
     spsw = args.sweeps_per_step
-    ctx.icm_set_run_config(threads=args.threads, sweeps_per_launch=spsw, use_graph=args.graph,
-                           icm_slots=args.icm_slots)
+    launch = dict(threads=args.threads, icm_slots=args.icm_slots, sweeps_per_launch=args.sweeps_per_launch,
+                  use_graph=args.graph, table_placement=0)
+    tuned = {"source": "flags"}
+    if not args.no_tune:
+        # the autotuner times every candidate shape on this batch (advancing
+        # it), then the batch restarts from its hot start
+        from paper_1501_05630_amd import autotune
+        cands = [c for c in autotune.candidates() if spsw % c["sweeps_per_launch"] == 0]
+        best, info = autotune.tune(ctx, hs, cache_path=args.tune_cache or None, cands=cands)
+        launch.update(best)
+        tuned = {"source": info["source"], "key": info["key"], "candidates": len(cands)}
+        if "ms_per_sweep" in info:
+            tuned["best_ms_per_sweep"] = min(info["ms_per_sweep"].values())
+            dflt = json.dumps(dict(threads=DEFAULT_LAUNCH["threads"], icm_slots=DEFAULT_LAUNCH["icm_slots"],
+                                   sweeps_per_launch=DEFAULT_LAUNCH["sweeps_per_launch"], use_graph=1),
+                              sort_keys=True)
+            if dflt in info["ms_per_sweep"]:
+                tuned["default_ms_per_sweep"] = info["ms_per_sweep"][dflt]
+        for h in hs:
+            ctx.icm_init_states(h)
+    ctx.icm_set_run_config(**launch)
+    spl = launch["sweeps_per_launch"]
+    # one launch per size class of units (sites <= 512, <= 1024, <= 2048, more)
+    n_groups = len({0 if n <= 512 else (1 if n <= 1024 else (2 if n <= 2048 else 3)) for n in sizes})
+    launches_per_step = n_groups * ((spsw + spl - 1) // spl)
     stream = ctx.stream
     for _ in range(args.warmup):
         ctx.icm_run(hs, spsw)
@@ -606,41 +682,49 @@ def main():
     value = attempts_per_sweep * sweeps / secs
     icm_moves = sum(moves_per_sweep) * sweeps
     step_ms = ms / args.steps
-    deg = {inputs.SQUARE2D: 4, inputs.CUBIC3D: 6, inputs.CHIMERA: 6}[spec["topology"]]
-    opa = algorithmic_ops_per_attempt(deg, spec["kind"])
-    ops_per_step = (opa * attempts_per_sweep
-                    + sum(algorithmic_ops_per_move(N) * m for N, m in zip(sizes, moves_per_sweep))) * spsw
     bytes_per_sweep = sum(2 * S * N + nb * jbytes for N, nb in zip(sizes, bonds))
-    # one launch per size class: the roofline is taken over the whole step
-    achieved_tops = ops_per_step / (step_ms / 1e3) / 1e12
-    achieved_gbs = bytes_per_sweep * spsw / (step_ms / 1e3) / 1e9
-    tr = TRAFFIC.get(name, {})
-    traffic = tr.get("bytes_per_launch") if (tr.get("kernel") == kernel_source_digest()
-                                              and spsw == 256 and args.threads == 256 and args.icm_slots == 16) else None
     uneven = bool(spec.get("sides"))
+    # the roofline of the fused kernel: one size class -> launches back to
+    # back on the context stream, so a launch lasts step time / launches;
+    # several classes (uneven batch) -> taken over the whole step
+    launch_ms = step_ms / launches_per_step if n_groups == 1 else step_ms
+    per_launch_bytes = bytes_per_sweep * (spl if n_groups == 1 else spsw)
+    achieved_gbs = per_launch_bytes / (launch_ms / 1e3) / 1e9
+    prof = profiled(name, launch) if n_groups == 1 else None
+    alu = None
+    if prof:
+        lane_ops = prof["valu_insts_per_launch"] * 64
+        alu = {"valu_lane_ops_per_attempt": lane_ops / (attempts_per_sweep * spl),
+               "achieved": lane_ops / (launch_ms / 1e3) / 1e12, "peak": VALU_PEAK_TOPS, "unit": "T lane-op/s"}
+        alu["frac"] = alu["achieved"] / VALU_PEAK_TOPS
 
     out = {
         "metric": "spin-flip attempts/s + ICM moves/s, batched vs per-instance; % HBM roofline",
         "value": value, "unit": "spin-flip attempts/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": step_ms, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if spec["kind"] == "gauss" else "i32",
+        "scaling": "weak", "vs_baseline": None, "dtype": "i32",
+        "dtype_detail": ("bit-packed spins; int32 fields of 24-bit fixed-point couplings (2^-20 grid); fp32 "
+                         "acceptance filter with an exact fp64 decision near the boundary; fp64 energies"
+                         if spec["kind"] == "gauss" else
+                         "bit-packed spins; int32 fields and energies; u32 threshold tables"),
         "data": "synthetic (seeded disorder, hot start)",
         "config": {"workload": name, "instances": n_inst, "topology": inputs.TOPOLOGY_NAMES[spec["topology"]],
                    "L": list(spec["sides"]) if uneven else spec["L"],
                    "N": sorted(set(sizes)) if uneven else sizes[0], "temps": spec["n_temps"],
                    "replicas": spec["n_replicas"], "icm_temps": moves_per_sweep[0] * 2 // spec["n_replicas"],
-                   "sweeps_per_step": spsw,
-                   "threads": sorted({icm.launch_threads(n, args.threads) for n in sizes}),
-                   "threads_requested": args.threads,
-                   "icm_slots": args.icm_slots, "graph": bool(args.graph),
+                   "sweeps_per_step": spsw, "sweeps_per_launch": spl, "launches_per_step": launches_per_step,
+                   "threads": sorted({icm.launch_threads(n, launch["threads"]) for n in sizes}),
+                   "threads_requested": launch["threads"], "icm_slots": launch["icm_slots"],
+                   "graph": bool(launch["use_graph"]) and spsw // spl > 1, "launch_shape": tuned,
                    "parallelism": "single GPU, one workgroup per instance"},
         "icm_moves_per_s": icm_moves / secs,
-        "roofline": {"bound": "alu", "achieved": achieved_tops, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
-                     "frac": achieved_tops / VALU_PEAK_TOPS, "traffic": traffic,
-                     "ops_per_attempt": opa, "ops_per_icm_move": "2 N"},
-        "hbm_effective": {"achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                          "frac": achieved_gbs / HBM_PEAK_GBS,
-                          "bytes_per_attempt": bytes_per_sweep / attempts_per_sweep},
+        "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved_gbs / HBM_PEAK_GBS,
+                     "traffic": prof["hbm_bytes_per_launch"] if prof else None,
+                     "kind": "effective (algorithmic bytes / kernel time)",
+                     "bytes_per_attempt": bytes_per_sweep / attempts_per_sweep,
+                     "algorithmic_bytes_per_launch": per_launch_bytes, "launch_ms": launch_ms,
+                     "alu": alu},
     }
     # the cluster moves' own accounting: a move reads both replicas' N spins and
     # writes the |C| flipped sites in both (2 N + 2 <|C|> bytes as int8)
@@ -656,21 +740,24 @@ def main():
         k = min(args.per_instance_sample, n_inst)
         pick = [b * n_inst // k for b in range(k)]
         sample = [hs[b] for b in pick]
-        ctx.icm_set_run_config(use_graph=0)
-        ctx.icm_run_per_instance(sample, spsw)
+        ctx.icm_set_run_config(use_graph=0, sweeps_per_launch=spl)
+        ctx.icm_run_per_instance(sample, spl)
         torch.cuda.synchronize()
         ev0.record(stream)
-        ctx.icm_run_per_instance(sample, spsw)
+        ctx.icm_run_per_instance(sample, spl)
         ev1.record(stream)
         torch.cuda.synchronize()
         pms = ev0.elapsed_time(ev1)
-        out["per_instance"] = {"value": S * sum(sizes[b] for b in pick) * spsw / (pms / 1e3),
-                               "icm_moves_per_s": sum(moves_per_sweep[b] for b in pick) * spsw / (pms / 1e3),
-                               "sample": f"{k} instances, one launch each"}
+        out["per_instance"] = {"value": S * sum(sizes[b] for b in pick) * spl / (pms / 1e3),
+                               "icm_moves_per_s": sum(moves_per_sweep[b] for b in pick) * spl / (pms / 1e3),
+                               "sample": f"{k} instances, one launch of {spl} sweeps each, no graph"}
         out["batched_over_per_instance"] = value / out["per_instance"]["value"]
+    ctx.close()
+    if args.served_requests:
+        out["served"] = serve_mix(args.served_requests, args.serve_sweeps, args.serve_block, args.serve_load,
+                                  args.arena_mib, n_sat=max(8, args.served_requests // 3), per_instance=12)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(name, spec, args.cpu_seconds)
-    ctx.close()
     print(json.dumps(out), flush=True)
 
 

@@ -31,10 +31,17 @@
  *     u < min(floor(2^32 exp(-(beta*dE)/j_scale)), 2^32-1); the PT rule uses the
  *     same form with (beta_k - beta_k+1) and the energy gap.  Energies are exact
  *     integers in units of 1/j_scale.
- *   - float couplings: J is rounded to the 2^-32 grid (a no-op for |J| >= 2^-8);
- *     local fields and energies are exact on that grid; dE > 0 is accepted iff
- *     u * 2^-32 < exp(-(beta*dE)) evaluated in double; energies are reported in
- *     units of 2^-32.
+ *   - float couplings: the model paragraph takes Gaussian J and fixes no
+ *     precision.  The library rounds every float J of an instance to the grid
+ *     2^-e, e the largest exponent <= 20 for which every |J| 2^e rounds to at
+ *     most 2^23 - 1 (e = 20 whenever all |J| < 8), so that each coupling is a
+ *     signed 24-bit integer and local fields, energy changes and energies are
+ *     exact integer sums.  Each J moves by at most 2^-(e+1): 2^-21 when all
+ *     |J| < 8.  The chain simulated is the one of the rounded couplings; for
+ *     couplings already on the grid nothing is rounded.  dE > 0 is accepted
+ *     iff u * 2^-32 < exp(-(beta*dE)) evaluated in double (beta in double);
+ *     PT likewise with (beta_k - beta_k+1) and the energy gap.  Energies are
+ *     reported in units of 2^-40 (multiples of 2^(40-e) of that unit).
  *
  * Memory: the caller hands the library one device buffer (the arena, e.g. a
  * torch uint8 tensor) at icm_create; every device allocation of the library is
@@ -74,7 +81,7 @@ extern "C" {
 #define ICM_TOPO_CHIMERA 2
 
 #define ICM_J_INT8 0 /* couplings int8 j, J = j / j_scale */
-#define ICM_J_F32 1  /* couplings float, rounded to the 2^-32 grid */
+#define ICM_J_F32 1  /* couplings float, rounded to a 2^-e grid, e <= 20 (see above) */
 
 #define ICM_FLAG_2A 1            /* step 2a (spin-reversal flip of the 2nd replica) */
 #define ICM_FLAG_PT 2            /* step 3 (parallel tempering) */
@@ -166,9 +173,11 @@ int icm_sync(icm_ctx* ctx);
 int icm_set_run_config(icm_ctx* ctx, const icm_run_config* cfg);
 int icm_get_run_config(icm_ctx* ctx, icm_run_config* cfg);
 
-/* Energies [K][R] in temperature order: raw (int64: units of 1/j_scale, or
-   2^-32 for F32) and/or real (double); either pointer may be NULL.  cap is the
-   number of elements the buffers hold. */
+/* Energies H = -sum over bonds J_ij s_i s_j (model paragraph) of every
+   walker, [K][R] in temperature order: raw (int64: units of 1/j_scale, or
+   2^-40 for F32) and/or real (double); either pointer may be NULL.  cap is the
+   number of elements the buffers hold (ICM_E_BUFSIZE if fewer than K R).
+   Synchronizes the context stream. */
 int icm_read_energies(icm_ctx* ctx, int32_t handle, int64_t* raw, double* real, size_t cap);
 /* Spins [K][R][N] (+1/-1) in temperature order, canonical site order. */
 int icm_read_states(icm_ctx* ctx, int32_t handle, int8_t* out, size_t cap);
@@ -193,7 +202,7 @@ int icm_read_stats(icm_ctx* ctx, int32_t handle, icm_stats* out);
    sums [ICM_OBS_BINS][K][R/2][ICM_OBS_FIELDS], int64:
      0: E_a + E_b, in units of 1/j_scale for integer couplings and of 2^-20
         for float couplings (exact: their energies are multiples of the
-        coupling grid; coarser than the 2^-32 of icm_read_energies so that a
+        coupling grid; coarser than the 2^-40 of icm_read_energies so that a
         bin of up to ~2^29 steps at 4096 sites stays within int64),
      1: sum over bonds of q_i q_j = N_b q_l (q_i = s_a,i s_b,i),
      2: (sum_i q_i)^2,

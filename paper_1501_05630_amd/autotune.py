@@ -1,77 +1,109 @@
 """Launch-shape autotuner for the fused sweep-block kernel.
 
-Searches threads per workgroup, concurrent ICM moves per workgroup and sweeps
-per launch for one batch of instances, timing `icm_run` with HIP events on the
-context stream, and caches the winner in a JSON file keyed by the batch's
-shape.  The choice never changes results: every launch shape computes the same
-bits (the random streams are keyed by site, sweep and walker, not by thread).
+Searches threads per workgroup, cluster moves in flight per workgroup (ICM
+slots) and sweeps per launch for one batch of instances, timing `icm_run` with
+HIP events on the context stream, and caches the winner in a JSON file keyed by
+the batch's shape.  The choice never changes results: every launch shape
+computes the same bits (the random streams are keyed by site, sweep and walker,
+not by thread), which the GPU tests check for the shapes the search can pick.
 """
 import itertools
 import json
 import os
 
-DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "icm_autotune.json")
 THREADS = (256, 512, 1024)
 SLOTS = (4, 8, 16, 32)
-SWEEPS = (64, 256)
+SWEEPS = (128, 256)
 
 
-def shape_key(meta, n_instances):
-    """Cache key: topology shape, walkers, ICM temperatures, coupling kind, batch size bucket."""
-    bucket = 1 << max(0, (n_instances - 1).bit_length())
-    return "N{N}_K{K}_R{R}_Kc{Kc}_j{jkind}_b{b}".format(b=bucket, **meta)
+def batch_key(metas, n_instances):
+    """Cache key: the distinct unit shapes of the batch (sites, temperatures,
+    replicas, cluster-move temperatures, coupling kind) with their counts
+    rounded up to a power of two."""
+    shapes = {}
+    for m in metas:
+        k = "N{N}_K{K}_R{R}_Kc{Kc}_j{jkind}".format(**m)
+        shapes[k] = shapes.get(k, 0) + 1
+    parts = []
+    for k in sorted(shapes):
+        parts.append(f"{k}x{1 << max(0, (shapes[k] - 1).bit_length())}")
+    return "|".join(parts) + f"|n{1 << max(0, (n_instances - 1).bit_length())}"
 
 
-def _time_run(ctx, handles, sweeps, repeats=2):
+def candidates(threads=THREADS, slots=SLOTS, sweeps=SWEEPS):
+    """Launch shapes the search tries: every combination in which a wave
+    carries at most four moves on average (slots <= 4 x waves)."""
+    out = []
+    for t, s, n in itertools.product(threads, slots, sweeps):
+        if s > 4 * (t // 64):
+            continue
+        out.append(dict(threads=t, icm_slots=s, sweeps_per_launch=n, use_graph=1))
+    return out
+
+
+def event_timer(ctx, handles, sweeps, repeats=2):
+    """ms per sweep of icm_run over `handles`, by HIP events on the context
+    stream, after one untimed run (which also captures the launch graph)."""
     torch = ctx.torch
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ctx.icm_run(handles, sweeps)  # warm-up (and graph/unit-table creation)
-    torch.cuda.synchronize()
+    ctx.icm_run(handles, sweeps)
+    ctx.icm_sync()
     e0.record(ctx.stream)
     for _ in range(repeats):
         ctx.icm_run(handles, sweeps)
     e1.record(ctx.stream)
-    torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / (repeats * sweeps)  # ms per sweep
+    ctx.icm_sync()
+    return e0.elapsed_time(e1) / (repeats * sweeps)
 
 
-def tune(ctx, handles, cache_path=DEFAULT_CACHE, budget_sweeps=None, verbose=False):
-    """Returns the best config dict for this batch and applies it to ctx.
-
-    Runs each candidate for a few sweeps on the live instances (their state
-    advances; callers tune on a warm-up batch or accept the extra sweeps)."""
-    meta = dict(ctx.meta[handles[0]])
-    key = shape_key({k: meta[k] for k in ("N", "K", "R", "Kc", "jkind")}, len(handles))
-    cache = {}
+def _load(cache_path):
     if cache_path and os.path.exists(cache_path):
         try:
             with open(cache_path) as f:
-                cache = json.load(f)
+                return json.load(f)
         except (OSError, ValueError):
-            cache = {}
+            return {}
+    return {}
+
+
+def _store(cache_path, cache):
+    if not cache_path:
+        return
+    d = os.path.dirname(cache_path)
+    if d:
+        os.makedirs(d, exist_ok=True)
+    tmp = cache_path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    os.replace(tmp, cache_path)
+
+
+def tune(ctx, handles, cache_path=None, cands=None, sweeps_per_candidate=None, timer=event_timer,
+         verbose=False):
+    """Picks the fastest launch shape for this batch, applies it to ctx and
+    returns (config, info).  info: the cache key, where the choice came from
+    ("cache" or "search") and, after a search, each candidate's ms per sweep.
+
+    A search runs every candidate on the live instances, so their state
+    advances: tune on a warm-up batch, or reset the states afterwards."""
+    key = batch_key([ctx.meta[h] for h in handles], len(handles))
+    cache = _load(cache_path)
     if key in cache:
-        best = cache[key]
+        best = dict(cache[key])
         ctx.icm_set_run_config(**best)
-        return best
+        return best, {"key": key, "source": "cache"}
     results = []
-    for threads, slots, spl in itertools.product(THREADS, SLOTS, SWEEPS):
-        if slots > 4 * (threads // 64):  # at most four moves per wave
-            continue
-        cfg = dict(threads=threads, icm_slots=slots, sweeps_per_launch=spl, use_graph=1)
+    for cfg in (cands if cands is not None else candidates()):
         ctx.icm_set_run_config(**cfg)
-        n = budget_sweeps or spl
-        ms = _time_run(ctx, handles, n)
+        n = sweeps_per_candidate or cfg["sweeps_per_launch"]
+        ms = timer(ctx, handles, n)
         results.append((ms, cfg))
         if verbose:
             print(f"autotune {key} {cfg}: {ms * 1e3:.2f} us/sweep", flush=True)
     results.sort(key=lambda r: r[0])
-    best = results[0][1]
+    best = dict(results[0][1])
     cache[key] = best
-    if cache_path:
-        os.makedirs(os.path.dirname(cache_path), exist_ok=True)
-        tmp = cache_path + ".tmp"
-        with open(tmp, "w") as f:
-            json.dump(cache, f, indent=1, sort_keys=True)
-        os.replace(tmp, cache_path)
+    _store(cache_path, cache)
     ctx.icm_set_run_config(**best)
-    return best
+    return best, {"key": key, "source": "search",
+                  "ms_per_sweep": {json.dumps(c, sort_keys=True): ms for ms, c in results}}

@@ -121,7 +121,7 @@ __device__ __forceinline__ double uniform_d(double v) {
 }
 
 // ----------------------------------------------------------------------------
-// Metropolis acceptance for float couplings.  dE is exact (2^-32 grid); the
+// Metropolis acceptance for float couplings.  dE is exact (coupling grid); the
 // decision is u * 2^-32 < exp(-beta dE) in double.  A float estimate settles
 // all but a ~1e-4 band around the boundary: P = 2^(32 - dE * beta log2 e)
 // (the 2^32 scale folded into the exponent of one fma) has a relative error
@@ -681,7 +681,7 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
   for (int x = tid; x < Wp; x += nthr) {
     tau[x] = U.tau[x];
     gauge[x] = U.gauge[x];
-    if (JK) energy[x] = (E_t)((double)U.energy[x] * 0x1p-32);
+    if (JK) energy[x] = (E_t)((double)U.energy[x] * 0x1p-40);
     else energy[x] = (E_t)U.energy[x];
   }
   for (int x = tid; x < K * R; x += nthr) at[x] = U.at[x];
@@ -1446,7 +1446,7 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
   for (int x = tid; x < Wp; x += nthr) {
     U.tau[x] = tau[x];
     U.gauge[x] = (uint8_t)gauge[x];
-    if (JK) U.energy[x] = (int64_t)((double)energy[x] * 0x1p32);
+    if (JK) U.energy[x] = (int64_t)((double)energy[x] * 0x1p40);
     else U.energy[x] = (int64_t)energy[x];
   }
   for (int x = tid; x < K * R; x += nthr) U.at[x] = at[x];
@@ -1491,7 +1491,7 @@ __global__ void scatter_spins_kernel(uint32_t* spins, const int8_t* src, int N, 
 }
 
 // Energy of every walker from scratch: each bond is seen from both ends, so the
-// slot sum is halved (exact: integer, or float couplings on the 2^-32 grid summed
+// slot sum is halved (exact: integer, or float couplings on their 2^-jexp grid summed
 // as int64 after scaling).  grid: (Wp), block 256.
 template <int JK>
 __global__ void energy_kernel(const uint32_t* spins, const uint16_t* nbr, const void* coup, int N,
@@ -1505,7 +1505,7 @@ __global__ void energy_kernel(const uint32_t* spins, const uint16_t* nbr, const 
       const int j = nbr[i * deg + d];
       const int sj = spin_of(spins[(size_t)q * N + j], b);
       long long Jraw;
-      if (JK) Jraw = (long long)((const int32_t*)coup)[i * deg + d] << (32 - jexp);
+      if (JK) Jraw = (long long)((const int32_t*)coup)[i * deg + d] << (40 - jexp);
       else Jraw = ((const int8_t*)coup)[i * deg + d];
       acc -= Jraw * si * sj;
     }
@@ -1519,6 +1519,61 @@ __global__ void energy_kernel(const uint32_t* spins, const uint16_t* nbr, const 
   if (threadIdx.x == 0) energy[w] = part[0] / 2;
 }
 
+
+// ----------------------------------------------------------------------------
+// Overlaps of the replica pairs (paper, "Benchmark model and observables":
+// the spin overlap q = (1/N) sum_i q_i and the link overlap of Eq. 1,
+// q_l = (1/N_b) sum over bonds of q_i q_j, with q_i = s_i^(a) s_i^(b) for the
+// two replicas of a pair).  For each temperature k and pair p (chains 2p,
+// 2p+1): out_q = sum_i q_i, out_ql = sum over bonds of q_i q_j.  Stored spins
+// of a reversed walker (gauge bit) are the negation of its true spins; q_i
+// takes the gauge parity of the two walkers, q_i q_j does not depend on it.
+// Each bond is counted once: lattices from the slots of the +axis steps
+// (even slots), chimera in-cell bonds from the u < 4 side (slots 0-3) and
+// inter-cell bonds from the next row / column (slot 5, absent where it
+// points back at the site).  grid: (K * R/2), block 256 (four waves).
+// ----------------------------------------------------------------------------
+template <int DEG>
+__global__ void __launch_bounds__(256) overlap_kernel(const uint32_t* __restrict__ spins,
+                                                      const uint16_t* __restrict__ nbr,
+                                                      const int32_t* __restrict__ at,
+                                                      const uint8_t* __restrict__ gauge, int N, int R,
+                                                      int topo, int n_bonds, int32_t* out_q,
+                                                      int32_t* out_ql) {
+  __shared__ int part[2][4];
+  const int half = R >> 1, x = blockIdx.x, k = x / half, p = x - k * half;
+  const int a = at[k * R + 2 * p], b = at[k * R + 2 * p + 1];
+  const uint32_t* wa = spins + (size_t)(a >> 2) * N;
+  const uint32_t* wb = spins + (size_t)(b >> 2) * N;
+  const int sa = 8 * (a & 3), sb = 8 * (b & 3);
+  // q_i as a bit: 1 where the stored spins differ (byte 0xFF = down, 0x01 = up)
+  auto qbit = [&](int i) { return ((wa[i] >> sa) ^ (wb[i] >> sb)) & 0x80u; };
+  int nd = 0, dl = 0;  // differing sites; bonds whose ends differ in q
+  for (int i = threadIdx.x; i < N; i += blockDim.x) {
+    const uint32_t qi = qbit(i);
+    nd += qi ? 1 : 0;
+#pragma unroll
+    for (int d = 0; d < DEG; ++d) {
+      const int j = nbr[i * DEG + d];
+      const bool bond = topo == 2 ? (((i & 7) < 4 && d < 4) || (d == 5 && j != i)) : (d & 1) == 0;
+      if (bond) dl += (qi != qbit(j)) ? 1 : 0;
+    }
+  }
+  nd = wave_sum(nd);
+  dl = wave_sum(dl);
+  if (lane_id() == 0) {
+    part[0][threadIdx.x >> 6] = nd;
+    part[1][threadIdx.x >> 6] = dl;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int n = part[0][0] + part[0][1] + part[0][2] + part[0][3];
+    const int D = part[1][0] + part[1][1] + part[1][2] + part[1][3];
+    const int sign = (gauge[a] ^ gauge[b]) ? -1 : 1;
+    out_q[x] = sign * (N - 2 * n);
+    out_ql[x] = n_bonds - 2 * D;  // sum over bonds of q_i q_j
+  }
+}
 
 }  // namespace icm
 
@@ -1582,6 +1637,22 @@ int icmk_launch_scatter(uint32_t* spins, const int8_t* src, int N, int Wq, int W
   return (int)hipGetLastError();
 }
 
+
+int icmk_launch_overlaps(const uint32_t* spins, const uint16_t* nbr, const int32_t* at, const uint8_t* gauge,
+                         int N, int deg, int K, int R, int topo, int n_bonds, int32_t* out_q,
+                         int32_t* out_ql, hipStream_t stream) {
+  const int n = K * (R / 2);
+  if (n <= 0) return 0;
+  if (deg == 6)
+    hipLaunchKernelGGL(icm::overlap_kernel<6>, dim3(n), dim3(256), 0, stream, spins, nbr, at, gauge, N, R, topo,
+                       n_bonds, out_q, out_ql);
+  else if (deg == 4)
+    hipLaunchKernelGGL(icm::overlap_kernel<4>, dim3(n), dim3(256), 0, stream, spins, nbr, at, gauge, N, R, topo,
+                       n_bonds, out_q, out_ql);
+  else
+    return (int)hipErrorInvalidValue;
+  return (int)hipGetLastError();
+}
 
 int icmk_launch_energy(const uint32_t* spins, const uint16_t* nbr, const void* coup, int N, int deg,
                        int Wp, int jkind, int jexp, int64_t* energy, hipStream_t stream) {

@@ -35,6 +35,9 @@ int icmk_launch_scatter(uint32_t* spins, const int8_t* src, int N, int Wq, int W
                         hipStream_t stream);
 int icmk_launch_energy(const uint32_t* spins, const uint16_t* nbr, const void* coup, int N, int deg,
                        int Wp, int jkind, int jexp, int64_t* energy, hipStream_t stream);
+int icmk_launch_overlaps(const uint32_t* spins, const uint16_t* nbr, const int32_t* at, const uint8_t* gauge,
+                         int N, int deg, int K, int R, int topo, int n_bonds, int32_t* out_q,
+                         int32_t* out_ql, hipStream_t stream);
 size_t icmk_percolation_lds(int N);
 int icmk_launch_percolation(const uint16_t* nbr, int N, int deg, unsigned long long thr, uint32_t sample0,
                             uint32_t n_samples, uint32_t seed, uint32_t key, int32_t* smax, int n_cus,
@@ -255,7 +258,7 @@ struct icm_ctx {
   std::vector<hipEvent_t> events;
   uint32_t seed = 0;
   Arena arena;
-  bool poisoned = false;
+  std::atomic<bool> poisoned{false};
   std::string last_error;
   std::map<std::pair<int, int>, std::unique_ptr<Topology>> topologies;
   std::map<int32_t, std::unique_ptr<Instance>> instances;
@@ -335,6 +338,15 @@ int check_ctx(icm_ctx* c) {
   if (!c) return ICM_E_INVALID;
   if (c->poisoned) return ICM_E_DEVICE;
   return ICM_OK;
+}
+
+// Entry points other than the serving calls: while the serving loop runs it
+// owns the instances, the arena and the run configuration, so they return
+// ICM_E_BUSY (without touching last_error, which the loop may be writing).
+int guard(icm_ctx* c) {
+  const int rc = check_ctx(c);
+  if (rc) return rc;
+  return c->serving ? ICM_E_BUSY : ICM_OK;
 }
 
 int validate_desc(const icm_instance_desc* d, std::string& why) {
@@ -978,17 +990,15 @@ size_t icm_instance_bytes(const icm_instance_desc* d) {
 }
 
 int icm_add_instance(icm_ctx* c, const icm_instance_desc* d, int32_t* out) {
-  int rc = check_ctx(c);
+  int rc = guard(c);
   if (rc) return rc;
   if (!out) return fail(c, ICM_E_INVALID, "null output handle");
-  if (c->serving) return fail(c, ICM_E_BUSY, "the serving loop owns the context");
   return add_instance_impl(c, d, out);
 }
 
 int icm_remove_instance(icm_ctx* c, int32_t h) {
-  int rc = check_ctx(c);
+  int rc = guard(c);
   if (rc) return rc;
-  if (c->serving) return fail(c, ICM_E_BUSY, "the serving loop owns the context");
   Instance* in = find(c, h);
   if (!in) return fail(c, ICM_E_NOTFOUND, "unknown handle %d", h);
   HIP_OK(c, hipStreamSynchronize(c->stream));
@@ -998,9 +1008,8 @@ int icm_remove_instance(icm_ctx* c, int32_t h) {
   return ICM_OK;
 }
 
-int icm_init_states(icm_ctx* c, int32_t h) {
-  int rc = check_ctx(c);
-  if (rc) return rc;
+static int init_states_impl(icm_ctx* c, int32_t h) {
+  int rc = ICM_OK;
   Instance* in = find(c, h);
   if (!in) return fail(c, ICM_E_NOTFOUND, "unknown handle %d", h);
   KERNEL_OK(c, icmk_launch_init(in->unit.spins, in->N, in->Wq, in->W, c->seed, in->key, c->stream));
@@ -1012,10 +1021,15 @@ int icm_init_states(icm_ctx* c, int32_t h) {
   return ICM_OK;
 }
 
-int icm_set_temperatures(icm_ctx* c, int32_t h, const double* temps) {
-  int rc = check_ctx(c);
+int icm_init_states(icm_ctx* c, int32_t h) {
+  int rc = guard(c);
   if (rc) return rc;
-  if (c->serving) return fail(c, ICM_E_BUSY, "the serving loop owns the context");
+  return init_states_impl(c, h);
+}
+
+int icm_set_temperatures(icm_ctx* c, int32_t h, const double* temps) {
+  int rc = guard(c);
+  if (rc) return rc;
   Instance* in = find(c, h);
   if (!in) return fail(c, ICM_E_NOTFOUND, "unknown handle %d", h);
   if (!temps) return fail(c, ICM_E_INVALID, "null temperatures");
@@ -1068,9 +1082,8 @@ int icm_set_temperatures(icm_ctx* c, int32_t h, const double* temps) {
 
 int icm_percolation_smax(icm_ctx* c, int32_t topology, int32_t L, double p, uint32_t sample0,
                          uint32_t n_samples, uint32_t key, int32_t* smax) {
-  int rc = check_ctx(c);
+  int rc = guard(c);
   if (rc) return rc;
-  if (c->serving) return fail(c, ICM_E_BUSY, "the serving loop owns the context");
   if (!(p >= 0.0 && p <= 1.0)) return fail(c, ICM_E_INVALID, "occupation probability outside [0, 1]");
   if (n_samples > 0 && !smax) return fail(c, ICM_E_INVALID, "null output");
   if ((uint64_t)sample0 + n_samples > (1ull << 32))
@@ -1087,7 +1100,7 @@ int icm_percolation_smax(icm_ctx* c, int32_t topology, int32_t L, double p, uint
 }
 
 int icm_set_states(icm_ctx* c, int32_t h, const int8_t* spins, uint32_t sweep0) {
-  int rc = check_ctx(c);
+  int rc = guard(c);
   if (rc) return rc;
   Instance* in = find(c, h);
   if (!in) return fail(c, ICM_E_NOTFOUND, "unknown handle %d", h);
@@ -1111,28 +1124,26 @@ int icm_set_states(icm_ctx* c, int32_t h, const int8_t* spins, uint32_t sweep0) 
 }
 
 int icm_run(icm_ctx* c, const int32_t* handles, int32_t n, uint32_t n_sweeps) {
-  int rc = check_ctx(c);
+  int rc = guard(c);
   if (rc) return rc;
-  if (c->serving) return fail(c, ICM_E_BUSY, "the serving loop owns the context");
   return run_impl(c, handles, n, n_sweeps, false);
 }
 
 int icm_run_per_instance(icm_ctx* c, const int32_t* handles, int32_t n, uint32_t n_sweeps) {
-  int rc = check_ctx(c);
+  int rc = guard(c);
   if (rc) return rc;
-  if (c->serving) return fail(c, ICM_E_BUSY, "the serving loop owns the context");
   return run_impl(c, handles, n, n_sweeps, true);
 }
 
 int icm_sync(icm_ctx* c) {
-  int rc = check_ctx(c);
+  int rc = guard(c);
   if (rc) return rc;
   HIP_OK(c, hipStreamSynchronize(c->stream));
   return ICM_OK;
 }
 
 int icm_set_run_config(icm_ctx* c, const icm_run_config* cfg) {
-  int rc = check_ctx(c);
+  int rc = guard(c);
   if (rc) return rc;
   if (!cfg) return fail(c, ICM_E_INVALID, "null config");
   icm_run_config n = c->cfg;
@@ -1155,20 +1166,20 @@ int icm_set_run_config(icm_ctx* c, const icm_run_config* cfg) {
 
 int icm_get_run_config(icm_ctx* c, icm_run_config* cfg) {
   if (!c || !cfg) return ICM_E_INVALID;
+  if (c->serving) return ICM_E_BUSY;
   *cfg = c->cfg;
   return ICM_OK;
 }
 
-int icm_read_energies(icm_ctx* c, int32_t h, int64_t* raw, double* real, size_t cap) {
-  int rc = check_ctx(c);
-  if (rc) return rc;
+static int read_energies_impl(icm_ctx* c, int32_t h, int64_t* raw, double* real, size_t cap) {
+  int rc = ICM_OK;
   Instance* in = find(c, h);
   if (!in) return fail(c, ICM_E_NOTFOUND, "unknown handle %d", h);
   if (cap < (size_t)in->K * in->R) return fail(c, ICM_E_BUFSIZE, "need %d elements", in->K * in->R);
   HostState hs;
   rc = fetch_state(c, in, hs, false);
   if (rc) return rc;
-  const double unit = in->jkind == ICM_J_F32 ? std::ldexp(1.0, -32) : 1.0 / in->jscale;
+  const double unit = in->jkind == ICM_J_F32 ? std::ldexp(1.0, -40) : 1.0 / in->jscale;
   for (int x = 0; x < in->K * in->R; ++x) {
     const int64_t e = hs.energy[hs.at[x]];
     if (raw) raw[x] = e;
@@ -1177,9 +1188,14 @@ int icm_read_energies(icm_ctx* c, int32_t h, int64_t* raw, double* real, size_t 
   return ICM_OK;
 }
 
-int icm_read_states(icm_ctx* c, int32_t h, int8_t* out, size_t cap) {
-  int rc = check_ctx(c);
+int icm_read_energies(icm_ctx* c, int32_t h, int64_t* raw, double* real, size_t cap) {
+  int rc = guard(c);
   if (rc) return rc;
+  return read_energies_impl(c, h, raw, real, cap);
+}
+
+static int read_states_impl(icm_ctx* c, int32_t h, int8_t* out, size_t cap) {
+  int rc = ICM_OK;
   Instance* in = find(c, h);
   if (!in) return fail(c, ICM_E_NOTFOUND, "unknown handle %d", h);
   if (!out || cap < (size_t)in->W * in->N) return fail(c, ICM_E_BUFSIZE, "need %d bytes", in->W * in->N);
@@ -1190,8 +1206,14 @@ int icm_read_states(icm_ctx* c, int32_t h, int8_t* out, size_t cap) {
   return ICM_OK;
 }
 
+int icm_read_states(icm_ctx* c, int32_t h, int8_t* out, size_t cap) {
+  int rc = guard(c);
+  if (rc) return rc;
+  return read_states_impl(c, h, out, cap);
+}
+
 int icm_read_walkers(icm_ctx* c, int32_t h, int32_t* out, size_t cap) {
-  int rc = check_ctx(c);
+  int rc = guard(c);
   if (rc) return rc;
   Instance* in = find(c, h);
   if (!in) return fail(c, ICM_E_NOTFOUND, "unknown handle %d", h);
@@ -1204,34 +1226,32 @@ int icm_read_walkers(icm_ctx* c, int32_t h, int32_t* out, size_t cap) {
 }
 
 int icm_read_overlaps(icm_ctx* c, int32_t h, int32_t* q_sum, int32_t* ql_sum, size_t cap) {
-  int rc = check_ctx(c);
+  int rc = guard(c);
   if (rc) return rc;
   Instance* in = find(c, h);
   if (!in) return fail(c, ICM_E_NOTFOUND, "unknown handle %d", h);
-  const int half = in->R / 2;
-  if (cap < (size_t)in->K * half) return fail(c, ICM_E_BUFSIZE, "need %d elements", in->K * half);
-  HostState hs;
-  rc = fetch_state(c, in, hs, true);
-  if (rc) return rc;
-  std::vector<int8_t> st((size_t)in->W * in->N);
-  states_from(in, hs, st.data());
-  const int N = in->N;
-  for (int k = 0; k < in->K; ++k)
-    for (int p = 0; p < half; ++p) {
-      const int8_t* a = &st[((size_t)k * in->R + 2 * p) * N];
-      const int8_t* b = &st[((size_t)k * in->R + 2 * p + 1) * N];
-      int q = 0, ql = 0;
-      for (int i = 0; i < N; ++i) q += a[i] * b[i];
-      for (const auto& e : in->topo->bonds) ql += a[e.first] * a[e.second] * b[e.first] * b[e.second];
-      if (q_sum) q_sum[k * half + p] = q;
-      if (ql_sum) ql_sum[k * half + p] = ql;
-    }
+  const int half = in->R / 2, n = in->K * half;
+  if (cap < (size_t)n) return fail(c, ICM_E_BUFSIZE, "need %d elements", n);
+  int32_t* d = (int32_t*)c->arena.alloc((size_t)2 * n * 4);
+  if (!d) return fail(c, ICM_E_NOMEM, "arena full (overlap readout)");
+  std::vector<int32_t> host((size_t)2 * n);
+  const int e = icmk_launch_overlaps(in->unit.spins, in->unit.nbr, in->unit.at, in->unit.gauge, in->N, in->deg,
+                                     in->K, in->R, in->topo->topo, (int)in->topo->bonds.size(), d, d + n,
+                                     c->stream);
+  int r = ICM_OK;
+  if (e != 0 || hipMemcpyAsync(host.data(), d, host.size() * 4, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
+    r = fail(c, ICM_E_DEVICE, "overlap readout failed");
+  c->arena.release(d);
+  if (r) return r;
+  if (q_sum) std::memcpy(q_sum, host.data(), (size_t)n * 4);
+  if (ql_sum) std::memcpy(ql_sum, host.data() + n, (size_t)n * 4);
   return ICM_OK;
 }
 
 int icm_read_labels(icm_ctx* c, int32_t h, int32_t k, int32_t pair, int32_t* labels, int32_t* seed,
                     int32_t* n_minus, size_t cap) {
-  int rc = check_ctx(c);
+  int rc = guard(c);
   if (rc) return rc;
   Instance* in = find(c, h);
   if (!in) return fail(c, ICM_E_NOTFOUND, "unknown handle %d", h);
@@ -1251,7 +1271,7 @@ int icm_read_labels(icm_ctx* c, int32_t h, int32_t k, int32_t pair, int32_t* lab
 }
 
 int icm_read_observables(icm_ctx* c, int32_t h, int64_t* sums, int64_t* counts, size_t cap) {
-  int rc = check_ctx(c);
+  int rc = guard(c);
   if (rc) return rc;
   Instance* in = find(c, h);
   if (!in) return fail(c, ICM_E_NOTFOUND, "unknown handle %d", h);
@@ -1267,7 +1287,7 @@ int icm_read_observables(icm_ctx* c, int32_t h, int64_t* sums, int64_t* counts, 
 }
 
 int icm_read_stats(icm_ctx* c, int32_t h, icm_stats* out) {
-  int rc = check_ctx(c);
+  int rc = guard(c);
   if (rc) return rc;
   Instance* in = find(c, h);
   if (!in) return fail(c, ICM_E_NOTFOUND, "unknown handle %d", h);
@@ -1287,13 +1307,14 @@ int icm_read_stats(icm_ctx* c, int32_t h, icm_stats* out) {
 }
 
 uint32_t icm_sweep_index(icm_ctx* c, int32_t h) {
-  if (!c) return 0;
+  if (!c || c->serving) return 0;
   Instance* in = find(c, h);
   return in ? in->sweep_host : 0;
 }
 
 int icm_arena_usage(icm_ctx* c, size_t* used, size_t* total) {
   if (!c) return ICM_E_INVALID;
+  if (c->serving) return ICM_E_BUSY;
   if (used) *used = c->arena.used();
   if (total) *total = c->arena.size();
   return ICM_OK;
@@ -1328,8 +1349,8 @@ void retire(icm_ctx* c, const std::shared_ptr<Request>& r) {
   Instance* in = find(c, r->handle);
   std::vector<int64_t> e((size_t)in->K * in->R);
   std::vector<int8_t> st((size_t)in->W * in->N);
-  icm_read_energies(c, r->handle, e.data(), nullptr, e.size());
-  icm_read_states(c, r->handle, st.data(), st.size());
+  read_energies_impl(c, r->handle, e.data(), nullptr, e.size());
+  read_states_impl(c, r->handle, st.data(), st.size());
   drop_cached_tables(c, r->handle);
   release_instance(c, in);
   c->instances.erase(r->handle);
@@ -1403,7 +1424,7 @@ void serve_loop(icm_ctx* c) {
         int rc = add_instance_impl(c, &r->desc, &h);
         if (rc == ICM_E_NOMEM && (resident() || !admitted.empty())) break;  // wait for a retirement
         c->queue.pop_front();
-        if (rc == ICM_OK) rc = icm_init_states(c, h);
+        if (rc == ICM_OK) rc = init_states_impl(c, h);
         if (rc != ICM_OK) {  // invalid, or larger than the whole arena
           r->error = rc;
           r->done = true;
@@ -1487,7 +1508,7 @@ extern "C" {
 int icm_serve_start(icm_ctx* c, int32_t sweeps_per_block) {
   int rc = check_ctx(c);
   if (rc) return rc;
-  if (c->serving) return fail(c, ICM_E_BUSY, "already serving");
+  if (c->serving) return ICM_E_BUSY;
   if (sweeps_per_block <= 0) return fail(c, ICM_E_INVALID, "sweeps_per_block must be > 0");
   c->serve_block = sweeps_per_block;
   c->serving = true;

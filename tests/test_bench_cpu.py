@@ -1,5 +1,6 @@
 """Host-side parts of bench.py that need no GPU: the one-GPU guard of every
-mode and the algorithmic byte and operation counts its roofline uses."""
+mode, the algorithmic byte counts of its roofline, the step's launch shape and
+the rule that measured counters apply only to the kernel they were taken on."""
 import json
 import os
 import subprocess
@@ -31,12 +32,35 @@ def test_algorithmic_counts_of_the_bench_workload():
     b = bench.algorithmic_bytes_per_sweep(spec, N, 3 * N, 4)
     assert b == 2 * 80 * 512 + 1536 * 4 == 88064
     assert abs(b / (S * N) - 2.15) < 1e-3
-    # a quarter Philox block (10), six extract + multiply-add (12), the
-    # acceptance (5 float, 3 integer), the flip (1)
-    assert bench.algorithmic_ops_per_attempt(6, "gauss") == 28
-    assert bench.algorithmic_ops_per_attempt(6, "int3") == 26
-    assert bench.algorithmic_ops_per_move(512) == 1024
     assert abs(bench.VALU_PEAK_TOPS - 39.3216) < 1e-9
+
+
+def test_default_step_is_several_graph_replayed_launches():
+    # a step of the headline line covers four launches of the fused kernel,
+    # so the captured graph is replayed inside the timed region, and the 20
+    # driver steps cover more than the workload's 2^14 sweeps
+    spl = bench.DEFAULT_LAUNCH["sweeps_per_launch"]
+    assert bench.SWEEPS_PER_STEP % spl == 0 and bench.SWEEPS_PER_STEP // spl == 4
+    assert bench.DEFAULT_LAUNCH["use_graph"] == 1
+    assert 20 * bench.SWEEPS_PER_STEP >= inputs.WORKLOADS["3d_L8_gauss_1024inst"]["n_sweeps"]
+
+
+def test_profiled_counters_apply_only_to_their_kernel_and_shape():
+    cfg = dict(bench.DEFAULT_LAUNCH)
+    tag = bench.launch_tag(cfg)
+    assert tag == "t256_s16_spl256"
+    saved = dict(bench.PROFILED)
+    try:
+        bench.PROFILED["w"] = {"kernel": bench.kernel_source_digest(), "launch": tag,
+                               "hbm_bytes_per_launch": 1, "valu_insts_per_launch": 2}
+        assert bench.profiled("w", cfg)["valu_insts_per_launch"] == 2
+        assert bench.profiled("w", dict(cfg, icm_slots=8)) is None
+        bench.PROFILED["w"]["kernel"] = "0" * 16
+        assert bench.profiled("w", cfg) is None
+        assert bench.profiled("other", cfg) is None
+    finally:
+        bench.PROFILED.clear()
+        bench.PROFILED.update(saved)
 
 
 def test_launch_threads_follows_the_size_classes():

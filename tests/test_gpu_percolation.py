@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import oracle as orc
-from paper_1501_05630_amd import icm, inputs
+from paper_1501_05630_amd import analysis, icm, inputs
 
 pytestmark = pytest.mark.gpu
 SEED = inputs.MASTER_SEED
@@ -109,7 +109,7 @@ def test_binder_crossing_at_the_papers_threshold(ctx, name, top, sizes, tol):
     n = 1 << 16
     d = []
     for p in ps:
-        g = [icm.binder_ratio(ctx.icm_percolation_smax(top, L, float(p), n, sample0=0, key=L).cpu().numpy())
+        g = [analysis.binder_ratio(ctx.icm_percolation_smax(top, L, float(p), n, sample0=0, key=L).cpu().numpy())
              for L in sizes]
         d.append(g[1] - g[0])
     d = np.array(d)

@@ -6,6 +6,7 @@ and HCA mode (no step 2a, cluster moves at every temperature)."""
 import numpy as np
 import pytest
 
+import gridded
 import oracle as orc
 from paper_1501_05630_amd import icm, inputs
 
@@ -42,7 +43,7 @@ CASES = [(inputs.SQUARE2D, 16, "pmJ", 1), (inputs.CUBIC3D, 6, "gauss", 1), (inpu
 
 @pytest.mark.parametrize("top,L,kind,scale", CASES)
 def test_annealing_with_cluster_moves_bit_exact(ctx, top, L, kind, scale):
-    J = inputs.make_couplings(kind, top, L, inputs.make_rng(110, L))
+    J = gridded.make_couplings(kind, top, L, inputs.make_rng(110, L))
     h, o = pair(ctx, top, L, J, [3.0], 8, 1, icm.FLAG_2A, 21, scale)
     ctx.icm_init_states(h)
     o.init_hot()
@@ -58,7 +59,7 @@ def test_annealing_with_cluster_moves_bit_exact(ctx, top, L, kind, scale):
 
 @pytest.mark.parametrize("top,L,kind,scale", CASES[:3])
 def test_pt_ladder_replaced_mid_run_bit_exact(ctx, top, L, kind, scale):
-    J = inputs.make_couplings(kind, top, L, inputs.make_rng(111, L))
+    J = gridded.make_couplings(kind, top, L, inputs.make_rng(111, L))
     temps = inputs.geometric_temps(0.5, 2.0, 5)
     h, o = pair(ctx, top, L, J, temps, 2, 3, icm.FLAG_2A | icm.FLAG_PT, 22, scale)
     ctx.icm_init_states(h)
@@ -88,7 +89,7 @@ def test_zero_temperature_cluster_hopping_bit_exact(ctx, top, L, kind, scale):
     # anneal, then at a temperature where no uphill flip is accepted the energy
     # of each replica pair never rises (a cluster move keeps E_a + E_b and moves
     # energy between the two) while the cluster moves keep changing the states
-    J = inputs.make_couplings(kind, top, L, inputs.make_rng(112, L))
+    J = gridded.make_couplings(kind, top, L, inputs.make_rng(112, L))
     R = 8
     h, o = pair(ctx, top, L, J, [2.0], R, 1, icm.FLAG_2A, 23, scale)
     ctx.icm_init_states(h)
@@ -121,7 +122,7 @@ def test_zero_temperature_cluster_hopping_bit_exact(ctx, top, L, kind, scale):
 @pytest.mark.parametrize("top,L,kind,scale", [(inputs.SQUARE2D, 8, "pmJ", 1), (inputs.CUBIC3D, 4, "gauss", 1),
                                               (inputs.CHIMERA, 3, "int3", 3)])
 def test_hca_mode_trajectory_bit_exact(ctx, top, L, kind, scale):
-    J = inputs.make_couplings(kind, top, L, inputs.make_rng(113, L))
+    J = gridded.make_couplings(kind, top, L, inputs.make_rng(113, L))
     temps = inputs.geometric_temps(0.4, 2.5, 6)
     h, o = pair(ctx, top, L, J, temps, 4, len(temps), icm.FLAG_PT, 24, scale)
     ctx.icm_init_states(h)

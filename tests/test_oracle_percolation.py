@@ -17,7 +17,7 @@ from scipy.sparse import coo_matrix
 from scipy.sparse.csgraph import connected_components
 
 import oracle as orc
-from paper_1501_05630_amd import icm, inputs
+from paper_1501_05630_amd import analysis, inputs
 
 import exact
 
@@ -100,9 +100,9 @@ def test_moments_match_exact_enumeration(top, L):
 
 
 def test_binder_ratio_helper():
-    assert icm.binder_ratio(np.full(10, 7)) == 1.0
+    assert analysis.binder_ratio(np.full(10, 7)) == 1.0
     # s in {1, 3} with equal weight: <s^2> = 5, <s^4> = 41
-    assert abs(icm.binder_ratio([1, 3] * 50) - 0.5 * (3 - 41 / 25)) < 1e-12
+    assert abs(analysis.binder_ratio([1, 3] * 50) - 0.5 * (3 - 41 / 25)) < 1e-12
 
 
 def test_binder_collapse_recovers_a_known_scaling_form():
@@ -116,5 +116,5 @@ def test_binder_collapse_recovers_a_known_scaling_form():
         x = n ** (0.5 / nu) * (1 / ps - 1 / pc)
         g.append(0.72 - 0.08 * x + 0.004 * x ** 2 + 0.001 * x ** 3 + rng.normal(0, 1e-4, len(ps)))
         se.append(np.full(len(ps), 1e-4))
-    p_fit, nu_fit, chi = icm.binder_collapse(ps, sizes, g, se, 0.38, 1.2, degree=3)
+    p_fit, nu_fit, chi = analysis.binder_collapse(ps, sizes, g, se, 0.38, 1.2, degree=3)
     assert abs(p_fit - pc) < 2e-4 and abs(nu_fit - nu) < 0.03 and chi < 3.0, (p_fit, nu_fit, chi)
