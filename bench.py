@@ -501,7 +501,7 @@ def run_anneal(args):
     residual energy per spin; then zero-temperature dynamics from the annealed
     states, with and without cluster moves, counting the distinct
     lowest-energy configurations visited (hopping through a degenerate
-    ground-state manifold, discussion of Fig. 4)."""
+    ground-state manifold, discussion of Fig. 1)."""
     import numpy as np
     import torch
 

@@ -56,7 +56,8 @@
  *
  * Threading: one context per host thread, except icm_submit / icm_poll /
  * icm_take_result, which may be called from any thread while the serving loop
- * runs.
+ * runs.  While it runs, the loop owns the context: every other call returns
+ * ICM_E_BUSY (and does not set icm_last_error, which the loop may be writing).
  */
 #ifndef ICM_H
 #define ICM_H
@@ -143,33 +144,63 @@ typedef struct {
 
 /* Creates a context on `device`, issuing all work on `hip_stream` (a
    hipStream_t, NULL = the null stream).  `arena` is a caller-owned device
-   buffer of arena_bytes (>= 1 MiB, 256-byte aligned); `seed` is Philox key
-   word 0 for every instance of the context. */
+   buffer of arena_bytes (>= 1 MiB, 256-byte aligned) that must outlive the
+   context; `seed` is Philox key word 0 for every instance of the context.
+   The container of the paper's simulations: many disorder instances, each
+   with its temperatures and replicas (Table I: N_sa instances per size).
+   Errors: ICM_E_INVALID (null out, arena too small or misaligned),
+   ICM_E_DEVICE (no such device). */
 int icm_create(icm_ctx** out, int device, void* hip_stream, void* arena, size_t arena_bytes,
                uint32_t seed);
+/* Stops serving if it runs, waits for the stream, frees everything the
+   context holds (not the arena, which the caller owns). */
 int icm_destroy(icm_ctx* ctx);
 
-/* Copies the descriptor (couplings, temperatures) into the arena and returns a
-   handle.  ICM_E_INVALID for a bad descriptor, ICM_E_NOMEM when the arena is
-   full.  The state is all spins up until icm_init_states / icm_set_states. */
+/* One disorder instance of the model paragraph (graph, couplings J_ij) with
+   its temperature ladder, replicas and cluster-move temperatures (Table I:
+   N_T temperatures, cluster moves at the lowest N_c).  Copies the descriptor
+   (couplings, temperatures) into the arena and returns a handle; no caller
+   pointer is kept.  The state is all spins up until icm_init_states /
+   icm_set_states.  Errors: ICM_E_INVALID (bad descriptor), ICM_E_NOMEM
+   (arena full), ICM_E_BUSY (serving), ICM_E_DEVICE. */
 int icm_add_instance(icm_ctx* ctx, const icm_instance_desc* d, int32_t* out_handle);
+/* Frees the instance's arena blocks.  ICM_E_NOTFOUND, ICM_E_BUSY. */
 int icm_remove_instance(icm_ctx* ctx, int32_t handle);
 /* Arena bytes an instance with this descriptor needs (0 if invalid). */
 size_t icm_instance_bytes(const icm_instance_desc* d);
 
-/* Hot start: every walker draws its spins from Philox; sweep counter = 0. */
+/* Initial state (the paper does not give one): a hot start, every walker's
+   spins drawn from Philox (stream INIT above); temperature labels w -> h,
+   gauge cleared, sweep counter = 0, statistics and observables cleared.
+   ICM_E_NOTFOUND, ICM_E_BUSY, ICM_E_DEVICE. */
 int icm_init_states(icm_ctx* ctx, int32_t handle);
 /* Sets spins [K][R][N] (host, any nonzero int8; < 0 means down) in
-   temperature order, resets temperature labels and gauge, sweep counter =
-   sweep0. */
+   temperature order, resets temperature labels, gauge, statistics and
+   observables; sweep counter = sweep0.  The state is copied before return.
+   ICM_E_INVALID (null spins), ICM_E_NOTFOUND, ICM_E_NOMEM (staging),
+   ICM_E_BUSY, ICM_E_DEVICE. */
 int icm_set_states(icm_ctx* ctx, int32_t handle, const int8_t* spins, uint32_t sweep0);
 
-/* Runs n_sweeps simulation steps on every listed instance with batched,
-   fused launches (asynchronous on the context stream). */
+/* Runs n_sweeps simulation steps -- the paper's isoenergetic cluster
+   algorithm list: step 1 (a Metropolis sweep of every replica), steps 2a and
+   2b (at the K_c coldest temperatures, for every pair of chains), step 3 (a
+   PT sweep over neighbouring temperatures) -- on every listed instance, with
+   batched launches of the fused kernel (one per size class and sweep block;
+   replayed from a captured graph when use_graph is set and a run spans
+   several launches).  Asynchronous on the context stream; the results do not
+   depend on the batch, the launch shape or the block size.
+   Errors: ICM_E_INVALID (bad list, a handle twice, a unit larger than the
+   device's LDS), ICM_E_NOTFOUND, ICM_E_NOMEM (work table), ICM_E_BUSY,
+   ICM_E_DEVICE. */
 int icm_run(icm_ctx* ctx, const int32_t* handles, int32_t n, uint32_t n_sweeps);
-/* Baseline mode: the same kernels, one instance per launch, no graph. */
+/* The same simulation steps with plain per-instance launches (one instance
+   per launch, no graph): the baseline the batched form is measured against.
+   Same errors as icm_run. */
 int icm_run_per_instance(icm_ctx* ctx, const int32_t* handles, int32_t n, uint32_t n_sweeps);
+/* Waits for the context stream.  ICM_E_BUSY, ICM_E_DEVICE. */
 int icm_sync(icm_ctx* ctx);
+/* Launch shape of later runs (fields 0 keep the current value).
+   ICM_E_INVALID for values outside the ranges above, ICM_E_BUSY. */
 int icm_set_run_config(icm_ctx* ctx, const icm_run_config* cfg);
 int icm_get_run_config(icm_ctx* ctx, icm_run_config* cfg);
 
@@ -177,19 +208,35 @@ int icm_get_run_config(icm_ctx* ctx, icm_run_config* cfg);
    walker, [K][R] in temperature order: raw (int64: units of 1/j_scale, or
    2^-40 for F32) and/or real (double); either pointer may be NULL.  cap is the
    number of elements the buffers hold (ICM_E_BUFSIZE if fewer than K R).
-   Synchronizes the context stream. */
+   Synchronizes the context stream.  ICM_E_NOTFOUND, ICM_E_BUSY,
+   ICM_E_DEVICE. */
 int icm_read_energies(icm_ctx* ctx, int32_t handle, int64_t* raw, double* real, size_t cap);
-/* Spins [K][R][N] (+1/-1) in temperature order, canonical site order. */
+/* Spin configurations (the replicas of the paper's method), [K][R][N] int8
+   +1/-1, in temperature order and canonical site order, step 2a's reversals
+   undone (the true spins).  Synchronizes the context stream.
+   ICM_E_BUFSIZE (cap < K R N), ICM_E_NOTFOUND, ICM_E_BUSY, ICM_E_DEVICE. */
 int icm_read_states(icm_ctx* ctx, int32_t handle, int8_t* out, size_t cap);
-/* Site overlap q = sum_i s_i^(2p) s_i^(2p+1) per (k, pair) [K][R/2] and the
-   link overlap numerator sum over bonds of s_i s_j s'_i s'_j [K][R/2] (Eq. 1
-   of the paper uses q_l = that / N_b).  Either pointer may be NULL. */
+/* The two overlaps of the model paragraph for the replicas of each pair
+   (chains 2p, 2p+1) at temperature k, q_i = s_i^(2p) s_i^(2p+1): the spin
+   overlap sum_i q_i (q = that / N) and the link overlap's numerator, the sum
+   over bonds (each once) of q_i q_j (Eq. 1: q_l = that / N_b); [K][R/2]
+   int32 each, formed on the device.  Either pointer may be NULL; cap is the
+   number of elements each holds.  ICM_E_BUFSIZE, ICM_E_NOTFOUND, ICM_E_NOMEM
+   (a scratch of 8 K R/2 bytes in the arena), ICM_E_BUSY, ICM_E_DEVICE. */
 int icm_read_overlaps(icm_ctx* ctx, int32_t handle, int32_t* q_sum, int32_t* ql_sum, size_t cap);
-/* Labels [N] of the last ICM move at temperature k, pair p: minimum site index
-   of the q = -1 component, -1 off the mask; requires ICM_FLAG_RECORD_LABELS.
-   seed = seed site (-1 if no q = -1 site), n_minus = post-2a count. */
+/* Labels [N] of the last cluster move (steps 2a, 2b) of the last step run at
+   temperature k, pair p: the connected q = -1 domains after step 2a, each
+   site labelled with the smallest site index of its domain, -1 off the mask;
+   requires ICM_FLAG_RECORD_LABELS.  seed = the seed site (-1 if no q = -1
+   site), n_minus = the number of q = -1 sites after 2a.  ICM_E_INVALID (no
+   labels recorded, no cluster moves at (k, pair)), ICM_E_BUFSIZE,
+   ICM_E_NOTFOUND, ICM_E_BUSY, ICM_E_DEVICE. */
 int icm_read_labels(icm_ctx* ctx, int32_t handle, int32_t k, int32_t pair, int32_t* labels,
                     int32_t* seed, int32_t* n_minus, size_t cap);
+/* Counters of the steps since the state was set (icm_stats above): accepted
+   Metropolis flips (step 1), cluster moves, their sizes and the 2a reversals
+   (steps 2a, 2b), PT attempts and accepted swaps (step 3).  ICM_E_INVALID
+   (null out), ICM_E_NOTFOUND, ICM_E_BUSY, ICM_E_DEVICE. */
 int icm_read_stats(icm_ctx* ctx, int32_t handle, icm_stats* out);
 /* Observables of the paper's "Benchmark model and observables" paragraph (the
    energy, the link overlap q_l of Eq. 1 and the spin overlap) and of its
@@ -212,15 +259,19 @@ int icm_read_stats(icm_ctx* ctx, int32_t handle, icm_stats* out);
    and Delta = <E(q_l)> - <H/N> (Eq. 2) follow from the bin means.
    cap = capacity of sums in elements; ICM_E_BUFSIZE if too small. */
 int icm_read_observables(icm_ctx* ctx, int32_t handle, int64_t* sums, int64_t* counts, size_t cap);
-/* Walker index at (k, r), [K][R] (PT permutation). */
+/* Walker index at (k, r), [K][R]: the permutation of replicas over
+   temperatures that step 3 (parallel tempering) maintains.  ICM_E_BUFSIZE,
+   ICM_E_NOTFOUND, ICM_E_BUSY, ICM_E_DEVICE. */
 int icm_read_walkers(icm_ctx* ctx, int32_t handle, int32_t* out, size_t cap);
+/* The instance's sweep counter t (the counter of the random streams); 0 for
+   an unknown handle or while serving. */
 uint32_t icm_sweep_index(icm_ctx* ctx, int32_t handle);
 
 /* Replaces the K temperatures of an instance (same K; finite, > 0, strictly
    ascending), for annealing schedules: the paper proposes adding the cluster
    moves at every temperature step of simulated annealing (introduction), and
    hopping through a degenerate ground-state manifold with cluster moves at
-   very low temperature (discussion of Fig. 4).  The walkers keep their spins,
+   very low temperature (discussion of Fig. 1).  The walkers keep their spins,
    temperature labels, energies and sweep counter; walker (k, r) continues at
    the new T_k.  Ordered after earlier work on the context stream; returns
    when the new tables are on the device.  Integer couplings with PT: the
@@ -249,23 +300,42 @@ int icm_set_temperatures(icm_ctx* ctx, int32_t handle, const double* temps);
 int icm_percolation_smax(icm_ctx* ctx, int32_t topology, int32_t L, double p, uint32_t sample0,
                          uint32_t n_samples, uint32_t key, int32_t* smax);
 
-/* Serving: a request = descriptor + n_sweeps from a hot start.  The loop
-   admits requests at sweep-block boundaries while the arena has room, keeps
-   their state on the device, runs them batched with whatever else is
-   resident, and retires them when done.  Thread-safe. */
+/* Serving: thermalization requests -- an instance (descriptor) and a number
+   of simulation steps from a hot start, the paper's unit of work per
+   disorder instance (Table I: 2^b sweeps per instance) -- arriving while
+   others run.  icm_serve_start starts a host thread that admits queued
+   requests at sweep-block boundaries (sweeps_per_block steps) while the
+   arena has room for them, keeps their state on the device, runs the
+   resident requests of each kernel variant and size class together, block
+   by block, on a stream per group, and retires each when it is done.  A
+   request's results are the same as when it runs alone.  Errors:
+   ICM_E_INVALID (sweeps_per_block <= 0), ICM_E_BUSY (already serving),
+   ICM_E_DEVICE. */
 int icm_serve_start(icm_ctx* ctx, int32_t sweeps_per_block);
+/* Stops admitting, returns queued requests unrun (ICM_E_BUSY in their
+   result), lets the resident ones finish, joins the thread.  ICM_E_DEVICE if
+   the loop failed on the device. */
 int icm_serve_stop(icm_ctx* ctx);
+/* Queues a request (the descriptor and couplings are copied).  Thread-safe.
+   ICM_E_INVALID (bad descriptor, n_sweeps = 0), ICM_E_BUSY (not serving). */
 int icm_submit(icm_ctx* ctx, const icm_instance_desc* d, uint32_t n_sweeps, uint64_t* ticket);
-/* done = 1 when the result is ready; latency_us = submit-to-retire time. */
+/* done = 1 when the result is ready; latency_us = submit-to-retire time.
+   Thread-safe.  ICM_E_NOTFOUND for an unknown or taken ticket. */
 int icm_poll(icm_ctx* ctx, uint64_t ticket, int32_t* done, double* latency_us);
-/* Energies [K][R] raw and states [K][R][N] (either may be NULL); frees the
-   ticket. */
+/* Energies [K][R] raw and states [K][R][N] (either may be NULL) of a
+   finished request, in the units and order of icm_read_energies /
+   icm_read_states; frees the ticket.  Thread-safe.  ICM_E_BUSY (not done),
+   ICM_E_BUFSIZE, ICM_E_NOTFOUND, or the request's own error (ICM_E_NOMEM if
+   it can never fit the arena, ICM_E_DEVICE). */
 int icm_take_result(icm_ctx* ctx, uint64_t ticket, int64_t* energies, int8_t* states,
                     size_t cap_energies, size_t cap_states);
 
+/* Static text for an ICM_* code. */
 const char* icm_strerror(int code);
+/* Reason of the context's last failure (valid until the next call on it). */
 const char* icm_last_error(icm_ctx* ctx);
-/* Bytes of arena in use / total. */
+/* Bytes of arena in use / total (the HBM budget serving admits against).
+   ICM_E_INVALID, ICM_E_BUSY. */
 int icm_arena_usage(icm_ctx* ctx, size_t* used, size_t* total);
 
 #ifdef __cplusplus

@@ -45,11 +45,11 @@ struct UnitDesc {
   int32_t* tau;             // [Wp] temperature of walker (K for padding walkers)
   int32_t* at;              // [K][R] walker at temperature k in chain r
   uint8_t* gauge;           // [Wp] 1 = stored spins are the reversal of the true ones
-  int64_t* energy;          // [Wp] raw energies
+  int64_t* energy;          // [Wp] raw energies (1/j_scale, or 2^-40 for float couplings)
   unsigned long long* stats;// [kNumStats]
   int32_t* labels;          // [Kc][R/2][N] (RECORD_LABELS only)
   int32_t* seeds;           // [Kc][R/2] seed site, then [Kc][R/2] n_minus
-  int64_t* obs;             // MEASURE only: [32][K][R/2][3] observable sums, then [32] counts
+  int64_t* obs;             // MEASURE only: [32][K][R/2][4] observable sums, then [32] counts
   uint32_t* sweep;          // sweep counter t
   int32_t N, Nc, deg, W, Wq, K, R, Kc, HM, ptlen, jkind, jscale;
   uint32_t flags, seed, key;

@@ -386,11 +386,12 @@ def test_step_2a_is_strict_at_exactly_half(ctx, metro):
     L, N = 4, 16
     J = np.ones((N, 2), dtype=np.int8)
     flags = icm.FLAG_2A | icm.FLAG_RECORD_LABELS | (0 if metro else icm.FLAG_SKIP_METRO)
-    h, o = make_pair(ctx, inputs.SQUARE2D, L, J, [0.05], 2, 1, flags, key=23)
     a = np.ones(N, dtype=np.int8)
     b = a.copy()
     b[:2 * L] = -1
     for extra in (False, True):
+        # a fresh pair per case: the statistics compared below count from it
+        h, o = make_pair(ctx, inputs.SQUARE2D, L, J, [0.05], 2, 1, flags, key=23)
         bb = b.copy()
         if extra and not metro:
             bb[N - 1] = -1             # one site more: now 2 n_minus > N
@@ -410,7 +411,7 @@ def test_step_2a_is_strict_at_exactly_half(ctx, metro):
             assert nm == N // 2 and ctx.icm_read_stats(h)["icm_2a_flips"] == 0
             out = ctx.icm_read_states(h)[0]
             assert np.array_equal(out[0], b) and np.array_equal(out[1], a)
-    ctx.icm_remove_instance(h)
+        ctx.icm_remove_instance(h)
 
 
 @pytest.mark.parametrize("top,L,kind,K,R", [

@@ -1,6 +1,6 @@
 """Pins of the method's variants that reuse the same step (the introduction's
 simulated annealing with cluster moves at every temperature step, the
-zero-temperature ground-state hopping of the discussion of Fig. 4, and the
+zero-temperature ground-state hopping of the discussion of Fig. 1, and the
 Houdayer algorithm without step 2a).
 
 - changing the temperatures of a running simulation continues exactly as a
