@@ -66,7 +66,9 @@ ICM_HD uint32_t align16(uint32_t x) { return (x + 15u) & ~15u; }
 
 // Byte offsets of the regions of the fused kernel's LDS image of one unit.
 // Spins are bit-packed in LDS: word (g, i) holds walkers 32g..32g+31 at site i,
-// bit set = spin down.
+// bit set = spin down, in rows of 32 site_words(N) words per group g (the
+// sites past N are zero), so that the image transposes in place into its
+// walker-major view by 32 x 32 blocks.
 struct LdsLayout {
   uint32_t sp, nbr, clist, coup, tau, at, gauge, energy, thr, beta, bl2e, dbl2e, ptu, icmu, terms, jplanes,
       slots, parent, meas, stats, total;
@@ -121,7 +123,7 @@ ICM_HD LdsLayout lds_layout(int N, int deg, int Wq, int K, int R, int HM, int jk
   const int Wp = 4 * Wq;
   const uint32_t tn = tables ? (uint32_t)N : 0u;
   const uint32_t ns = Kc > 0 ? (uint32_t)slots_reserved(N, slots) : 0u;
-  L.sp = o;      o = align16(o + 4u * bit_words(Wq) * N);
+  L.sp = o;      o = align16(o + 4u * bit_words(Wq) * 32u * site_words(N));  // rows padded to whole words
   L.nbr = o;     o = align16(o + 2u * tn * deg);
   L.clist = o;   o = align16(o + 2u * tn);
   L.coup = o;    o = align16(o + (jkind ? 4u : 1u) * tn * deg);

@@ -448,6 +448,97 @@ __device__ __forceinline__ uint32_t shifted_word(const uint32_t* F, int w, int s
 }
 
 
+// ----------------------------------------------------------------------------
+// The LDS spin image in two views.  Site-major (Metropolis): word (g, i) at
+// g Np + i holds walkers 32g..32g+31 at site i.  Walker-major (cluster
+// moves): for walker w and site word j, the bits of sites 32j..32j+31 -- what
+// a move's q-mask and cluster bitsets are made of.  Block (g, j) is the 32
+// words g Np + 32j .. g Np + 32j + 31 in both views, so the switch is an
+// in-place 32 x 32 bit transpose per block; in the walker-major view walker
+// 32g + r of block j sits at position r ^ (j & 31), so that the lanes of a
+// move, which read consecutive words of one walker, hit distinct LDS banks.
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ int wt_index(int w, int j, int Np) { return (w >> 5) * Np + 32 * j + ((w ^ j) & 31); }
+
+// Row r ^ s of the half-wave (32 lanes) for s = 16, 8, 4, 2, 1.
+template <int S>
+__device__ __forceinline__ uint32_t partner_row(uint32_t x) {
+  if constexpr (S == 16) return (uint32_t)__builtin_amdgcn_ds_swizzle((int)x, 0x401F);  // xor 16 in 32 lanes
+  if constexpr (S == 8) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x128, 0xF, 0xF, false);  // row_ror:8
+  if constexpr (S == 4) {
+    // lanes with bit 2 clear (banks 0, 2 of a row) read lane + 4, the others lane - 4
+    const int up = __builtin_amdgcn_update_dpp(0, (int)x, 0x104, 0xF, 0x5, false);   // row_shl:4
+    return (uint32_t)__builtin_amdgcn_update_dpp(up, (int)x, 0x114, 0xF, 0xA, false);  // row_shr:4
+  }
+  if constexpr (S == 2) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x4E, 0xF, 0xF, false);  // quad [2,3,0,1]
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0xB1, 0xF, 0xF, false);                     // quad [1,0,3,2]
+}
+
+// One stage of the 32 x 32 bit transpose (lane r holds row r of the block):
+// the off-diagonal s x s sub-blocks of every 2s x 2s block trade places with
+// the partner row r ^ s -- a row with bit s clear takes the partner's low
+// column halves into its high ones, the other row the reverse.
+template <int S>
+__device__ __forceinline__ uint32_t transpose_stage(uint32_t x, int r) {
+  constexpr uint32_t lo = S == 16 ? 0x0000FFFFu : (S == 8 ? 0x00FF00FFu : (S == 4 ? 0x0F0F0F0Fu : (S == 2 ? 0x33333333u : 0x55555555u)));
+  const uint32_t p = partner_row<S>(x);
+  const bool low_row = (r & S) == 0;
+  const uint32_t m = low_row ? ~lo : lo;
+  const uint32_t y = __builtin_amdgcn_alignbit(p, p, low_row ? 32u - S : (uint32_t)S);  // p << S or p >> S (rotated)
+  return (y & m) | (x & ~m);
+}
+
+__device__ __forceinline__ uint32_t transpose32(uint32_t x, int r) {
+  x = transpose_stage<16>(x, r);
+  x = transpose_stage<8>(x, r);
+  x = transpose_stage<4>(x, r);
+  x = transpose_stage<2>(x, r);
+  return transpose_stage<1>(x, r);
+}
+
+// Switches the whole image between the views (to_walkers: site-major ->
+// walker-major), every wave taking two blocks at a time (one per half-wave).
+// All lanes run every stage (the cross-lane reads need them); lanes past the
+// last block only skip their loads and stores.
+__device__ __forceinline__ void transpose_image(uint32_t* sp, int G, int nw, bool to_walkers) {
+  const int lane = lane_id(), half = lane >> 5, r = lane & 31;
+  const int nblk = G * nw, Np = 32 * nw, nwaves = (int)(blockDim.x >> 6);
+  for (int base = 2 * wave_id(); base < nblk; base += 2 * nwaves) {
+    const int blk = base + half;
+    const bool live = blk < nblk;
+    const int g = live ? blk / nw : 0, j = live ? blk - g * nw : 0;
+    const int site_pos = g * Np + 32 * j + r, walker_pos = g * Np + 32 * j + ((r ^ j) & 31);
+    const uint32_t x = live ? sp[to_walkers ? site_pos : walker_pos] : 0u;
+    const uint32_t t = transpose32(x, r);
+    if (live) sp[to_walkers ? walker_pos : site_pos] = t;
+  }
+}
+
+// Sum over the lpm lanes of each lane group (16, 32 or 64: one, two or four
+// DPP rows), returned to every lane of the group.
+__device__ __forceinline__ int group_sum(int v, int lpm) {
+  v = dpp_row_sum(v);
+  if (lpm == 16) return v;
+  const int r0 = __builtin_amdgcn_readlane(v, 0), r1 = __builtin_amdgcn_readlane(v, 16);
+  const int r2 = __builtin_amdgcn_readlane(v, 32), r3 = __builtin_amdgcn_readlane(v, 48);
+  if (lpm == 32) return lane_id() < 32 ? r0 + r1 : r2 + r3;
+  return (r0 + r1) + (r2 + r3);
+}
+
+// Exclusive prefix sum within each lane group (rows of 16 lanes: the row
+// scans; groups of 32: row 1 and row 3 add the last value of the row before;
+// 64: the whole wave).
+__device__ __forceinline__ int group_exclusive_scan(int v, int lpm) {
+  int x = v;
+  x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xF, 0xF, false);  // row_shr:1
+  x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xF, 0xF, false);  // row_shr:2
+  x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xF, 0xF, false);  // row_shr:4
+  x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xF, 0xF, false);  // row_shr:8
+  if (lpm >= 32) x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xA, 0xF, false);  // row_bcast:15 into rows 1, 3
+  if (lpm == 64) x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xC, 0xF, false);  // row_bcast:31 into rows 2, 3
+  return x - v;
+}
+
 // The two-word layouts' cluster growth and boundary walk, out of line: they
 // run once per move batch, and inlined they push the fused kernel past its
 // register budget.  LDS regions are passed as byte offsets into the dynamic
@@ -480,20 +571,17 @@ __device__ __noinline__ void pair_grow(bool sq64, uint32_t mc_off, int lane) {
   gmc[4 * lane + 3] = c1;
 }
 
-// Boundary bonds (slot by slot) and the flips of one cluster in the two-word
-// layouts; returns the sum of J s_a,i s_a,j over the bonds that leave it.
+// Boundary bonds (slot by slot) of one cluster in the two-word layouts;
+// returns the sum of J s_a,i s_a,j over the bonds that leave it.
 template <int JK, int DEG>
 __device__ __noinline__ typename EnergyT<JK>::T pair_boundary(bool sq64, uint32_t mc_off, uint32_t aw_off,
                                                              uint32_t coup_off, const void* coup_global,
-                                                             uint32_t rowa_off, uint32_t rowb_off,
-                                                             uint32_t fa, uint32_t fb, int lane, int& csize) {
+                                                             int lane, int& csize) {
   using E_t = typename EnergyT<JK>::T;
   const uint32_t* gmc = (const uint32_t*)(lds + mc_off);
   const uint32_t* gaw = (const uint32_t*)(lds + aw_off);
   const int32_t* cf = coup_global ? (const int32_t*)coup_global : (const int32_t*)(lds + coup_off);
   const int8_t* cj = coup_global ? (const int8_t*)coup_global : (const int8_t*)(lds + coup_off);
-  uint32_t* rowa = (uint32_t*)(lds + rowa_off);
-  uint32_t* rowb = (uint32_t*)(lds + rowb_off);
   const uint32_t cw0 = gmc[4 * lane + 1], cw1 = gmc[4 * lane + 3];
   const uint32_t aw0 = gaw[2 * lane], aw1 = gaw[2 * lane + 1];
   csize = __popc(cw0) + __popc(cw1);
@@ -521,18 +609,6 @@ __device__ __noinline__ typename EnergyT<JK>::T pair_boundary(bool sq64, uint32_
       }
     }
   }
-  const bool same = rowa == rowb;
-#pragma unroll
-  for (int h = 0; h < 2; ++h)
-    for (uint32_t fl = h ? cw1 : cw0; fl; fl &= fl - 1u) {
-      const int i = 64 * lane + 32 * h + __builtin_ctz(fl);
-      if (same) {
-        atomicXor(&rowa[i], fa | fb);
-      } else {
-        atomicXor(&rowa[i], fa);
-        atomicXor(&rowb[i], fb);
-      }
-    }
   return dEa;
 }
 
@@ -566,8 +642,9 @@ __device__ __noinline__ void measure_step(uint32_t t_end, int N, int K, int R, i
   for (int x = wave; x < K * half; x += nwaves) {
     const int k = x / half, p = x - k * half;
     const int a = at[k * R + 2 * p], b = at[k * R + 2 * p + 1];
-    const uint32_t* rowa = sp + (a >> 5) * N;
-    const uint32_t* rowb = sp + (b >> 5) * N;
+    const int Np = 32 * nw;  // row length of the LDS spin image
+    const uint32_t* rowa = sp + (a >> 5) * Np;
+    const uint32_t* rowb = sp + (b >> 5) * Np;
     const int pa = a & 31, pb = b & 31;
     int n = 0;
     for (int s2 = 0; s2 * 64 < N; ++s2) {
@@ -650,12 +727,13 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
 
   const int tid = threadIdx.x, nthr = blockDim.x;
   // ---- load the unit into LDS; int8 quad words -> bit-packed words ----
-  for (int x = tid; x < G * N; x += nthr) {
-    const int g = x / N, i = x - g * N;
+  const int Np = 32 * site_words(N);  // LDS row length (sites past N stay zero)
+  for (int x = tid; x < G * Np; x += nthr) {
+    const int g = x / Np, i = x - g * Np;
     uint32_t bits = 0;
     for (int qq = 0; qq < 8; ++qq) {
       const int q = 8 * g + qq;
-      if (q >= Wq) break;
+      if (q >= Wq || i >= N) break;
       const uint32_t w = U.spins[(size_t)q * N + i];
       // byte 0x01 = up, 0xFF = down: bit 7 of each byte is the down flag
       const uint32_t d = (w >> 7) & 0x01010101u;
@@ -797,7 +875,7 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
           if (j < Nc) {
             const int q0 = QPT * qt;
             const int g = q0 >> 3, sh = 4 * (q0 & 7);
-            uint32_t* row = sp + g * N;
+            uint32_t* row = sp + g * Np;
             const int i = clist[c * Nc + j];
             // bit sh + b of a word is walker 4 q0 + b (one bit-field extract each)
             const uint32_t own = row[i];
@@ -879,17 +957,21 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
     }
 
     // ---------------- steps 2a + 2b: isoenergetic cluster moves ----------------
-    // A move's sites are a bitset of nw words.  Each ICM wave carries P moves
-    // in lane groups of lpm lanes (lane li of a group owns words li, li + lpm).
-    // Set-up, one move at a time with the full wave: ballots over 64 sites
-    // give the q-mask words (replicas differ) and replica a's spin words,
-    // then 2a, the seed (idx-th q = -1 site in ascending order, found from a
-    // prefix of word popcounts).  Growth: every level expands the frontier of
-    // all P clusters at once through the lattice's shift program, restricted
-    // to q-mask sites not yet in the cluster, until no group's frontier is
-    // left.  Then each lane walks its cluster sites: bonds to q = +1
-    // neighbours change sign in replica a (every q = -1 neighbour of the
-    // cluster is in it), and the site flips in both replicas.
+    // A move's sites are a bitset of nw words.  The spin image switches to its
+    // walker-major view first (in-place bit transposes), where walker w's word
+    // j holds its spins at sites 32j..32j+31.  Each ICM wave carries P moves
+    // in lane groups of lpm lanes (lane li of a group owns words li, li + lpm),
+    // and the groups set up their moves side by side: the q-mask word is
+    // a-word ^ b-word (replicas differ, the pair's gauge parity applied), then
+    // 2a, the seed (idx-th q = -1 site in ascending order, from a group prefix
+    // of word popcounts).  Growth: every level expands the frontier of all P
+    // clusters at once through the lattice's shift program, restricted to
+    // q-mask sites not yet in the cluster, until no group's frontier is left.
+    // The bonds that leave the cluster give the energy change (every q = -1
+    // neighbour of the cluster is in it, so they are the bonds whose sign
+    // changes in replica a), and the cluster words are xor-ed into both
+    // walkers' words.  Every walker belongs to one move, so no two lanes touch
+    // the same word.  Then the image switches back.
     if (Kc > 0) {
       const int half = R >> 1;
       const int nmoves = Kc * half;
@@ -908,150 +990,127 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
       const bool cube16 = DEG == 6 && U.topo == 1 && U.L == 16;
       const bool pair = sq64 || cube16;
       const bool record = (flags & kFlagRecord) && s + 1 == n_sweeps;
+      transpose_image(sp, G, nw, true);
+      __syncthreads();
       if (wave < iwaves) {
         const int grp = lane / lpm, li = lane - grp * lpm;
         uint32_t* gsl = (uint32_t*)(lds + lay.slots) + (wave * P + grp) * sw;  // my group's slot
         uint32_t* gmc = gsl + 2 * (nw + 2);
-        const uint32_t* gaw = gmc + 2 * nw;
-        const int* ginfo = (const int*)(gaw + nw);
+        uint32_t* gaw = gmc + 2 * nw;
+        int* ginfo = (int*)(gaw + nw);
         // moves are dealt round-robin over the ICM waves, so every wave gets a
         // mix of cold (small clusters) and warm temperatures
         for (int mbase = wave; mbase < nmoves; mbase += iwaves * P) {
-          // the walkers, gauge parity and seed draw of the wave's moves, read
-          // at once (lane g for move g) ahead of their set-ups
-          int la = 0, lb = 0, lgx = 0;
-          uint32_t lu = 0;
-          if (lane < P && mbase + lane * iwaves < nmoves) {
-            const int mvl = mbase + lane * iwaves, kl = mvl / half, pl = mvl - kl * half;
-            la = at[kl * R + 2 * pl];
-            lb = at[kl * R + 2 * pl + 1];
-            lgx = gauge[la] ^ gauge[lb];
-            lu = icmu[mvl];
+          // ---- set-up: every group its own move ----
+          const int mv = mbase + grp * iwaves;
+          const bool live = mv < nmoves;
+          int a = 0, b = 0;
+          uint32_t gx = 0u, um = 0u;
+          if (live) {
+            const int k = mv / half, p2 = mv - k * half;
+            a = at[k * R + 2 * p2];
+            b = at[k * R + 2 * p2 + 1];
+            gx = (uint32_t)(gauge[a] ^ gauge[b]);
+            um = icmu[mv];
           }
-          // ---- set-up, one move at a time with the full wave ----
-#pragma unroll 1
-          for (int g = 0; g < P; ++g) {
-            const int mv = mbase + g * iwaves, slot = wave * P + g;
-            uint32_t* sl = (uint32_t*)(lds + lay.slots) + slot * sw;
-            uint32_t* f0 = sl + 1;
-            uint32_t* mc = sl + 2 * (nw + 2);
-            uint32_t* aw = mc + 2 * nw;
-            int* info = (int*)(aw + nw);
-            if (mv >= nmoves) {  // no move in this slot: empty cluster
-              for (int w = lane; w < nw; w += 64) { f0[w] = 0; mc[2 * w + 1] = 0; }
-              if (lane == 0) { info[kInMv] = -1; info[kInN] = 0; }
-              continue;
+          // q_i = -1 <=> the true replicas differ at i; sites past N are zero
+          // in both words and are masked out of the parity term
+          uint32_t mw[2] = {0u, 0u}, av[2] = {0u, 0u};
+          int n = 0;
+#pragma unroll
+          for (int k2 = 0; k2 < 2; ++k2) {
+            const int w = li + lpm * k2;
+            if (live && w < nw) {
+              const int rem_bits = N - 32 * w;
+              const uint32_t valid = rem_bits >= 32 ? ~0u : (1u << rem_bits) - 1u;
+              av[k2] = sp[wt_index(a, w, Np)];
+              mw[k2] = av[k2] ^ sp[wt_index(b, w, Np)] ^ (gx ? valid : 0u);
+              n += __popc(mw[k2]);
             }
-            const int a = __builtin_amdgcn_readlane(la, g), b = __builtin_amdgcn_readlane(lb, g);
-            const uint32_t* rowa = sp + (a >> 5) * N;
-            const uint32_t* rowb = sp + (b >> 5) * N;
-            const int pa = a & 31, pb = b & 31;
-            const uint32_t gx = (uint32_t)__builtin_amdgcn_readlane(lgx, g);
-            // q_i = -1 <=> the replicas differ at i; 64 sites per ballot.  Lane l
-            // keeps words l and l + 64 of the mask and of replica a in registers
-            // (no stores in the loop, so its loads can all be in flight at once)
-            int n = 0;
-            uint32_t mw0 = 0, mw1 = 0, aw0 = 0, aw1 = 0;
-            for (int s0 = 0; s0 * 64 < N; s0 += 4) {
-              // four rows of 64 sites: all loads first (clamped to the last
-              // site, whose bits past N are dropped below), then the ballots
-              uint32_t va[4], vb[4];
+          }
+          n = group_sum(n, lpm);
+          const bool twoa = live && (flags & kFlag2a) && 2 * n > N;
+          // step 2a: reverse the second replica (the q-mask complements); the
+          // cluster and frontier start empty
 #pragma unroll
-              for (int u = 0; u < 4; ++u) {
-                const int i = min((s0 + u) * 64 + lane, N - 1);
-                va[u] = rowa[i];
-                vb[u] = rowb[i];
-              }
-#pragma unroll
-              for (int u = 0; u < 4; ++u) {
-                const int s2 = s0 + u;
-                if (s2 * 64 >= N) break;
-                const bool in = s2 * 64 + lane < N;
-                const uint32_t ab = in ? bit_of(va[u], pa) : 0u;
-                const uint32_t qb = in ? (ab ^ bit_of(vb[u], pb) ^ gx) : 0u;
-                const unsigned long long bq = __ballot(qb), ba = __ballot(ab);
-                n += __popcll(bq);
-                // words 2 s2 and 2 s2 + 1 go to lanes w0 and w0 + 1
-                const int w0 = (2 * s2) & 63;
-                const bool lo = lane == w0, hi = lane == w0 + 1;
-                if (2 * s2 < 64) {
-                  mw0 = lo ? (uint32_t)bq : (hi ? (uint32_t)(bq >> 32) : mw0);
-                  aw0 = lo ? (uint32_t)ba : (hi ? (uint32_t)(ba >> 32) : aw0);
-                } else {
-                  mw1 = lo ? (uint32_t)bq : (hi ? (uint32_t)(bq >> 32) : mw1);
-                  aw1 = lo ? (uint32_t)ba : (hi ? (uint32_t)(ba >> 32) : aw1);
-                }
-              }
-            }
-            n = uniform(n);
-            const bool twoa = (flags & kFlag2a) && 2 * n > N;
-            // step 2a: reverse the second replica (the q-mask complements);
-            // the cluster and frontier start empty.  Lane l's mask words
-            // (l and l + 64) stay in registers for the seed search.
-#pragma unroll
-            for (int k2 = 0; k2 < 2; ++k2) {
-              const int w = lane + 64 * k2;
-              uint32_t mword = k2 ? mw1 : mw0;
+          for (int k2 = 0; k2 < 2; ++k2) {
+            const int w = li + lpm * k2;
+            if (w < nw) {
               if (twoa) {
                 const int rem_bits = N - 32 * w;
-                const uint32_t valid = rem_bits >= 32 ? ~0u : (rem_bits > 0 ? (1u << rem_bits) - 1u : 0u);
-                mword = ~mword & valid;
+                const uint32_t valid = rem_bits >= 32 ? ~0u : (1u << rem_bits) - 1u;
+                mw[k2] = ~mw[k2] & valid;
               }
-              if (k2) mw1 = mword; else mw0 = mword;
-              if (w < nw) {
-                mc[2 * w] = mword;
-                mc[2 * w + 1] = 0;
-                aw[w] = k2 ? aw1 : aw0;
-                f0[w] = 0;
-              }
+              gmc[2 * w] = mw[k2];
+              gmc[2 * w + 1] = 0;
+              gaw[w] = av[k2];
+              gsl[1 + w] = 0;
             }
-            if (twoa) n = N - n;
-            int seedsite = -1;
-            if (n > 0) {
-              // step 2b: the idx-th q = -1 site in ascending order seeds the
-              // cluster, found from a wave prefix of the words' popcounts
-              const uint32_t um = (uint32_t)__builtin_amdgcn_readlane((int)lu, g);
-              int rem = (int)(((unsigned long long)um * (unsigned long long)n) >> 32);
-              for (int k2 = 0; 64 * k2 < nw; ++k2) {
-                const uint32_t word = lane + 64 * k2 < nw ? (k2 ? mw1 : mw0) : 0u;
-                const int c = __popc(word);
-                const int excl = wave_exclusive_scan(c);
-                const int tot = __builtin_amdgcn_readlane(excl + c, 63);
-                if (rem < tot) {
-                  const bool mine = rem >= excl && rem < excl + c;
-                  // position of the (rem - excl)-th set bit of the word, by halving
-                  int pos = 0;
-                  {
-                    int kk = rem - excl;
-                    uint32_t x = word;
+          }
+          if (twoa) n = N - n;
+          if (li == 0) {
+            if (twoa) gauge[b] ^= 1;
+            ginfo[kInMv] = live ? mv : -1;
+            ginfo[kInA] = a;
+            ginfo[kInB] = b;
+            ginfo[kInN] = live ? n : 0;
+            ginfo[kInSeed] = -1;
+            if (live) {
+              atomicAdd(&stats[kStatIcmMoves], 1ull);
+              if (twoa) atomicAdd(&stats[kStat2a], 1ull);
+              if (n > 0) atomicAdd(&stats[kStatIcmNontrivial], 1ull);
+            }
+          }
+          // step 2b: the idx-th q = -1 site in ascending order seeds the
+          // cluster, found from a group prefix of the words' popcounts; the
+          // lane holding that word marks it (frontier, cluster, the seed)
+          {
+            int rem = (live && n > 0) ? (int)(((unsigned long long)um * (unsigned long long)n) >> 32) : -1;
 #pragma unroll
-                    for (int h = 16; h >= 1; h >>= 1) {
-                      const int ch = __popc(x & ((1u << h) - 1u));
-                      const bool up = kk >= ch;
-                      kk = up ? kk - ch : kk;
-                      x = up ? x >> h : x;
-                      pos = up ? pos + h : pos;
-                    }
+            for (int k2 = 0; k2 < 2; ++k2) {
+              if (lpm * k2 >= nw) break;
+              const int w = li + lpm * k2;
+              const uint32_t word = w < nw ? mw[k2] : 0u;
+              const int c = __popc(word);
+              const int excl = group_exclusive_scan(c, lpm);
+              const int tot = group_sum(c, lpm);
+              if (rem >= 0 && rem < tot) {
+                if (rem >= excl && rem < excl + c) {
+                  // position of the (rem - excl)-th set bit of the word, by halving
+                  int kk = rem - excl, pos = 0;
+                  uint32_t x = word;
+#pragma unroll
+                  for (int h = 16; h >= 1; h >>= 1) {
+                    const int ch = __popc(x & ((1u << h) - 1u));
+                    const bool up = kk >= ch;
+                    kk = up ? kk - ch : kk;
+                    x = up ? x >> h : x;
+                    pos = up ? pos + h : pos;
                   }
-                  const int src = (int)__builtin_ctzll(__ballot(mine));
-                  seedsite = 32 * (64 * k2 + src) + __builtin_amdgcn_readlane(pos, src);
-                  break;
+                  const int seedsite = 32 * w + pos;
+                  gsl[1 + w] = 1u << pos;
+                  gmc[2 * w + 1] = 1u << pos;
+                  ginfo[kInSeed] = seedsite;
                 }
+                rem = -1;
+              } else if (rem >= 0) {
                 rem -= tot;
               }
-              // the same wave stored the words above, so these land after them
-              if (lane == 0) {
-                f0[seedsite >> 5] = 1u << (seedsite & 31);
-                mc[2 * (seedsite >> 5) + 1] = 1u << (seedsite & 31);
-                info[kInSeed] = seedsite;
-              }
             }
-            if (record) {
-              wave_sync();
-              // full labelling for the readout: union-find over the q = -1
-              // subgraph, roots hooked towards the smaller index, path compression
+          }
+          wave_sync();
+          if (record) {
+            // full labelling for the readout, one move at a time with the full
+            // wave: union-find over the q = -1 subgraph, roots hooked towards
+            // the smaller index, path compression
+            for (int g = 0; g < P; ++g) {
+              const int slot = wave * P + g;
+              uint32_t* mc = (uint32_t*)(lds + lay.slots) + slot * sw + 2 * (nw + 2);
+              const int* info = (const int*)(mc + 3 * nw);
+              const int mvr = info[kInMv];
+              if (mvr < 0) continue;
               int* parent = (int*)(lds + lay.parent) + slot * N;
-              int* lab = U.labels + (size_t)mv * N;
+              int* lab = U.labels + (size_t)mvr * N;
               const int nown = N > lane ? (N - lane + 63) >> 6 : 0;
               auto inmask = [&](int j) { return (mc[2 * (j >> 5)] >> (j & 31)) & 1u; };
               for (int s2 = 0; s2 < nown; ++s2) {
@@ -1081,22 +1140,12 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
                 lab[i] = inmask(i) ? uf_load(parent, i) : -1;
               }
               if (lane == 0) {
-                U.seeds[mv] = seedsite;
-                U.seeds[nmoves + mv] = n;
+                U.seeds[mvr] = info[kInSeed];
+                U.seeds[nmoves + mvr] = info[kInN];
               }
-            }
-            if (lane == 0) {
-              if (twoa) gauge[b] ^= 1;
-              info[kInMv] = mv;
-              info[kInA] = a;
-              info[kInB] = b;
-              info[kInN] = n;
-              atomicAdd(&stats[kStatIcmMoves], 1ull);
-              if (twoa) atomicAdd(&stats[kStat2a], 1ull);
-              if (n > 0) atomicAdd(&stats[kStatIcmNontrivial], 1ull);
+              wave_sync();
             }
           }
-          wave_sync();
           // ---- the P clusters grow together, a whole frontier per level ----
           if (cube8) {
             // one word per lane, frontier, mask and cluster kept in registers
@@ -1182,10 +1231,6 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
           int ib = 0;  // one word per lane: the lane's boundary sum fits an int
           int csize = 0;
           {
-            const int ga = ginfo[kInA], gb = ginfo[kInB];
-            uint32_t* rowa = sp + (ga >> 5) * N;
-            uint32_t* rowb = sp + (gb >> 5) * N;
-            const uint32_t fa = 1u << (ga & 31), fb = 1u << (gb & 31);
             const int jpl = JK ? 0 : U.jpl;
             const uint32_t* jplw = (const uint32_t*)(lds + lay.jplanes);
             const int jw = min(li, nw - 1);  // lanes past the last word have no bits
@@ -1204,15 +1249,6 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
                 const uint32_t anti = awd ^ ad[d];
                 ib += (!JK && jpl > 0) ? boundary_sum_planes(bb, anti, jplw + (jw * DEG + d) * jpl, jpl)
                                       : boundary_sum<JK, DEG>(bb, anti, li, d, cf, cj);
-              }
-              for (uint32_t fl = cw; fl; fl &= fl - 1u) {
-                const int i = 32 * li + __builtin_ctz(fl);
-                if (rowa == rowb) {
-                  atomicXor(&rowa[i], fa | fb);
-                } else {
-                  atomicXor(&rowa[i], fa);
-                  atomicXor(&rowb[i], fb);
-                }
               }
             }
             if (chimreg) {
@@ -1246,15 +1282,6 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
                 ib += (!JK && jpl > 0) ? boundary_sum_planes(bb, anti, jplw + (jw * DEG + d) * jpl, jpl)
                                       : boundary_sum<JK, DEG>(bb, anti, li, d, cf, cj);
               }
-              for (uint32_t fl = cw; fl; fl &= fl - 1u) {
-                const int i = 32 * li + __builtin_ctz(fl);
-                if (rowa == rowb) {
-                  atomicXor(&rowa[i], fa | fb);
-                } else {
-                  atomicXor(&rowa[i], fa);
-                  atomicXor(&rowb[i], fb);
-                }
-              }
             }
             if (latreg) {
               // slot 2a = +axis a (terms 4a, 4a+1), slot 2a+1 = -axis a (terms 4a+2, 4a+3)
@@ -1273,23 +1300,13 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
                 ib += (!JK && jpl > 0) ? boundary_sum_planes(bb, anti, jplw + (jw * DEG + d) * jpl, jpl)
                                       : boundary_sum<JK, DEG>(bb, anti, li, d, cf, cj);
               }
-              for (uint32_t fl = cw; fl; fl &= fl - 1u) {
-                const int i = 32 * li + __builtin_ctz(fl);
-                if (rowa == rowb) {
-                  atomicXor(&rowa[i], fa | fb);
-                } else {
-                  atomicXor(&rowa[i], fa);
-                  atomicXor(&rowb[i], fb);
-                }
-              }
             }
             if (pair) {
               int cs2 = 0;
               dEa = pair_boundary<JK, DEG>(sq64, (uint32_t)((unsigned char*)gmc - lds),
                                            (uint32_t)((const unsigned char*)gaw - lds),
                                            TL ? (uint32_t)((const unsigned char*)cf - lds) : 0u,
-                                           TL ? nullptr : U.coup, (uint32_t)((unsigned char*)rowa - lds),
-                                           (uint32_t)((unsigned char*)rowb - lds), fa, fb, lane, cs2);
+                                           TL ? nullptr : U.coup, lane, cs2);
               csize = cs2;
             }
             if (!cube8 && !chimreg && !latreg && !pair) {
@@ -1337,17 +1354,20 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
                     }
                   }
                 }
-                for (uint32_t fl = cw; fl; fl &= fl - 1u) {
-                  const int i = 32 * w + __builtin_ctz(fl);
-                  if (rowa == rowb) {
-                    atomicXor(&rowa[i], fa | fb);
-                  } else {
-                    atomicXor(&rowa[i], fa);
-                    atomicXor(&rowb[i], fb);
-                  }
-                }
               }
             }
+          }
+          // the flips: the cluster words into both walkers' words (walker-major view)
+          {
+            const int ga = ginfo[kInA], gb = ginfo[kInB];
+            if (ginfo[kInMv] >= 0 && ginfo[kInN] > 0)
+              for (int w = li; w < nw; w += lpm) {
+                const uint32_t cwf = gmc[2 * w + 1];
+                if (cwf) {
+                  sp[wt_index(ga, w, Np)] ^= cwf;
+                  sp[wt_index(gb, w, Np)] ^= cwf;
+                }
+              }
           }
           dEa += (E_t)ib;
           // per-group sums: DPP row sums are 16-lane sums, groups are 1, 2 or 4 rows
@@ -1385,6 +1405,8 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
           wave_sync();
         }
       }
+      __syncthreads();
+      transpose_image(sp, G, nw, false);
     }
     __syncthreads();
 
@@ -1437,7 +1459,7 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
   __syncthreads();
   for (int x = tid; x < Wq * N; x += nthr) {
     const int q = x / N, i = x - q * N;
-    const uint32_t nib = (sp[(q >> 3) * N + i] >> (4 * (q & 7))) & 0xFu;
+    const uint32_t nib = (sp[(q >> 3) * Np + i] >> (4 * (q & 7))) & 0xFu;
     uint32_t w = 0;
 #pragma unroll
     for (int b = 0; b < 4; ++b) w |= (((nib >> b) & 1u) ? 0xFFu : 0x01u) << (8 * b);
