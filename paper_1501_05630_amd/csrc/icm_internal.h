@@ -71,7 +71,7 @@ ICM_HD uint32_t align16(uint32_t x) { return (x + 15u) & ~15u; }
 // walker-major view by 32 x 32 blocks.
 struct LdsLayout {
   uint32_t sp, nbr, clist, coup, tau, at, gauge, energy, thr, beta, bl2e, dbl2e, ptu, icmu, terms, jplanes,
-      slots, parent, meas, stats, total;
+      slots, parent, meas, exq, stats, total;
 };
 
 // Neighbour relation of the lattice as bit shifts of a site bitset (for the
@@ -109,13 +109,20 @@ ICM_HD int coupling_planes(int jkind, int Kc, int N, int jmin, int jmax) {
   return p;
 }
 
+// Float couplings: Metropolis decisions the float estimate cannot make are
+// queued per wave (site | quad-pair index << 16, the estimate's flip bits) and
+// made exactly at the end of the colour; a wave's queue holds kExactQ tasks
+// and is emptied early when a task could fill it.
+constexpr int kExactQ = 96;
+ICM_HD int exact_queue_words(int jkind, int waves) { return jkind ? waves * (2 + 2 * kExactQ) : 0; }
+
 // tables = 1: neighbour table, colour lists and couplings are copied into LDS;
 // tables = 0: they are read from global memory (for units too large otherwise).
 // jpl: bit planes of the int8 couplings kept for the cluster moves' boundary
 // sums (word [(w deg + d) jpl + k] = bit k of J over the 32 sites of word w,
 // slot d), 0 for none.
 ICM_HD LdsLayout lds_layout(int N, int deg, int Wq, int K, int R, int HM, int jkind, int slots,
-                            int tables, int extras, int Kc, int jpl) {
+                            int tables, int extras, int Kc, int jpl, int waves) {
   // extras: bit 0 = ICM labels recorded, bit 1 = observables measured
   const int record = extras & 1, measure = extras & 2;
   LdsLayout L{};
@@ -142,6 +149,7 @@ ICM_HD LdsLayout lds_layout(int N, int deg, int Wq, int K, int R, int HM, int jk
   L.slots = o;   o = align16(o + 4u * slot_words(N) * ns);
   L.parent = o;  o = align16(o + (record ? 4u * N * ns : 0u));
   L.meas = o;    o = align16(o + (measure ? 4u * site_words(N) * 16u : 0u));  // q-mask words per wave
+  L.exq = o;     o = align16(o + 4u * (uint32_t)exact_queue_words(jkind, waves));
   L.stats = o;   o = align16(o + 8u * kNumStats);
   L.total = o;
   return L;

@@ -241,6 +241,13 @@ __device__ __forceinline__ int mad_i24(int a, int b, int acc) {
   return r;
 }
 
+// |a - b| for unsigned a, b (one v_sad_u32)
+__device__ __forceinline__ uint32_t absdiff(uint32_t a, uint32_t b) {
+  uint32_t r;
+  asm("v_sad_u32 %0, %1, %2, 0" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+
 // Spin (+1/-1) of byte b of an int8 quad word.
 __device__ __forceinline__ int spin_of(uint32_t word, int b) {
   return (int)(int8_t)(uint8_t)(word >> (8 * b));
@@ -690,6 +697,90 @@ __device__ __noinline__ void measure_step(uint32_t t_end, int N, int K, int R, i
 }
 
 // ----------------------------------------------------------------------------
+// The exact pass of a Metropolis colour (float couplings): for each queued
+// task (site i, the quad pair qt, the estimate's flip bits) every walker
+// whose float call was too close is decided again in double as
+// u 2^-32 < exp(-beta dE); where that differs from the estimate, the spin is
+// flipped back or forth, and the energy and the accepted-flip count are
+// corrected.  The task's other inputs are recomputed as the sweep made them
+// (the neighbours have the other colour, so they have not moved; the site's
+// own bits are restored from the estimate's flips).  One lane per queued
+// task; empties the wave's queue.  Out of line, so that the sweep loop keeps
+// no registers for it.
+// ----------------------------------------------------------------------------
+template <int DEG, int QPT>
+__device__ __noinline__ void exact_pass(uint32_t q_off, uint32_t sp_off, int Np, uint32_t nbr_off,
+                                        const uint16_t* nbr_global, uint32_t coup_off, const int32_t* coup_global,
+                                        uint32_t tau_off, uint32_t beta_off, uint32_t bl2e_off, uint32_t energy_off,
+                                        uint32_t stats_off, int W, int Wq, int jexp, uint32_t t, uint32_t seed,
+                                        uint32_t key) {
+  constexpr int WPT = 4 * QPT;
+  uint32_t* q = (uint32_t*)(lds + uniform((int)q_off));
+  uint32_t* sp = (uint32_t*)(lds + uniform((int)sp_off));
+  const uint16_t* nbr = nbr_global ? nbr_global : (const uint16_t*)(lds + uniform((int)nbr_off));
+  const int32_t* cf = coup_global ? coup_global : (const int32_t*)(lds + uniform((int)coup_off));
+  const int* tau = (const int*)(lds + uniform((int)tau_off));
+  const double* beta = (const double*)(lds + uniform((int)beta_off));
+  const float* bl2e = (const float*)(lds + uniform((int)bl2e_off));
+  double* energy = (double*)(lds + uniform((int)energy_off));
+  unsigned long long* stats = (unsigned long long*)(lds + uniform((int)stats_off));
+  Np = uniform(Np); W = uniform(W); Wq = uniform(Wq); jexp = uniform(jexp);
+  t = (uint32_t)uniform((int)t); seed = (uint32_t)uniform((int)seed); key = (uint32_t)uniform((int)key);
+  const int lane = lane_id();
+  const int n = uniform((int)__hip_atomic_load(&q[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT));
+  const double jq2 = ldexp(1.0, 1 - jexp);
+  for (int x0 = 0; x0 < n; x0 += 64) {
+    const int x = x0 + lane;
+    if (x >= n) continue;
+    const uint32_t w0 = q[2 + 2 * x], guess = q[3 + 2 * x];
+    const int i = (int)(w0 & 0xFFFFu), qt = (int)(w0 >> 16);
+    const int q0 = QPT * qt, g = q0 >> 3, sh = 4 * (q0 & 7);
+    uint32_t* row = sp + g * Np;
+    const uint32_t own = row[i] ^ (guess << sh);
+    uint32_t xw[DEG];
+    int Ji[DEG], Jsum = 0;
+#pragma unroll
+    for (int d = 0; d < DEG; ++d) {
+      xw[d] = row[nbr[i * DEG + d]] ^ own;
+      Ji[d] = cf[i * DEG + d];
+      Jsum += Ji[d];
+    }
+    Words4 u[QPT];
+#pragma unroll
+    for (int h = 0; h < QPT; ++h)
+      if (h == 0 || q0 + h < Wq) u[h] = philox4x32_10((uint32_t)i, t, (uint32_t)(q0 + h), kStreamMetro, seed, key);
+      else u[h] = u[0];
+    uint32_t corr = 0;
+    int dcnt = 0;
+#pragma unroll
+    for (int b = 0; b < WPT; ++b) {
+      const int w = WPT * qt + b;
+      if (w >= W) continue;
+      int mn = 0;
+#pragma unroll
+      for (int d = 0; d < DEG; ++d) mn = mad_i24(__builtin_amdgcn_sbfe((int)xw[d], (unsigned)(sh + b), 1u), Ji[d], mn);
+      const int e = Jsum + 2 * mn;
+      const uint32_t uu = u[b >> 2].w[b & 3];
+      const int k = tau[w];
+      const float lqb = ldexpf(bl2e[k], 1 - jexp);
+      const float P = __builtin_amdgcn_exp2f(__builtin_fmaf(-(float)e, lqb, 32.0f));
+      if (absdiff(__float_as_uint((float)uu), __float_as_uint(P)) >= 4096u) continue;
+      const bool ex = e <= 0 || accept_exact(uu, (double)e * jq2, beta[k]);
+      if (ex != (((guess >> b) & 1u) != 0u)) {
+        corr |= 1u << b;
+        atomicAdd(&energy[w], ldexp((double)(ex ? e : -e), 1 - jexp));
+        dcnt += ex ? 1 : -1;
+      }
+    }
+    if (corr) atomicXor(&row[i], corr << sh);
+    if (dcnt) atomicAdd(&stats[kStatMetroAcc], (unsigned long long)(long long)dcnt);
+  }
+  wave_sync();
+  if (lane == 0) q[0] = 0;
+  wave_sync();
+}
+
+// ----------------------------------------------------------------------------
 // The fused sweep-block kernel.  JK: 0 = int8 couplings, 1 = float couplings.
 // DEG: neighbour slots (4 for square2d, 6 otherwise).  One workgroup runs one
 // unit; its spins live bit-packed in LDS for the whole block of sweeps.
@@ -704,7 +795,7 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
   const int Wp = 4 * Wq, G = bit_words(Wq);
   const LdsLayout lay = lds_layout(N, DEG, Wq, K, R, HM, JK, icm_slots, TL,
                                    ((U.flags & kFlagRecord) ? 1 : 0) | ((U.flags & kFlagMeasure) ? 2 : 0), Kc,
-                                   JK ? 0 : U.jpl);
+                                   JK ? 0 : U.jpl, (int)(blockDim.x >> 6));
 
   uint32_t* sp = (uint32_t*)(lds + lay.sp);
   // TL: tables in LDS; otherwise read-only global memory (cached in L1/L2)
@@ -770,6 +861,8 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
     dbl2e[x] = x + 1 < K ? (float)((U.beta[x] - U.beta[x + 1]) * 1.4426950408889634) : 0.0f;
   }
   for (int x = tid; x < kNumStats; x += nthr) stats[x] = 0;
+  if (JK)
+    for (int x = tid; x < (int)(nthr >> 6); x += nthr) ((uint32_t*)(lds + lay.exq))[x * (2 + 2 * kExactQ)] = 0;
   if (Kc > 0) {
     // shift program of the lattice and zeroed frontier padding of every slot
     const int nw = site_words(N), nterm = lattice_terms(U.topo);
@@ -844,13 +937,24 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
         const int te = (int)(((long long)ntasks * (wave + 1)) / nwaves);
         int cur_q = -1;
         int acc[WPT];  // per lane: sum of e over its accepted flips (dE = 2 e in field units)
-        int tq[WPT], rowb[WPT];
-        double bq[WPT];
+        // per walker of the current task's quads (uniform): float couplings
+        // the acceptance exponent's scale, integer couplings the threshold row;
+        // vmask: the walkers that exist (the last quad may be padding)
         float lq[WPT];
+        int rowb[WPT];
+        uint32_t vmask = 0;
 #pragma unroll
-        for (int b = 0; b < WPT; ++b) { acc[b] = 0; tq[b] = K; rowb[b] = 0; bq[b] = 0.0; lq[b] = 0.0f; }
+        for (int b = 0; b < WPT; ++b) { acc[b] = 0; rowb[b] = 0; lq[b] = 0.0f; }
         int qt = tb / nchunk, chunk = tb - qt * nchunk;
+        uint32_t* exq = (uint32_t*)(lds + lay.exq) + wave * (2 + 2 * kExactQ);
         for (int task = tb; task < te; ++task, (++chunk == nchunk ? (chunk = 0, ++qt) : 0)) {
+          // the queue holds room for every lane of the next task
+          if constexpr (JK) {
+            if (uniform((int)__hip_atomic_load(&exq[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT)) > kExactQ - 64)
+              exact_pass<DEG, QPT>(lay.exq + 4u * (uint32_t)wave * (2 + 2 * kExactQ), lay.sp, Np, lay.nbr,
+                                TL ? nullptr : U.nbr, lay.coup, TL ? nullptr : (const int32_t*)U.coup, lay.tau,
+                                lay.beta, lay.bl2e, lay.energy, lay.stats, W, Wq, U.jexp, t, seed, key);
+          }
           if (qt != cur_q) {
             if (cur_q >= 0) {
               flush_energy<JK, WPT>(acc, energy + WPT * cur_q, U.jexp);
@@ -858,16 +962,14 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
               for (int b = 0; b < WPT; ++b) acc[b] = 0;
             }
             cur_q = qt;
+            vmask = 0;
 #pragma unroll
             for (int b = 0; b < WPT; ++b) {
-              tq[b] = uniform(WPT * qt + b < W ? tau[WPT * qt + b] : K);
-              if (tq[b] < K) {
-                if (JK) {
-                  bq[b] = uniform_d(beta[tq[b]]);
-                  lq[b] = ldexpf(__int_as_float(uniform(__float_as_int(bl2e[tq[b]]))), 1 - U.jexp);
-                } else {
-                  rowb[b] = tq[b] * HM;
-                }
+              const int tb2 = uniform(WPT * qt + b < W ? tau[WPT * qt + b] : K);
+              if (tb2 < K) {
+                vmask |= 1u << b;
+                if (JK) lq[b] = ldexpf(__int_as_float(uniform(__float_as_int(bl2e[tb2]))), 1 - U.jexp);
+                else rowb[b] = tb2 * HM;
               }
             }
           }
@@ -887,59 +989,65 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
             for (int h = 0; h < QPT; ++h)
               if (h == 0 || q0 + h < Wq) u[h] = philox4x32_10((uint32_t)i, t, (uint32_t)(q0 + h), kStreamMetro, seed, key);
               else u[h] = u[0];
-            uint32_t flip = 0;
-            if (JK) {
-              // e = s_i h = sum_d J_d s_i s_d = sum J - 2 sum_d J_d x_d, x_d = 1 where
-              // the spin and its d-neighbour differ (own word xor neighbour word,
-              // once for all walkers of the task); exact in units of 2^-jexp
-              const double jq2 = ldexp(1.0, 1 - U.jexp);
-              int Ji[DEG];
-              int Jsum = 0;
-              uint32_t xw[DEG];
+            // e = s_i h = sum_d J_d s_i s_d = sum J - 2 sum_d J_d x_d, x_d = 1 where
+            // the spin and its d-neighbour differ (own word xor neighbour word,
+            // once for all walkers of the task): the bit extracted sign-extended
+            // (0 or -1) times J_d, 24-bit integers (float couplings in units of
+            // 2^-jexp), dE = 2 e
+            int Ji[DEG];
+            int Jsum = 0;
+            uint32_t xw[DEG];
 #pragma unroll
-              for (int d = 0; d < DEG; ++d) {
-                Ji[d] = cf[i * DEG + d];
-                Jsum += Ji[d];
-                xw[d] = nw[d] ^ own;
-              }
+            for (int d = 0; d < DEG; ++d) {
+              Ji[d] = JK ? cf[i * DEG + d] : (int)cj[i * DEG + d];
+              Jsum += Ji[d];
+              xw[d] = nw[d] ^ own;
+            }
+            uint32_t flip = 0;
+            if constexpr (JK) {
+              // every walker decided by the float estimate P of 2^32 exp(-beta dE)
+              // (accept iff float(u) < P), no branch; `close` keeps the nearest
+              // call of the task in float bit patterns (units in the last
+              // place).  4096 of them are a relative gap above 2^-12, far wider
+              // than the estimate's error (below 2^-17), so any call that close
+              // is made again exactly, in double, as the oracle does: the task
+              // is queued (rare) and exact_pass redoes those calls before the
+              // colour ends (same-colour sites do not interact, so a decision
+              // may wait until then).
+              uint32_t close = 0xFFFFFFFFu;
 #pragma unroll
               for (int b = 0; b < WPT; ++b) {
-                if (tq[b] >= K) continue;
-                // the bit extracted sign-extended (0 or -1) times J_d (24-bit
-                // integers): mn = -sum_d J_d x_d
                 int mn = 0;
 #pragma unroll
                 for (int d = 0; d < DEG; ++d)
                   mn = mad_i24(__builtin_amdgcn_sbfe((int)xw[d], (unsigned)(sh + b), 1u), Ji[d], mn);
                 const int e = Jsum + 2 * mn;  // dE = e 2^(1 - jexp)
-                if (accept_int_field(u[b >> 2].w[b & 3], e, bq[b], lq[b], jq2)) {
-                  flip |= 1u << b;
-                  acc[b] += e;
-                }
+                const float P = __builtin_amdgcn_exp2f(__builtin_fmaf(-(float)e, lq[b], 32.0f));
+                const float uf = (float)u[b >> 2].w[b & 3];
+                const bool ok = ((vmask >> b) & 1u) && uf < P;
+                close = min(close, absdiff(__float_as_uint(uf), __float_as_uint(P)));
+                flip |= ok ? (1u << b) : 0u;
+                acc[b] += ok ? e : 0;
+              }
+              if (close < 4096u) {
+                // queue the task for the exact pass at the end of the colour
+                const uint32_t pos = atomicAdd(&exq[0], 1u);
+                exq[2 + 2 * pos] = (uint32_t)i | ((uint32_t)qt << 16);
+                exq[3 + 2 * pos] = flip;
               }
             } else {
-              // e = s_i h = sum J - 2 sum_d J_d x_d as for float couplings
-              int Ji[DEG];
-              int Jsum = 0;
-              uint32_t xw[DEG];
-#pragma unroll
-              for (int d = 0; d < DEG; ++d) {
-                Ji[d] = cj[i * DEG + d];
-                Jsum += Ji[d];
-                xw[d] = nw[d] ^ own;
-              }
 #pragma unroll
               for (int b = 0; b < WPT; ++b) {
-                if (tq[b] >= K) continue;
                 int mn = 0;
 #pragma unroll
                 for (int d = 0; d < DEG; ++d)
                   mn = mad_i24(__builtin_amdgcn_sbfe((int)xw[d], (unsigned)(sh + b), 1u), Ji[d], mn);
                 const int e = Jsum + 2 * mn;  // dE = 2e
-                if (e <= 0 || u[b >> 2].w[b & 3] < thr[rowb[b] + e]) {
-                  flip |= 1u << b;
-                  acc[b] += e;
-                }
+                // e <= 0 is always accepted; else u below the threshold of (T, e)
+                const uint32_t th = thr[rowb[b] + (e > 0 ? e : 0)];
+                const bool ok = ((vmask >> b) & 1u) && (e <= 0 || u[b >> 2].w[b & 3] < th);
+                flip |= ok ? (1u << b) : 0u;
+                acc[b] += ok ? e : 0;
               }
             }
             if (flip) atomicXor(&row[i], flip << sh);
@@ -947,6 +1055,12 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
           }
         }
         if (cur_q >= 0) flush_energy<JK, WPT>(acc, energy + WPT * cur_q, U.jexp);
+        if constexpr (JK) {
+          if (uniform((int)__hip_atomic_load(&exq[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT)) > 0)
+            exact_pass<DEG, QPT>(lay.exq + 4u * (uint32_t)wave * (2 + 2 * kExactQ), lay.sp, Np, lay.nbr,
+                                TL ? nullptr : U.nbr, lay.coup, TL ? nullptr : (const int32_t*)U.coup, lay.tau,
+                                lay.beta, lay.bl2e, lay.energy, lay.stats, W, Wq, U.jexp, t, seed, key);
+        }
         __syncthreads();
       }
       {

@@ -237,10 +237,10 @@ struct Instance {
   // device regions
   std::vector<void*> blocks;  // everything this instance owns in the arena
   UnitDesc unit{};
-  size_t lds_bytes_at(int slots, int tables) const {
+  size_t lds_bytes_at(int slots, int tables, int threads) const {
     return icm::lds_layout(N, deg, Wq, K, R, HM, jkind, slots, tables,
                            ((flags & ICM_FLAG_RECORD_LABELS) ? 1 : 0) | ((flags & ICM_FLAG_MEASURE) ? 2 : 0),
-                           Kc, jpl).total;
+                           Kc, jpl, threads / 64).total;
   }
 };
 
@@ -737,7 +737,7 @@ int effective_slots(icm_ctx* c, const std::vector<int32_t>& hs, int threads, int
   for (tables = first; tables >= last; --tables) {
     for (int slots = top; slots >= 1; --slots) {
       lds = 0;
-      for (int32_t h : hs) lds = std::max(lds, find(c, h)->lds_bytes_at(slots, tables));
+      for (int32_t h : hs) lds = std::max(lds, find(c, h)->lds_bytes_at(slots, tables, threads));
       if (lds <= c->lds_limit) return slots;
       if (tables && slots <= std::min(top, 4)) break;  // prefer global tables over < 4 slots
     }
