@@ -51,7 +51,7 @@ def parse():
                     help="keep the launch shape of the flags instead of autotuning it")
     ap.add_argument("--tune-cache", default="", help="autotuner cache file (default: search every run)")
     ap.add_argument("--per-instance-sample", type=int, default=32)
-    ap.add_argument("--served-requests", type=int, default=160,
+    ap.add_argument("--served-requests", type=int, default=240,
                     help="requests of the short served run in the default line (0: none)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -106,7 +106,11 @@ def launch_tag(cfg):
 # 256 MiB device copy, and SQ_INSTS_VALU (wave instructions).  Valid only for
 # the kernel source (digest) and launch shape they were measured on; the line
 # reports null otherwise.
-PROFILED = {}
+PROFILED = {
+    "3d_L8_gauss_1024inst": {"kernel": "2a705bfdf770942e", "launch": "t256_s16_spl256",
+                             "hbm_bytes_per_launch": 202178987, "valu_insts_per_launch": 1.1367e10,
+                             "profile": "profiles/sweep_block_kernel_3d_L8_gauss_1024inst.md"},
+}
 
 
 def profiled(name, cfg):
@@ -755,7 +759,7 @@ def main():
     ctx.close()
     if args.served_requests:
         out["served"] = serve_mix(args.served_requests, args.serve_sweeps, args.serve_block, args.serve_load,
-                                  args.arena_mib, n_sat=max(8, args.served_requests // 3), per_instance=12)
+                                  args.arena_mib, n_sat=args.served_requests, per_instance=12)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(name, spec, args.cpu_seconds)
     print(json.dumps(out), flush=True)
