@@ -1526,29 +1526,55 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
 
     // ---------------- step 3: parallel tempering ---------------------------------
     if (flags & kFlagPt) {
+      // Lane r scans chain r up the ladder.  Rung k only ever meets the walker
+      // carried up from rung k - 1 (or the one that sat at k) and the walker
+      // still sitting at k + 1, so the carried walker and its energy stay in
+      // registers, rung k is final once decided, and the next rung's walker,
+      // energy and draw are read ahead: no LDS round trip on the chain.
       if (wave == 0) {
         const int r = lane;
         int acc_pt = 0;
-        for (int k = 0; r < R && k + 1 < K; ++k) {
-          const int x = at[k * R + r], y = at[(k + 1) * R + r];
-          bool accept;
-          const uint32_t u = ptu[k * R + r];
-          if (JK) {
-            // u 2^-32 < exp(-(beta_k - beta_k+1) D) in double, after the float
-            // pre-filter that settles all but a thin band (as for Metropolis)
-            const double D = (double)energy[y] - (double)energy[x];
-            accept = accept_float(u, D, beta[k] - beta[k + 1], dbl2e[k]);
-          } else {
-            const int D = (int)energy[y] - (int)energy[x];
-            accept = D <= 0 || (D <= U.ptlen && u < U.ptthr[k * U.ptlen + (D - 1)]);
+        if (r < R && K > 1) {
+          // two rungs of read-ahead: the walker at k + 3 and the energy of the
+          // walker at k + 2 are fetched while rung k is decided
+          int x = at[r];
+          E_t ex = energy[x];
+          int yn = at[R + r];
+          E_t eyn = energy[yn];
+          uint32_t un = ptu[r];
+          int ynn = K > 2 ? at[2 * R + r] : 0;
+          for (int k = 0; k + 1 < K; ++k) {
+            const int y = yn;
+            const E_t ey = eyn;
+            const uint32_t u = un;
+            if (k + 2 < K) {
+              yn = ynn;
+              eyn = energy[ynn];
+              un = ptu[(k + 1) * R + r];
+              if (k + 3 < K) ynn = at[(k + 3) * R + r];
+            }
+            bool accept;
+            if (JK) {
+              // u 2^-32 < exp(-(beta_k - beta_k+1) D) in double, after the float
+              // pre-filter that settles all but a thin band (as for Metropolis)
+              const double D = (double)ey - (double)ex;
+              accept = accept_float(u, D, beta[k] - beta[k + 1], dbl2e[k]);
+            } else {
+              const int D = (int)ey - (int)ex;
+              accept = D <= 0 || (D <= U.ptlen && u < U.ptthr[k * U.ptlen + (D - 1)]);
+            }
+            // rung k keeps y on a swap (x climbs on), else x (and y is carried)
+            const int stay = accept ? y : x;
+            at[k * R + r] = stay;
+            tau[stay] = k;
+            if (!accept) {
+              x = y;
+              ex = ey;
+            }
+            acc_pt += accept ? 1 : 0;
           }
-          if (accept) {
-            at[k * R + r] = y;
-            at[(k + 1) * R + r] = x;
-            tau[x] = k + 1;
-            tau[y] = k;
-            ++acc_pt;
-          }
+          at[(K - 1) * R + r] = x;
+          tau[x] = K - 1;
         }
         const int tot = wave_sum(acc_pt);
         if (lane == 0) {

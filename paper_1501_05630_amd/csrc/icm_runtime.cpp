@@ -266,7 +266,7 @@ struct icm_ctx {
   size_t lds_limit = 65536;
   int n_cus = 256;
   size_t lds_cu = 0;                 // LDS bytes per compute unit
-  icm_run_config cfg{512, 256, 0, 32, 0};
+  icm_run_config cfg{0, 256, 0, 32, 0};
   // unit tables cached per (handle list)
   std::map<std::vector<int32_t>, UnitDesc*> unit_tables;
   // captured graphs per (handle list, sweeps per launch, launches)
@@ -702,13 +702,14 @@ struct Group {
 };
 
 // Size classes of units (sites): up to 512, 1024, 2048, more.  Units of one
-// class share a launch (its LDS size is the largest member's), and larger
-// classes get more threads per workgroup.
+// class share a launch (its LDS size is the largest member's).  threads = 0
+// (automatic): 256 threads per workgroup up to 512 sites, 512 up to 1024,
+// 1024 above; otherwise the configured count for every class.
 int size_class(int N) { return N <= 512 ? 0 : (N <= 1024 ? 1 : (N <= 2048 ? 2 : 3)); }
 
 int class_threads(int threads, int cls) {
-  const int floor_t = cls == 0 ? 0 : (cls == 1 ? 512 : 1024);
-  return std::max(threads, floor_t);
+  if (threads > 0) return threads;
+  return cls == 0 ? 256 : (cls == 1 ? 512 : 1024);
 }
 
 std::vector<Group> group_handles(icm_ctx* c, const int32_t* handles, int n) {
@@ -730,8 +731,10 @@ std::vector<Group> group_handles(icm_ctx* c, const int32_t* handles, int n) {
 // else fewer slots, else tables in global memory.
 int effective_slots(icm_ctx* c, const std::vector<int32_t>& hs, int threads, int want, size_t& lds,
                     int& tables) {
-  // a wave carries at most four moves
-  const int top = std::max(1, std::min(want, 4 * (threads / 64)));
+  // no more slots than the waves can carry: 64 / lanes-per-move moves each
+  int per_wave = 4;
+  for (int32_t h : hs) per_wave = std::min(per_wave, 64 / icm::icm_lanes_per_move(find(c, h)->N));
+  const int top = std::max(1, std::min(want, per_wave * (threads / 64)));
   const int first = c->cfg.table_placement == 2 ? 0 : 1;
   const int last = c->cfg.table_placement == 1 ? 1 : 0;
   for (tables = first; tables >= last; --tables) {
@@ -1148,9 +1151,9 @@ int icm_set_run_config(icm_ctx* c, const icm_run_config* cfg) {
   if (!cfg) return fail(c, ICM_E_INVALID, "null config");
   icm_run_config n = c->cfg;
   if (cfg->threads) {
-    if (cfg->threads != 256 && cfg->threads != 512 && cfg->threads != 1024)
-      return fail(c, ICM_E_INVALID, "threads must be 256, 512 or 1024");
-    n.threads = cfg->threads;
+    if (cfg->threads != 256 && cfg->threads != 512 && cfg->threads != 1024 && cfg->threads != -1)
+      return fail(c, ICM_E_INVALID, "threads must be 256, 512, 1024, or -1 for the per-class default");
+    n.threads = cfg->threads < 0 ? 0 : cfg->threads;
   }
   if (cfg->sweeps_per_launch < 0) return fail(c, ICM_E_INVALID, "negative sweeps_per_launch");
   if (cfg->sweeps_per_launch) n.sweeps_per_launch = cfg->sweeps_per_launch;

@@ -118,11 +118,12 @@ def coupling_kind(couplings):
 
 def launch_threads(n_sites, threads):
     """Threads per workgroup that icm_run launches for units of n_sites sites
-    when icm_run_config.threads is `threads`: size classes above 512, 1024 and
-    2048 sites take at least 512, 1024 and 1024 threads (the rule the header
-    states for icm_run_config.threads)."""
-    floor = 0 if n_sites <= 512 else (512 if n_sites <= 1024 else 1024)
-    return max(int(threads), floor)
+    when icm_run_config.threads is `threads` (the rule the header states): the
+    configured count for every size class, or for 0 / -1 the per-class
+    default, 256 up to 512 sites, 512 up to 1024, 1024 above."""
+    if threads > 0:
+        return int(threads)
+    return 256 if n_sites <= 512 else (512 if n_sites <= 1024 else 1024)
 
 
 def make_desc(topology, L, couplings, temps, n_replicas, icm_ntemps,

@@ -63,14 +63,17 @@ def test_profiled_counters_apply_only_to_their_kernel_and_shape():
         bench.PROFILED.update(saved)
 
 
-def test_launch_threads_follows_the_size_classes():
-    # icm_run_config.threads applies to units of up to 512 sites; the classes
-    # above take at least 512 (<= 1024 sites) and 1024 threads
+def test_launch_threads_follows_the_configured_count_or_the_size_classes():
+    # an explicit icm_run_config.threads applies to every size class; 0 / -1
+    # pick per class: 256 up to 512 sites, 512 up to 1024, 1024 above
     from paper_1501_05630_amd import icm
     assert icm.launch_threads(512, 256) == 256
-    assert icm.launch_threads(513, 256) == 512
-    assert icm.launch_threads(1024, 256) == 512
-    assert icm.launch_threads(1024, 1024) == 1024
-    assert icm.launch_threads(1152, 256) == 1024
-    assert icm.launch_threads(4096, 512) == 1024
-    assert icm.launch_threads(64, 512) == 512
+    assert icm.launch_threads(1152, 256) == 256
+    assert icm.launch_threads(4096, 512) == 512
+    assert icm.launch_threads(64, 1024) == 1024
+    for auto in (0, -1):
+        assert icm.launch_threads(512, auto) == 256
+        assert icm.launch_threads(513, auto) == 512
+        assert icm.launch_threads(1024, auto) == 512
+        assert icm.launch_threads(1152, auto) == 1024
+        assert icm.launch_threads(4096, auto) == 1024

@@ -152,3 +152,38 @@ def test_other_entry_points_are_busy_while_serving():
     assert np.array_equal(ctx.icm_read_states(h), before)
     assert ctx.icm_sweep_index(h) == 5
     ctx.close()
+
+
+def test_serving_mix_at_its_largest_sizes():
+    # the serving workload's largest requests -- 2D +-J L = 64 (16 temperatures x 2
+    # replicas), 3D Gaussian L = 12 (20 x 4), chimera C = 16 (30 x 2, integer
+    # couplings) -- with a few small ones, in an arena that holds two or three
+    # at a time: each result equals the same request served alone, and one
+    # request of each large class equals the oracle's trajectory
+    rng = inputs.make_rng(83, 0)
+    big = []
+    for x, (top, L, kind, K, R, sc, tmax) in enumerate([(inputs.SQUARE2D, 64, "pmJ", 16, 2, 1, 1.6),
+                                                       (inputs.CUBIC3D, 12, "gauss", 20, 4, 1, 2.0),
+                                                       (inputs.CHIMERA, 16, "int3", 30, 2, 3, 3.0)] * 2):
+        J = gridded.make_couplings(kind, top, L, rng)
+        temps = inputs.geometric_temps(0.2, tmax, K)
+        big.append(dict(topology=top, L=L, couplings=J, temps=temps, n_replicas=R,
+                        icm_ntemps=inputs.icm_cutoff(temps), j_scale=sc, instance_key=2000 + x,
+                        flags=icm.FLAG_2A | icm.FLAG_PT))
+    reqs = big[:3] + requests(3, rng) + big[3:]
+    sweeps = 48
+    mixed, lat = serve(reqs, sweeps, arena_bytes=3 << 19, block=16, stagger_s=0.001)
+    for x in (0, 1, 2, len(reqs) - 1):
+        alone = serve([reqs[x]], sweeps, arena_bytes=64 << 20, block=16)[0][0]
+        assert np.array_equal(mixed[x][0], alone[0]), x
+        assert np.array_equal(mixed[x][1], alone[1]), x
+    for x in (0, 1, 2):
+        d = reqs[x]
+        o = orc.Sim(d["topology"], d["L"], d["couplings"], d["temps"], d["n_replicas"],
+                    d["icm_ntemps"], flags=orc.FLAG_2A | orc.FLAG_PT, seed=SEED,
+                    instance_key=d["instance_key"], j_scale=d["j_scale"])
+        o.init_hot()
+        o.run(sweeps)
+        assert np.array_equal(mixed[x][1], o.states()), x
+        assert np.array_equal(mixed[x][0], o.energies_raw()), x
+    assert all(v > 0 for v in lat)
