@@ -948,6 +948,9 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
         int qt = tb / nchunk, chunk = tb - qt * nchunk;
         uint32_t* exq = (uint32_t*)(lds + lay.exq) + wave * (2 + 2 * kExactQ);
         for (int task = tb; task < te; ++task, (++chunk == nchunk ? (chunk = 0, ++qt) : 0)) {
+          // past 3/8 of its share a wave outranks the waves (of any workgroup
+          // on the CU) still in their first part, so colours end together
+          if (task == tb + (((te - tb) * 3) >> 3)) __builtin_amdgcn_s_setprio(1);
           // the queue holds room for every lane of the next task
           if constexpr (JK) {
             if (uniform((int)__hip_atomic_load(&exq[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT)) > kExactQ - 64)
@@ -1061,6 +1064,7 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
                                 TL ? nullptr : U.nbr, lay.coup, TL ? nullptr : (const int32_t*)U.coup, lay.tau,
                                 lay.beta, lay.bl2e, lay.energy, lay.stats, W, Wq, U.jexp, t, seed, key);
         }
+        __builtin_amdgcn_s_setprio(0);
         __syncthreads();
       }
       {
@@ -1104,6 +1108,9 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
       const bool cube16 = DEG == 6 && U.topo == 1 && U.L == 16;
       const bool pair = sq64 || cube16;
       const bool record = (flags & kFlagRecord) && s + 1 == n_sweeps;
+      // the cluster moves are short dependent chains (growth levels, set-up
+      // scans): they issue ahead of Metropolis waves sharing the CU
+      __builtin_amdgcn_s_setprio(2);
       transpose_image(sp, G, nw, true);
       __syncthreads();
       if (wave < iwaves) {
@@ -1521,6 +1528,7 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
       }
       __syncthreads();
       transpose_image(sp, G, nw, false);
+      __builtin_amdgcn_s_setprio(0);
     }
     __syncthreads();
 
@@ -1534,6 +1542,7 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
       if (wave == 0) {
         const int r = lane;
         int acc_pt = 0;
+        __builtin_amdgcn_s_setprio(3);  // one serial chain: first in line on its SIMD
         if (r < R && K > 1) {
           // two rungs of read-ahead: the walker at k + 3 and the energy of the
           // walker at k + 2 are fetched while rung k is decided
@@ -1581,6 +1590,7 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
           stats[kStatPtAttempts] += (unsigned long long)(K - 1) * R;
           stats[kStatPtAccepts] += (unsigned long long)tot;
         }
+        __builtin_amdgcn_s_setprio(0);
       }
       __syncthreads();
     }
