@@ -87,11 +87,12 @@ __device__ __forceinline__ int wave_exclusive_scan(int v) {
 // NV per-lane values v[0..NV-1] (NV a power of two) summed over the wave at
 // once: each butterfly stage halves the values a lane holds (it keeps the sum
 // for one half of the indices and hands the other half to its partner), so
-// after log2 NV stages lane l holds a partial sum for index l mod NV, which
-// the remaining stages complete.  Returns, in every lane, the wave total for
+// after log2 NV stages lane l holds the sum over its NV-lane group for index
+// l mod NV (transpose_stages), which the remaining stages complete over the
+// wave (wave_rest).  transpose_sum returns, in every lane, the wave total for
 // index lane mod NV.  Exact for integers and for doubles holding integers.
 template <int NV, typename T>
-__device__ __forceinline__ T transpose_sum(T (&v)[NV]) {
+__device__ __forceinline__ T transpose_stages(T (&v)[NV]) {
   const int lane = lane_id();
 #pragma unroll
   for (int s = 0; (1 << s) < NV; ++s) {
@@ -104,10 +105,19 @@ __device__ __forceinline__ T transpose_sum(T (&v)[NV]) {
       v[j] = keep + __shfl_xor(send, m, 64);
     }
   }
-  T r = v[0];
+  return v[0];
+}
+
+template <int NV, typename T>
+__device__ __forceinline__ T wave_rest(T r) {
 #pragma unroll
   for (int m = NV; m < 64; m <<= 1) r += __shfl_xor(r, m, 64);
   return r;
+}
+
+template <int NV, typename T>
+__device__ __forceinline__ T transpose_sum(T (&v)[NV]) {
+  return wave_rest<NV>(transpose_stages<NV>(v));
 }
 
 
@@ -160,33 +170,6 @@ __device__ __forceinline__ bool accept_int_field(uint32_t u, int e, double beta,
 }
 
 
-// Sum over the set bits b of bb of +-J for the bond in slot d of site
-// 32 w + b (J in the coupling table's integer units): -J where replica a is
-// anti-aligned across the bond (anti bit set).  Four bits per round, so their
-// coupling loads are in flight together (the address of a spent round is site
-// 32 w, always valid, and its value is dropped).  One word: at most 32 sites x
-// 6 slots of 24-bit values, within an int.
-template <int JK, int DEG>
-__device__ __forceinline__ int boundary_sum(uint32_t bb, uint32_t anti, int w, int d, const int32_t* cf,
-                                            const int8_t* cj) {
-  int s = 0;
-  while (bb) {
-    int jv[4], pos[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const bool ok = bb != 0u;
-      pos[u] = ok ? __builtin_ctz(bb) : 0;
-      bb &= bb - 1u;
-      const int x = (32 * w + pos[u]) * DEG + d;
-      const int v = JK ? cf[x] : (int)cj[x];
-      jv[u] = ok ? v : 0;
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) s += ((anti >> pos[u]) & 1u) ? -jv[u] : jv[u];
-  }
-  return s;
-}
-
 // The same sum for int8 couplings from their bit planes (pl: the jpl plane
 // words of this word and slot, two's complement): sum over a bit set M of J
 // is sum_k w_k popc(M & plane_k), w_k = 2^k and -2^(jpl-1) for the sign
@@ -212,15 +195,25 @@ struct EnergyT<1> { using T = double; };
 // Adds a wave's accepted energy changes to the WPT walkers' energies: acc[b] is
 // a lane's sum of e = s_i h_i over its accepted flips of walker b (dE = 2 e in
 // field units; float couplings: units of 2^-jexp, and |acc| < 2^31 because a
-// lane takes at most 32 sites of a colour).  Integer sums throughout.
+// lane takes at most 32 sites of a colour).  Integer sums throughout.  narrow
+// (float couplings): a lane took at most nchunk sites with nchunk DEG WPT <
+// 256, so |acc| < 2^31 / WPT (|e| < DEG 2^23) and the WPT-lane group sums of
+// the butterfly stages still fit an int; only the rest of the wave is summed
+// in double.
 template <int JK, int WPT>
-__device__ __forceinline__ void flush_energy(int (&acc)[WPT], typename EnergyT<JK>::T* en, int jexp) {
+__device__ __forceinline__ void flush_energy(int (&acc)[WPT], typename EnergyT<JK>::T* en, int jexp,
+                                             bool narrow) {
   const int lane = lane_id();
   if constexpr (JK) {
-    double v[WPT];
+    double tot;  // integers below 2^53: exact in any order
+    if (narrow) {
+      tot = wave_rest<WPT>((double)transpose_stages<WPT>(acc));
+    } else {
+      double v[WPT];
 #pragma unroll
-    for (int b = 0; b < WPT; ++b) v[b] = (double)acc[b];
-    const double tot = transpose_sum<WPT>(v);  // integers below 2^53: exact in any order
+      for (int b = 0; b < WPT; ++b) v[b] = (double)acc[b];
+      tot = transpose_sum<WPT>(v);
+    }
     if (lane < WPT && tot != 0.0) atomicAdd(&en[lane], ldexp(tot, 1 - jexp));
   } else {
     int v[WPT];
@@ -246,6 +239,41 @@ __device__ __forceinline__ uint32_t absdiff(uint32_t a, uint32_t b) {
   uint32_t r;
   asm("v_sad_u32 %0, %1, %2, 0" : "=v"(r) : "v"(a), "v"(b));
   return r;
+}
+
+// Index of the lowest set bit, all ones for 0 (one v_ffbl_b32).
+__device__ __forceinline__ uint32_t lowest_bit(uint32_t x) {
+  uint32_t r;
+  asm("v_ffbl_b32 %0, %1" : "=v"(r) : "v"(x));
+  return r;
+}
+
+// Sum over the set bits b of bb of +-J for the bond in slot d of site
+// 32 w + b (J in the coupling table's integer units): -J where replica a is
+// anti-aligned across the bond (bit b of anti set).  Four bits per round, their
+// coupling loads in flight together; a round's slot without a bit left reads
+// the bond of site 32 w (bit 0: the lowest-bit index of 0 is -1, clamped to 0),
+// a valid entry, and those reads are taken out at the end.  At most 32 bits of
+// 24-bit values, plus the same number taken out: the sum stays within an int.
+template <int JK, int DEG>
+__device__ __forceinline__ int boundary_sum(uint32_t bb, uint32_t anti, int w, int d, const int32_t* cf,
+                                            const int8_t* cj) {
+  const int cnt = (int)__popc(bb);
+  const int base = 32 * w * DEG + d;
+  int s = 0, slots = 0;
+  while (bb) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int pos = max((int)lowest_bit(bb), 0);
+      bb &= bb - 1u;
+      const int x = base + pos * DEG;
+      const int v = JK ? cf[x] : (int)cj[x];
+      s = mad_i24(v, mad_i24((int)bit_of(anti, pos), -2, 1), s);  // sign -1 where anti-aligned
+    }
+    slots += 4;
+  }
+  const int v0 = JK ? cf[base] : (int)cj[base];
+  return s - (slots - cnt) * mad_i24((int)(anti & 1u), -2, 1) * v0;
 }
 
 // Spin (+1/-1) of byte b of an int8 quad word.
@@ -932,6 +960,7 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
       const int Wqt = (Wq + QPT - 1) / QPT;
       for (int c = 0; c < 2; ++c) {
         const int nchunk = (Nc + 63) >> 6;
+        const bool narrow = nchunk * DEG * WPT < 256;
         const int ntasks = Wqt * nchunk;
         const int tb = (int)(((long long)ntasks * wave) / nwaves);
         const int te = (int)(((long long)ntasks * (wave + 1)) / nwaves);
@@ -960,7 +989,7 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
           }
           if (qt != cur_q) {
             if (cur_q >= 0) {
-              flush_energy<JK, WPT>(acc, energy + WPT * cur_q, U.jexp);
+              flush_energy<JK, WPT>(acc, energy + WPT * cur_q, U.jexp, narrow);
 #pragma unroll
               for (int b = 0; b < WPT; ++b) acc[b] = 0;
             }
@@ -1057,7 +1086,7 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
             metro_cnt += __popc(flip);
           }
         }
-        if (cur_q >= 0) flush_energy<JK, WPT>(acc, energy + WPT * cur_q, U.jexp);
+        if (cur_q >= 0) flush_energy<JK, WPT>(acc, energy + WPT * cur_q, U.jexp, narrow);
         if constexpr (JK) {
           if (uniform((int)__hip_atomic_load(&exq[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT)) > 0)
             exact_pass<DEG, QPT>(lay.exq + 4u * (uint32_t)wave * (2 + 2 * kExactQ), lay.sp, Np, lay.nbr,
@@ -1355,6 +1384,8 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
             const int jpl = JK ? 0 : U.jpl;
             const uint32_t* jplw = (const uint32_t*)(lds + lay.jplanes);
             const int jw = min(li, nw - 1);  // lanes past the last word have no bits
+            // integer couplings in the register layouts below (at most 64 words)
+            // always come with their bit planes: jpl > 0 whenever moves run
             if (cube8) {
               // boundary bonds per direction d: i in the cluster, its d-neighbour
               // not (then outside the q-mask); anti-aligned in replica a where
@@ -1364,13 +1395,16 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
               cube8_dirs(cw, cd);
               cube8_dirs(awd, ad);
               csize = __popc(cw);
+              uint32_t bb[6], an[6];
 #pragma unroll
               for (int d = 0; d < 6; ++d) {
-                uint32_t bb = cw & ~cd[d];
-                const uint32_t anti = awd ^ ad[d];
-                ib += (!JK && jpl > 0) ? boundary_sum_planes(bb, anti, jplw + (jw * DEG + d) * jpl, jpl)
-                                      : boundary_sum<JK, DEG>(bb, anti, li, d, cf, cj);
+                bb[d] = cw & ~cd[d];
+                an[d] = awd ^ ad[d];
               }
+#pragma unroll
+              for (int d = 0; d < 6; ++d)
+                ib += JK ? boundary_sum<1, DEG>(bb[d], an[d], jw, d, cf, cj)
+                   : boundary_sum_planes(bb[d], an[d], jplw + (jw * DEG + d) * jpl, jpl);
             }
             if (chimreg) {
               // slots 0-3 in-cell, 4 = row-1 / col-1, 5 = row+1 / col+1
@@ -1384,6 +1418,7 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
               chimera_inter(cw, lane, cs, ci);
               chimera_inter(awd, lane, cs, ai);
               csize = __popc(cw);
+              uint32_t bbs[6], ans[6];
 #pragma unroll
               for (int d = 0; d < 6; ++d) {
                 uint32_t nb, na;
@@ -1398,16 +1433,19 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
                   na = ai[0] | ai[2];
                 }
                 const uint32_t exist = d < 4 ? ~0u : (d == 4 ? (cs.m[1] | cs.m[3]) : (cs.m[0] | cs.m[2]));
-                uint32_t bb = cw & ~nb & exist;
-                const uint32_t anti = awd ^ na;
-                ib += (!JK && jpl > 0) ? boundary_sum_planes(bb, anti, jplw + (jw * DEG + d) * jpl, jpl)
-                                      : boundary_sum<JK, DEG>(bb, anti, li, d, cf, cj);
+                bbs[d] = cw & ~nb & exist;
+                ans[d] = awd ^ na;
               }
+#pragma unroll
+              for (int d = 0; d < 6; ++d)
+                ib += JK ? boundary_sum<1, DEG>(bbs[d], ans[d], jw, d, cf, cj)
+                   : boundary_sum_planes(bbs[d], ans[d], jplw + (jw * DEG + d) * jpl, jpl);
             }
             if (latreg) {
               // slot 2a = +axis a (terms 4a, 4a+1), slot 2a+1 = -axis a (terms 4a+2, 4a+3)
               const uint32_t cw = li < nw ? gmc[2 * li + 1] : 0u, awd = li < nw ? gaw[li] : 0u;
               csize = __popc(cw);
+              uint32_t bbs[DEG], ans[DEG];
 #pragma unroll
               for (int d = 0; d < DEG; ++d) {
                 const int t0 = 2 * d;
@@ -1416,11 +1454,13 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
                 const uint32_t m1 = li < nw ? tmask[(t0 + 1) * nw + li] : 0u;
                 const uint32_t nb = reg_term(cw, lane, s0, m0) | reg_term(cw, lane, s1, m1);
                 const uint32_t na = reg_term(awd, lane, s0, m0) | reg_term(awd, lane, s1, m1);
-                uint32_t bb = cw & ~nb;
-                const uint32_t anti = awd ^ na;
-                ib += (!JK && jpl > 0) ? boundary_sum_planes(bb, anti, jplw + (jw * DEG + d) * jpl, jpl)
-                                      : boundary_sum<JK, DEG>(bb, anti, li, d, cf, cj);
+                bbs[d] = cw & ~nb;
+                ans[d] = awd ^ na;
               }
+#pragma unroll
+              for (int d = 0; d < DEG; ++d)
+                ib += JK ? boundary_sum<1, DEG>(bbs[d], ans[d], jw, d, cf, cj)
+                   : boundary_sum_planes(bbs[d], ans[d], jplw + (jw * DEG + d) * jpl, jpl);
             }
             if (pair) {
               int cs2 = 0;
