@@ -1148,11 +1148,12 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
         uint32_t* gmc = gsl + 2 * (nw + 2);
         uint32_t* gaw = gmc + 2 * nw;
         int* ginfo = (int*)(gaw + nw);
-        // moves are dealt round-robin over the ICM waves, so every wave gets a
-        // mix of cold (small clusters) and warm temperatures
-        for (int mbase = wave; mbase < nmoves; mbase += iwaves * P) {
+        // a wave takes P consecutive moves (neighbouring temperatures, so
+        // clusters of like size): its growth and boundary loops run as long as
+        // its largest cluster needs, so like sizes waste the fewest rounds
+        for (int mbase = wave * P; mbase < nmoves; mbase += iwaves * P) {
           // ---- set-up: every group its own move ----
-          const int mv = mbase + grp * iwaves;
+          const int mv = mbase + grp;
           const bool live = mv < nmoves;
           int a = 0, b = 0;
           uint32_t gx = 0u, um = 0u;
