@@ -994,14 +994,25 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
               for (int b = 0; b < WPT; ++b) acc[b] = 0;
             }
             cur_q = qt;
-            vmask = 0;
+            if constexpr (JK) {
+              // lane b (mod WPT) looks up walker WPT qt + b and its scale; the
+              // wave then takes the values as uniforms
+              const int wb = WPT * qt + (lane & (WPT - 1));
+              const int tl = wb < W ? tau[wb] : K;
+              const bool real = tl < K;
+              vmask = (uint32_t)__builtin_amdgcn_ballot_w64(real) & ((1u << WPT) - 1u);
+              const float lql = real ? ldexpf(bl2e[real ? tl : 0], 1 - U.jexp) : 0.0f;
 #pragma unroll
-            for (int b = 0; b < WPT; ++b) {
-              const int tb2 = uniform(WPT * qt + b < W ? tau[WPT * qt + b] : K);
-              if (tb2 < K) {
-                vmask |= 1u << b;
-                if (JK) lq[b] = ldexpf(__int_as_float(uniform(__float_as_int(bl2e[tb2]))), 1 - U.jexp);
-                else rowb[b] = tb2 * HM;
+              for (int b = 0; b < WPT; ++b) lq[b] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lql), b));
+            } else {
+              vmask = 0;
+#pragma unroll
+              for (int b = 0; b < WPT; ++b) {
+                const int tb2 = uniform(WPT * qt + b < W ? tau[WPT * qt + b] : K);
+                if (tb2 < K) {
+                  vmask |= 1u << b;
+                  rowb[b] = tb2 * HM;
+                }
               }
             }
           }
