@@ -42,6 +42,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="3d_L8_gauss_1024inst")
+    ap.add_argument("--instances", type=int, default=0,
+                    help="run the first N instances of the workload (0: all; for the Table I workloads "
+                         "the first ones are all of the smallest size)")
     ap.add_argument("--sweeps-per-step", type=int, default=SWEEPS_PER_STEP)
     ap.add_argument("--sweeps-per-launch", type=int, default=DEFAULT_LAUNCH["sweeps_per_launch"])
     ap.add_argument("--threads", type=int, default=DEFAULT_LAUNCH["threads"])
@@ -630,7 +633,9 @@ def main():
     from paper_1501_05630_amd import analysis, icm, inputs
 
     name = args.workload
-    spec = inputs.WORKLOADS[name]
+    spec = dict(inputs.WORKLOADS[name])
+    if args.instances:
+        spec["n_instances"] = min(args.instances, spec["n_instances"])
     n_inst = spec["n_instances"]
     S = spec["n_temps"] * spec["n_replicas"]
     ctx = icm.Context(arena_bytes=4 << 30, seed=inputs.MASTER_SEED)
@@ -690,7 +695,8 @@ def main():
     icm_moves = sum(moves_per_sweep) * sweeps
     step_ms = ms / args.steps
     bytes_per_sweep = sum(2 * S * N + nb * jbytes for N, nb in zip(sizes, bonds))
-    uneven = bool(spec.get("sides"))
+    sides = sorted({inputs.instance_side(spec, b) for b in range(n_inst)})
+    uneven = len(sides) > 1
     # the roofline of the fused kernel: one size class -> launches back to
     # back on the context stream, so a launch lasts step time / launches;
     # several classes (uneven batch) -> taken over the whole step
@@ -716,7 +722,7 @@ def main():
                          "bit-packed spins; int32 fields and energies; u32 threshold tables"),
         "data": "synthetic (seeded disorder, hot start)",
         "config": {"workload": name, "instances": n_inst, "topology": inputs.TOPOLOGY_NAMES[spec["topology"]],
-                   "L": list(spec["sides"]) if uneven else spec["L"],
+                   "L": sides if uneven else sides[0],
                    "N": sorted(set(sizes)) if uneven else sizes[0], "temps": spec["n_temps"],
                    "replicas": spec["n_replicas"], "icm_temps": moves_per_sweep[0] * 2 // spec["n_replicas"],
                    "sweeps_per_step": spsw, "sweeps_per_launch": spl, "launches_per_step": launches_per_step,

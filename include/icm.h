@@ -130,11 +130,12 @@ typedef struct {
 /* Launch configuration of icm_run (a 0 field in icm_set_run_config keeps the
    current value). */
 typedef struct {
-  int32_t threads;          /* threads per workgroup for every size class: 256, 512 or
-                               1024; -1 (and the initial value 0): per class, 256 for
-                               units of up to 512 sites, 512 up to 1024, 1024 above.  A
-                               run launches once per size class (sites <= 512, <= 1024,
-                               <= 2048, more) */
+  int32_t threads;          /* threads per workgroup for every size class: 64, 128,
+                               256, 512 or 1024; -1 (and the initial value 0): per
+                               class, 256 for units of up to 512 sites, 512 up to 1024,
+                               1024 above.  A run launches once per size class (sites
+                               <= 512, <= 1024, <= 2048, more), one workgroup per unit:
+                               small workgroups let more small units share a CU */
   int32_t sweeps_per_launch;/* sweeps fused into one kernel launch */
   int32_t use_graph;        /* 1: replay launches from a captured hipGraph */
   int32_t icm_slots;        /* ICM moves in flight per workgroup, 1..64 (LDS scratch):

@@ -1,7 +1,9 @@
 """Launch-shape autotuner for the fused sweep-block kernel.
 
 Searches threads per workgroup, cluster moves in flight per workgroup (ICM
-slots) and sweeps per launch for one batch of instances, timing `icm_run` with
+slots) and sweeps per launch for one batch of instances (one workgroup per
+instance: 64- and 128-thread workgroups let up to 16 small instances share a
+compute unit, which pays for batches of many small instances), timing `icm_run` with
 HIP events on the context stream, and caches the winner in a JSON file keyed by
 the batch's shape.  The choice never changes results: every launch shape
 computes the same bits (the random streams are keyed by site, sweep and walker,
@@ -11,7 +13,7 @@ import itertools
 import json
 import os
 
-THREADS = (256, 512, 1024)
+THREADS = (64, 128, 256, 512, 1024)
 SLOTS = (4, 8, 16, 32)
 SWEEPS = (128, 256)
 

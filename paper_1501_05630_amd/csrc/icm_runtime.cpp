@@ -1151,8 +1151,9 @@ int icm_set_run_config(icm_ctx* c, const icm_run_config* cfg) {
   if (!cfg) return fail(c, ICM_E_INVALID, "null config");
   icm_run_config n = c->cfg;
   if (cfg->threads) {
-    if (cfg->threads != 256 && cfg->threads != 512 && cfg->threads != 1024 && cfg->threads != -1)
-      return fail(c, ICM_E_INVALID, "threads must be 256, 512, 1024, or -1 for the per-class default");
+    const int t = cfg->threads;
+    if (t != 64 && t != 128 && t != 256 && t != 512 && t != 1024 && t != -1)
+      return fail(c, ICM_E_INVALID, "threads must be 64, 128, 256, 512, 1024, or -1 for the per-class default");
     n.threads = cfg->threads < 0 ? 0 : cfg->threads;
   }
   if (cfg->sweeps_per_launch < 0) return fail(c, ICM_E_INVALID, "negative sweeps_per_launch");

@@ -30,7 +30,7 @@ def test_candidates_respect_four_moves_per_wave():
     c = autotune.candidates()
     assert c and all(x["icm_slots"] <= 4 * (x["threads"] // 64) for x in c)
     assert all(x["use_graph"] == 1 for x in c)
-    assert {x["threads"] for x in c} == {256, 512, 1024}
+    assert {x["threads"] for x in c} == {64, 128, 256, 512, 1024}
     assert len(c) == len({json.dumps(x, sort_keys=True) for x in c})
 
 

@@ -261,6 +261,24 @@ def test_launch_shape_does_not_change_results(ctx, threads, slots, tables, name)
     ctx.icm_remove_instance(h)
 
 
+@pytest.mark.parametrize("threads,slots", [(64, 4), (128, 8), (128, 3)])
+@pytest.mark.parametrize("name,L", [("table1_3d_gauss", 4), ("table1_chimera_gauss", 4), ("table1_2d_gauss", 16),
+                                    ("3d_L8_gauss_1024inst", 8)])
+def test_small_workgroups_bit_exact(ctx, threads, slots, name, L):
+    # one or two waves per instance (several instances share a CU): the whole
+    # sweep -- Metropolis tasks, every cluster move of the unit and the PT scan
+    # -- runs on those waves
+    J, temps, kc, spec = gridded.workload_instance(name, 5, L=L)
+    h, o = make_pair(ctx, spec["topology"], L, J, temps, spec["n_replicas"], kc,
+                     icm.FLAG_2A | icm.FLAG_PT, key=5, j_scale=spec["j_scale"])
+    ctx.icm_set_run_config(threads=threads, icm_slots=slots, sweeps_per_launch=9, table_placement=0)
+    ctx.icm_init_states(h)
+    o.init_hot()
+    run_both(ctx, h, o, [1, 20], f"{name} L={L} threads={threads} slots={slots}")
+    ctx.icm_set_run_config(threads=512, icm_slots=8, sweeps_per_launch=256, table_placement=0)
+    ctx.icm_remove_instance(h)
+
+
 def test_large_3d_L16_runs_with_tables_in_global_memory(ctx):
     # 4096 sites x 96 walkers: the spins fit LDS bit-packed, the tables do not.
     J = gridded.gaussian_couplings(inputs.CUBIC3D, 16, inputs.make_rng(75, 0))
