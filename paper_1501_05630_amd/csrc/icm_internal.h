@@ -70,7 +70,7 @@ ICM_HD uint32_t align16(uint32_t x) { return (x + 15u) & ~15u; }
 // sites past N are zero), so that the image transposes in place into its
 // walker-major view by 32 x 32 blocks.
 struct LdsLayout {
-  uint32_t sp, nbr, clist, coup, tau, at, gauge, energy, thr, beta, bl2e, dbl2e, ptu, icmu, terms, jplanes,
+  uint32_t sp, nbr, clist, coup, tau, at, gauge, energy, thr, beta, bl2e, dbl2e, ptu, ptacc, icmu, terms, jplanes,
       slots, parent, meas, exq, stats, total;
 };
 
@@ -114,6 +114,14 @@ ICM_HD int coupling_planes(int jkind, int Kc, int N, int jmin, int jmax) {
 // made exactly at the end of the colour; a wave's queue holds kExactQ tasks
 // and is emptied early when a task could fill it.
 constexpr int kExactQ = 96;
+
+// PT ladders of kPtTableMin to kPtTable temperatures decide every swap a
+// chain's scan could meet up front, in parallel: word (k, r) bit c = whether
+// the walker that sat at rung c, carried up to rung k, swaps with the walker at
+// rung k + 1.  The scan itself then only tests bits.  Shorter ladders scan
+// directly (the K (K - 1) / 2 decisions and the extra barrier do not pay for
+// themselves there: measured slower at 20 temperatures, faster at 24 and 30).
+constexpr int kPtTable = 33, kPtTableMin = 22;
 ICM_HD int exact_queue_words(int jkind, int waves) { return jkind ? waves * (2 + 2 * kExactQ) : 0; }
 
 // tables = 1: neighbour table, colour lists and couplings are copied into LDS;
@@ -143,6 +151,7 @@ ICM_HD LdsLayout lds_layout(int N, int deg, int Wq, int K, int R, int HM, int jk
   L.bl2e = o;    o = align16(o + 4u * K);
   L.dbl2e = o;   o = align16(o + 4u * K);   // float((beta_k - beta_k+1) log2 e), PT filter
   L.ptu = o;     o = align16(o + 4u * (K > 1 ? K - 1 : 1) * R);
+  L.ptacc = o;   o = align16(o + (K >= kPtTableMin && K <= kPtTable ? 4u * (K - 1) * R : 0u));
   L.icmu = o;    o = align16(o + 4u * (Kc > 0 ? Kc * (R / 2) : 1));
   L.terms = o;   o = align16(o + (Kc > 0 ? 4u * kMaxTerms * (1 + site_words(N)) : 0u));
   L.jplanes = o; o = align16(o + 4u * (uint32_t)jpl * deg * site_words(N));

@@ -736,6 +736,45 @@ __device__ __noinline__ void measure_step(uint32_t t_end, int N, int K, int R, i
 // task; empties the wave's queue.  Out of line, so that the sweep loop keeps
 // no registers for it.
 // ----------------------------------------------------------------------------
+// PT decisions of a step, up front (at most kPtTable temperatures): every
+// pair (k, c), c <= k, of every chain r -- the walker that sat at rung c,
+// carried up to rung k, against the walker at rung k + 1 -- decided with the
+// swap rule; bit c of word (k, r) of the table is set on a swap.  Energies do
+// not change during PT, so these are exactly the decisions a chain's scan
+// can meet.  Out of line and with scalar arguments, like exact_pass, so that
+// it does not weigh on the sweep loop's registers.
+template <int JK>
+__device__ __noinline__ void pt_decide(uint32_t at_off, uint32_t energy_off, uint32_t ptu_off, uint32_t ptacc_off,
+                                       uint32_t beta_off, uint32_t dbl2e_off, const uint32_t* ptthr, int ptlen,
+                                       int K, int R) {
+  using E_t = typename EnergyT<JK>::T;
+  const int* at = (const int*)(lds + uniform((int)at_off));
+  const E_t* energy = (const E_t*)(lds + uniform((int)energy_off));
+  const uint32_t* ptu = (const uint32_t*)(lds + uniform((int)ptu_off));
+  uint32_t* ptacc = (uint32_t*)(lds + uniform((int)ptacc_off));
+  const double* beta = (const double*)(lds + uniform((int)beta_off));
+  const float* dbl2e = (const float*)(lds + uniform((int)dbl2e_off));
+  const int T = K * (K - 1) / 2;
+  for (int d = (int)threadIdx.x; d < R * T; d += (int)blockDim.x) {
+    const int r = d / T, idx = d - r * T;
+    int k = (int)((__builtin_sqrtf(8.0f * (float)idx + 1.0f) - 1.0f) * 0.5f);
+    if ((k + 1) * (k + 2) / 2 <= idx) ++k;
+    if (k * (k + 1) / 2 > idx) --k;
+    const int c = idx - k * (k + 1) / 2;
+    const E_t ex = energy[at[c * R + r]], ey = energy[at[(k + 1) * R + r]];
+    const uint32_t u = ptu[k * R + r];
+    bool accept;
+    if constexpr (JK) {
+      const double D = (double)ey - (double)ex;
+      accept = accept_float(u, D, beta[k] - beta[k + 1], dbl2e[k]);
+    } else {
+      const int D = (int)ey - (int)ex;
+      accept = D <= 0 || (D <= ptlen && u < ptthr[k * ptlen + (D - 1)]);
+    }
+    if (accept) atomicOr(&ptacc[k * R + r], 1u << c);
+  }
+}
+
 template <int DEG, int QPT>
 __device__ __noinline__ void exact_pass(uint32_t q_off, uint32_t sp_off, int Np, uint32_t nbr_off,
                                         const uint16_t* nbr_global, uint32_t coup_off, const int32_t* coup_global,
@@ -946,6 +985,7 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
       for (int x = tid; x < (K - 1) * R; x += nthr) {
         const int k = x / R, r = x - k * R;
         ptu[x] = philox4x32_10((uint32_t)k, t, (uint32_t)r, kStreamPt, seed, key).w[0];
+        if (K >= kPtTableMin && K <= kPtTable) ((uint32_t*)(lds + lay.ptacc))[x] = 0u;  // this step's swap words
       }
     for (int x = tid; x < Kc * (R >> 1); x += nthr)
       icmu[x] = philox4x32_10((uint32_t)x, t, 0u, kStreamIcm, seed, key).w[0];
@@ -1586,63 +1626,118 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
 
     // ---------------- step 3: parallel tempering ---------------------------------
     if (flags & kFlagPt) {
-      // Lane r scans chain r up the ladder.  Rung k only ever meets the walker
-      // carried up from rung k - 1 (or the one that sat at k) and the walker
-      // still sitting at k + 1, so the carried walker and its energy stay in
-      // registers, rung k is final once decided, and the next rung's walker,
-      // energy and draw are read ahead: no LDS round trip on the chain.
-      if (wave == 0) {
-        const int r = lane;
-        int acc_pt = 0;
-        __builtin_amdgcn_s_setprio(3);  // one serial chain: first in line on its SIMD
-        if (r < R && K > 1) {
-          // two rungs of read-ahead: the walker at k + 3 and the energy of the
-          // walker at k + 2 are fetched while rung k is decided
-          int x = at[r];
-          E_t ex = energy[x];
-          int yn = at[R + r];
-          E_t eyn = energy[yn];
-          uint32_t un = ptu[r];
-          int ynn = K > 2 ? at[2 * R + r] : 0;
-          for (int k = 0; k + 1 < K; ++k) {
-            const int y = yn;
-            const E_t ey = eyn;
-            const uint32_t u = un;
-            if (k + 2 < K) {
-              yn = ynn;
-              eyn = energy[ynn];
-              un = ptu[(k + 1) * R + r];
-              if (k + 3 < K) ynn = at[(k + 3) * R + r];
+      // the swap rule between the walker carried up to rung k (energy ex) and
+      // the walker at rung k + 1 (energy ey), with the draw u of (k, chain):
+      // u 2^-32 < exp(-(beta_k - beta_k+1) D) in double after the float
+      // pre-filter that settles all but a thin band (as for Metropolis), or
+      // the threshold table for integer couplings
+      auto pt_accept = [&](uint32_t u, E_t ex, E_t ey, int k) -> bool {
+        if constexpr (JK) {
+          const double D = (double)ey - (double)ex;
+          return accept_float(u, D, beta[k] - beta[k + 1], dbl2e[k]);
+        } else {
+          const int D = (int)ey - (int)ex;
+          return D <= 0 || (D <= U.ptlen && u < U.ptthr[k * U.ptlen + (D - 1)]);
+        }
+      };
+      if (K >= kPtTableMin && K <= kPtTable) {
+        // Every decision a chain's scan can meet is known up front: at rung k
+        // the carried walker is one that sat at some rung c <= k before the
+        // step, and energies do not change during PT.  All threads decide the
+        // K (K - 1) / 2 pairs (k, c) of every chain; bit c of word (k, r) is
+        // set on a swap.  Lane r of wave 0 then scans chain r testing bits.
+        uint32_t* ptacc = (uint32_t*)(lds + lay.ptacc);
+        pt_decide<JK>((uint32_t)((unsigned char*)at - lds), (uint32_t)((unsigned char*)energy - lds), lay.ptu,
+                      lay.ptacc, lay.beta, lay.dbl2e, U.ptthr, U.ptlen, K, R);
+        __syncthreads();
+        if (wave == 0) {
+          const int r = lane;
+          int acc_pt = 0;
+          __builtin_amdgcn_s_setprio(3);
+          if (r < R) {
+            // rung k keeps the walker from k + 1 on a swap (the carried one
+            // climbs on), else the carried one (and the walker from k + 1,
+            // which sat at rung c = k + 1, is carried)
+            int x = at[r], c = 0;
+            int yn = at[R + r];
+            uint32_t bn = ptacc[r];
+            for (int k = 0; k + 1 < K; ++k) {
+              const int y = yn;
+              const uint32_t bits = bn;
+              if (k + 2 < K) {
+                yn = at[(k + 2) * R + r];
+                bn = ptacc[(k + 1) * R + r];
+              }
+              const bool swap = (bits >> c) & 1u;
+              const int stay = swap ? y : x;
+              at[k * R + r] = stay;
+              tau[stay] = k;
+              if (!swap) {
+                x = y;
+                c = k + 1;
+              }
+              acc_pt += swap ? 1 : 0;
             }
-            bool accept;
-            if (JK) {
-              // u 2^-32 < exp(-(beta_k - beta_k+1) D) in double, after the float
-              // pre-filter that settles all but a thin band (as for Metropolis)
-              const double D = (double)ey - (double)ex;
-              accept = accept_float(u, D, beta[k] - beta[k + 1], dbl2e[k]);
-            } else {
-              const int D = (int)ey - (int)ex;
-              accept = D <= 0 || (D <= U.ptlen && u < U.ptthr[k * U.ptlen + (D - 1)]);
-            }
-            // rung k keeps y on a swap (x climbs on), else x (and y is carried)
-            const int stay = accept ? y : x;
-            at[k * R + r] = stay;
-            tau[stay] = k;
-            if (!accept) {
-              x = y;
-              ex = ey;
-            }
-            acc_pt += accept ? 1 : 0;
+            at[(K - 1) * R + r] = x;
+            tau[x] = K - 1;
           }
-          at[(K - 1) * R + r] = x;
-          tau[x] = K - 1;
+          const int tot = wave_sum(acc_pt);
+          if (lane == 0) {
+            stats[kStatPtAttempts] += (unsigned long long)(K - 1) * R;
+            stats[kStatPtAccepts] += (unsigned long long)tot;
+          }
+          __builtin_amdgcn_s_setprio(0);
         }
-        const int tot = wave_sum(acc_pt);
-        if (lane == 0) {
-          stats[kStatPtAttempts] += (unsigned long long)(K - 1) * R;
-          stats[kStatPtAccepts] += (unsigned long long)tot;
+      } else {
+        // Long ladders: lane r scans chain r up the ladder.  Rung k only ever
+        // meets the walker carried up from rung k - 1 (or the one that sat at
+        // k) and the walker still sitting at k + 1, so the carried walker and
+        // its energy stay in registers, rung k is final once decided, and the
+        // next rung's walker, energy and draw are read ahead.
+        if (wave == 0) {
+          const int r = lane;
+          int acc_pt = 0;
+          __builtin_amdgcn_s_setprio(3);  // one serial chain: first in line on its SIMD
+          if (r < R && K > 1) {
+            // two rungs of read-ahead: the walker at k + 3 and the energy of the
+            // walker at k + 2 are fetched while rung k is decided
+            int x = at[r];
+            E_t ex = energy[x];
+            int yn = at[R + r];
+            E_t eyn = energy[yn];
+            uint32_t un = ptu[r];
+            int ynn = K > 2 ? at[2 * R + r] : 0;
+            for (int k = 0; k + 1 < K; ++k) {
+              const int y = yn;
+              const E_t ey = eyn;
+              const uint32_t u = un;
+              if (k + 2 < K) {
+                yn = ynn;
+                eyn = energy[ynn];
+                un = ptu[(k + 1) * R + r];
+                if (k + 3 < K) ynn = at[(k + 3) * R + r];
+              }
+              const bool accept = pt_accept(u, ex, ey, k);
+              // rung k keeps y on a swap (x climbs on), else x (and y is carried)
+              const int stay = accept ? y : x;
+              at[k * R + r] = stay;
+              tau[stay] = k;
+              if (!accept) {
+                x = y;
+                ex = ey;
+              }
+              acc_pt += accept ? 1 : 0;
+            }
+            at[(K - 1) * R + r] = x;
+            tau[x] = K - 1;
+          }
+          const int tot = wave_sum(acc_pt);
+          if (lane == 0) {
+            stats[kStatPtAttempts] += (unsigned long long)(K - 1) * R;
+            stats[kStatPtAccepts] += (unsigned long long)tot;
+          }
+          __builtin_amdgcn_s_setprio(0);
         }
-        __builtin_amdgcn_s_setprio(0);
       }
       __syncthreads();
     }
