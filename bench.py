@@ -653,7 +653,7 @@ def main():
     jbytes = 4 if spec["kind"] == "gauss" else 1
     spsw = args.sweeps_per_step
     launch = dict(threads=args.threads, icm_slots=args.icm_slots, sweeps_per_launch=args.sweeps_per_launch,
-                  use_graph=args.graph, table_placement=0)
+                  use_graph=args.graph, table_placement=0, class_threads=(-1, -1, -1, -1))
     tuned = {"source": "flags"}
     if not args.no_tune:
         # the autotuner times every candidate shape on this batch (advancing
@@ -666,8 +666,8 @@ def main():
         if "ms_per_sweep" in info:
             tuned["best_ms_per_sweep"] = min(info["ms_per_sweep"].values())
             dflt = json.dumps(dict(threads=DEFAULT_LAUNCH["threads"], icm_slots=DEFAULT_LAUNCH["icm_slots"],
-                                   sweeps_per_launch=DEFAULT_LAUNCH["sweeps_per_launch"], use_graph=1),
-                              sort_keys=True)
+                                   sweeps_per_launch=DEFAULT_LAUNCH["sweeps_per_launch"], use_graph=1,
+                                   class_threads=autotune.NO_CLASS_THREADS), sort_keys=True)
             if dflt in info["ms_per_sweep"]:
                 tuned["default_ms_per_sweep"] = info["ms_per_sweep"][dflt]
         for h in hs:
@@ -726,7 +726,9 @@ def main():
                    "N": sorted(set(sizes)) if uneven else sizes[0], "temps": spec["n_temps"],
                    "replicas": spec["n_replicas"], "icm_temps": moves_per_sweep[0] * 2 // spec["n_replicas"],
                    "sweeps_per_step": spsw, "sweeps_per_launch": spl, "launches_per_step": launches_per_step,
-                   "threads": sorted({icm.launch_threads(n, launch["threads"]) for n in sizes}),
+                   "threads": sorted({icm.launch_threads(n, launch["threads"], launch["class_threads"])
+                                      for n in sizes}),
+                   "class_threads": [int(x) for x in launch["class_threads"]],
                    "threads_requested": launch["threads"], "icm_slots": launch["icm_slots"],
                    "graph": bool(launch["use_graph"]) and spsw // spl > 1, "launch_shape": tuned,
                    "parallelism": "single GPU, one workgroup per instance"},

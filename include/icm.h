@@ -143,6 +143,11 @@ typedef struct {
                                (16, 32 or 64 for units of up to 512, 1024, 4096 sites) */
   int32_t table_placement;  /* 0: automatic, 1: neighbour/coupling tables in LDS,
                                2: tables read from global memory */
+  int32_t class_threads[4]; /* per size class (sites <= 512, <= 1024, <= 2048, more):
+                               threads per workgroup for that class's launches, 64 to
+                               1024 as for `threads`, overriding it; 0 keeps the
+                               current entry, -1 clears it (the class follows
+                               `threads` again).  Initially all clear. */
 } icm_run_config;
 
 /* Creates a context on `device`, issuing all work on `hip_stream` (a

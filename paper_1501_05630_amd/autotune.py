@@ -1,6 +1,7 @@
 """Launch-shape autotuner for the fused sweep-block kernel.
 
-Searches threads per workgroup, cluster moves in flight per workgroup (ICM
+Searches threads per workgroup (then, for a batch of several size classes,
+each class's own thread count), cluster moves in flight per workgroup (ICM
 slots) and sweeps per launch for one batch of instances (one workgroup per
 instance: 64- and 128-thread workgroups let up to 16 small instances share a
 compute unit, which pays for batches of many small instances), timing `icm_run` with
@@ -32,15 +33,26 @@ def batch_key(metas, n_instances):
     return "|".join(parts) + f"|n{1 << max(0, (n_instances - 1).bit_length())}"
 
 
+NO_CLASS_THREADS = [-1, -1, -1, -1]
+
+
 def candidates(threads=THREADS, slots=SLOTS, sweeps=SWEEPS):
     """Launch shapes the search tries: every combination in which a wave
-    carries at most four moves on average (slots <= 4 x waves)."""
+    carries at most four moves on average (slots <= 4 x waves), the same thread
+    count for every size class."""
     out = []
     for t, s, n in itertools.product(threads, slots, sweeps):
         if s > 4 * (t // 64):
             continue
-        out.append(dict(threads=t, icm_slots=s, sweeps_per_launch=n, use_graph=1))
+        out.append(dict(threads=t, icm_slots=s, sweeps_per_launch=n, use_graph=1,
+                        class_threads=list(NO_CLASS_THREADS)))
     return out
+
+
+def size_classes(metas):
+    """The size classes (as icm_run launches them) present in a batch."""
+    return sorted({0 if m["N"] <= 512 else (1 if m["N"] <= 1024 else (2 if m["N"] <= 2048 else 3))
+                   for m in metas})
 
 
 def event_timer(ctx, handles, sweeps, repeats=2):
@@ -92,10 +104,12 @@ def tune(ctx, handles, cache_path=None, cands=None, sweeps_per_candidate=None, t
     cache = _load(cache_path)
     if key in cache:
         best = dict(cache[key])
+        best["class_threads"] = list(best.get("class_threads", NO_CLASS_THREADS))
         ctx.icm_set_run_config(**best)
         return best, {"key": key, "source": "cache"}
     results = []
     for cfg in (cands if cands is not None else candidates()):
+        cfg = dict(cfg, class_threads=list(cfg.get("class_threads", NO_CLASS_THREADS)))
         ctx.icm_set_run_config(**cfg)
         n = sweeps_per_candidate or cfg["sweeps_per_launch"]
         ms = timer(ctx, handles, n)
@@ -104,6 +118,25 @@ def tune(ctx, handles, cache_path=None, cands=None, sweeps_per_candidate=None, t
             print(f"autotune {key} {cfg}: {ms * 1e3:.2f} us/sweep", flush=True)
     results.sort(key=lambda r: r[0])
     best = dict(results[0][1])
+    # a batch of several size classes (one launch each): then each class's
+    # thread count is refined in turn, the others held, on the whole batch
+    classes = size_classes([ctx.meta[h] for h in handles])
+    if len(classes) > 1:
+        best_ms = results[0][0]
+        ct = list(NO_CLASS_THREADS)
+        for cls in classes:
+            for t in THREADS:
+                trial = list(ct)
+                trial[cls] = t
+                cfg = dict(best, class_threads=list(trial))
+                ctx.icm_set_run_config(**cfg)
+                ms = timer(ctx, handles, sweeps_per_candidate or cfg["sweeps_per_launch"])
+                results.append((ms, cfg))
+                if verbose:
+                    print(f"autotune {key} {cfg}: {ms * 1e3:.2f} us/sweep", flush=True)
+                if ms < best_ms:
+                    best_ms, ct = ms, trial
+        best["class_threads"] = list(ct)
     cache[key] = best
     _store(cache_path, cache)
     ctx.icm_set_run_config(**best)

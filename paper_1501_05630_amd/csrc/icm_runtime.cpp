@@ -266,7 +266,7 @@ struct icm_ctx {
   size_t lds_limit = 65536;
   int n_cus = 256;
   size_t lds_cu = 0;                 // LDS bytes per compute unit
-  icm_run_config cfg{0, 256, 0, 32, 0};
+  icm_run_config cfg{0, 256, 0, 32, 0, {0, 0, 0, 0}};
   // unit tables cached per (handle list)
   std::map<std::vector<int32_t>, UnitDesc*> unit_tables;
   // captured graphs per (handle list, sweeps per launch, launches)
@@ -702,13 +702,15 @@ struct Group {
 };
 
 // Size classes of units (sites): up to 512, 1024, 2048, more.  Units of one
-// class share a launch (its LDS size is the largest member's).  threads = 0
-// (automatic): 256 threads per workgroup up to 512 sites, 512 up to 1024,
-// 1024 above; otherwise the configured count for every class.
+// class share a launch (its LDS size is the largest member's).  Threads per
+// workgroup of a class: its class_threads entry if set, else the configured
+// count, else (threads = 0, automatic) 256 up to 512 sites, 512 up to 1024,
+// 1024 above.
 int size_class(int N) { return N <= 512 ? 0 : (N <= 1024 ? 1 : (N <= 2048 ? 2 : 3)); }
 
-int class_threads(int threads, int cls) {
-  if (threads > 0) return threads;
+int class_threads(const icm_run_config& cfg, int cls) {
+  if (cfg.class_threads[cls] > 0) return cfg.class_threads[cls];
+  if (cfg.threads > 0) return cfg.threads;
   return cls == 0 ? 256 : (cls == 1 ? 512 : 1024);
 }
 
@@ -764,7 +766,7 @@ int unit_table(icm_ctx* c, const std::vector<int32_t>& hs, UnitDesc** out) {
 }
 
 int launch_group(icm_ctx* c, const Group& g, uint32_t n_sweeps, bool per_instance, hipStream_t strm) {
-  const int threads = class_threads(c->cfg.threads, g.cls);
+  const int threads = class_threads(c->cfg, g.cls);
   size_t lds = 0;
   int tables = 1;
   const int slots = effective_slots(c, g.handles, threads, c->cfg.icm_slots, lds, tables);
@@ -1150,11 +1152,17 @@ int icm_set_run_config(icm_ctx* c, const icm_run_config* cfg) {
   if (rc) return rc;
   if (!cfg) return fail(c, ICM_E_INVALID, "null config");
   icm_run_config n = c->cfg;
+  auto valid_threads = [](int t) { return t == 64 || t == 128 || t == 256 || t == 512 || t == 1024 || t == -1; };
   if (cfg->threads) {
-    const int t = cfg->threads;
-    if (t != 64 && t != 128 && t != 256 && t != 512 && t != 1024 && t != -1)
+    if (!valid_threads(cfg->threads))
       return fail(c, ICM_E_INVALID, "threads must be 64, 128, 256, 512, 1024, or -1 for the per-class default");
     n.threads = cfg->threads < 0 ? 0 : cfg->threads;
+  }
+  for (int k = 0; k < 4; ++k) {
+    if (!cfg->class_threads[k]) continue;
+    if (!valid_threads(cfg->class_threads[k]))
+      return fail(c, ICM_E_INVALID, "class_threads[%d] must be 64, 128, 256, 512, 1024, or -1 to clear", k);
+    n.class_threads[k] = cfg->class_threads[k] < 0 ? 0 : cfg->class_threads[k];
   }
   if (cfg->sweeps_per_launch < 0) return fail(c, ICM_E_INVALID, "negative sweeps_per_launch");
   if (cfg->sweeps_per_launch) n.sweeps_per_launch = cfg->sweeps_per_launch;

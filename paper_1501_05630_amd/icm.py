@@ -41,7 +41,7 @@ class Stats(ctypes.Structure):
 
 class RunConfig(ctypes.Structure):
     _fields_ = [("threads", _I32), ("sweeps_per_launch", _I32), ("use_graph", _I32),
-                ("icm_slots", _I32), ("table_placement", _I32)]
+                ("icm_slots", _I32), ("table_placement", _I32), ("class_threads", _I32 * 4)]
 
 
 EXPORTS = {
@@ -116,11 +116,19 @@ def coupling_kind(couplings):
     return J_F32 if np.asarray(couplings).dtype.kind == "f" else J_INT8
 
 
-def launch_threads(n_sites, threads):
+def size_class(n_sites):
+    """Size class of a unit, as icm_run groups launches: sites <= 512, <= 1024,
+    <= 2048, more."""
+    return 0 if n_sites <= 512 else (1 if n_sites <= 1024 else (2 if n_sites <= 2048 else 3))
+
+
+def launch_threads(n_sites, threads, class_threads=None):
     """Threads per workgroup that icm_run launches for units of n_sites sites
-    when icm_run_config.threads is `threads` (the rule the header states): the
-    configured count for every size class, or for 0 / -1 the per-class
-    default, 256 up to 512 sites, 512 up to 1024, 1024 above."""
+    (the rule the header states): the unit's size-class entry of class_threads
+    if set (> 0), else `threads` if set, else for 0 / -1 the per-class default,
+    256 up to 512 sites, 512 up to 1024, 1024 above."""
+    if class_threads is not None and class_threads[size_class(n_sites)] > 0:
+        return int(class_threads[size_class(n_sites)])
     if threads > 0:
         return int(threads)
     return 256 if n_sites <= 512 else (512 if n_sites <= 1024 else 1024)
@@ -211,8 +219,9 @@ class Context:
         _check(self.h, self._lib.icm_sync(self.h), "icm_sync")
 
     def icm_set_run_config(self, threads=0, sweeps_per_launch=0, use_graph=0, icm_slots=0,
-                           table_placement=0):
-        cfg = RunConfig(threads, sweeps_per_launch, use_graph, icm_slots, table_placement)
+                           table_placement=0, class_threads=(0, 0, 0, 0)):
+        ct = (_I32 * 4)(*[int(x) for x in class_threads])
+        cfg = RunConfig(threads, sweeps_per_launch, use_graph, icm_slots, table_placement, ct)
         _check(self.h, self._lib.icm_set_run_config(self.h, ctypes.byref(cfg)), "icm_set_run_config")
 
     def icm_get_run_config(self):
@@ -220,7 +229,7 @@ class Context:
         _check(self.h, self._lib.icm_get_run_config(self.h, ctypes.byref(cfg)), "icm_get_run_config")
         return dict(threads=cfg.threads, sweeps_per_launch=cfg.sweeps_per_launch,
                     use_graph=cfg.use_graph, icm_slots=cfg.icm_slots,
-                    table_placement=cfg.table_placement)
+                    table_placement=cfg.table_placement, class_threads=list(cfg.class_threads))
 
     # -- readout ---------------------------------------------------------------
     def icm_read_energies(self, h):

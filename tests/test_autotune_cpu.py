@@ -46,7 +46,8 @@ def test_search_picks_the_fastest_and_caches_it(tmp_path):
     cache = str(tmp_path / "tune.json")
     ctx = FakeCtx([META] * 8)
     best, info = autotune.tune(ctx, list(range(8)), cache_path=cache, timer=fake_timer)
-    assert best == dict(threads=512, icm_slots=16, sweeps_per_launch=256, use_graph=1)
+    assert best == dict(threads=512, icm_slots=16, sweeps_per_launch=256, use_graph=1,
+                        class_threads=[-1, -1, -1, -1])
     assert info["source"] == "search" and ctx.cfg == best
     assert len(info["ms_per_sweep"]) == len(autotune.candidates())
     with open(cache) as f:
@@ -66,3 +67,24 @@ def test_restricted_candidates_and_no_cache():
     cands = [c for c in autotune.candidates() if c["sweeps_per_launch"] == 128]
     best, info = autotune.tune(ctx, [0, 1, 2, 3], cache_path=None, cands=cands, timer=fake_timer)
     assert best["sweeps_per_launch"] == 128 and best["threads"] == 512 and best["icm_slots"] == 16
+
+
+def test_several_size_classes_get_their_own_thread_counts():
+    # a batch of 64-site and 2000-site units (size classes 0 and 2): after the
+    # common search each class's thread count is refined on the whole batch
+    ctx = FakeCtx([dict(META, N=64)] * 4 + [dict(META, N=2000)] * 4)
+
+    def timer(ctx, handles, sweeps):
+        c = ctx.cfg
+        ct = c["class_threads"]
+        small = ct[0] if ct[0] > 0 else c["threads"]
+        large = ct[2] if ct[2] > 0 else c["threads"]
+        return abs(small - 128) / 64 + abs(large - 1024) / 64 + abs(c["icm_slots"] - 16) / 8
+
+    best, info = autotune.tune(ctx, list(range(8)), cache_path=None, timer=timer)
+    assert best["class_threads"][0] == 128 and best["class_threads"][2] == 1024
+    assert best["class_threads"][1] == -1 and best["class_threads"][3] == -1
+    assert ctx.cfg == best
+    # the common search plus every thread count for each of the two classes
+    assert len(info["ms_per_sweep"]) <= len(autotune.candidates()) + 2 * len(autotune.THREADS)
+    assert autotune.size_classes(ctx.meta.values()) == [0, 2]

@@ -279,6 +279,32 @@ def test_small_workgroups_bit_exact(ctx, threads, slots, name, L):
     ctx.icm_remove_instance(h)
 
 
+def test_per_class_thread_counts_bit_exact(ctx):
+    # one batch of units from three size classes (3D L = 4, 6; 10; 12), each
+    # class launched with its own thread count
+    name = "3d_uneven_gauss_1536inst"
+    pairs = []
+    for b in (0, 300, 800, 1100):
+        J, temps, kc, spec = gridded.workload_instance(name, b)
+        h, o = make_pair(ctx, spec["topology"], spec["L"], J, temps, spec["n_replicas"], kc,
+                         icm.FLAG_2A | icm.FLAG_PT, key=b)
+        ctx.icm_init_states(h)
+        o.init_hot()
+        pairs.append((h, o, spec["L"]))
+    ctx.icm_set_run_config(threads=256, icm_slots=8, sweeps_per_launch=7, class_threads=(64, 1024, 512, -1))
+    assert ctx.icm_get_run_config()["class_threads"] == [64, 1024, 512, 0]
+    for n in (3, 12):
+        ctx.icm_run([h for h, _, _ in pairs], n)
+        ctx.icm_sync()
+        for h, o, L in pairs:
+            o.run(n)
+            assert_same(ctx, h, o, f"L={L} after +{n}")
+    ctx.icm_set_run_config(threads=512, icm_slots=8, sweeps_per_launch=256, class_threads=(-1, -1, -1, -1))
+    assert ctx.icm_get_run_config()["class_threads"] == [0, 0, 0, 0]
+    for h, _, _ in pairs:
+        ctx.icm_remove_instance(h)
+
+
 def test_large_3d_L16_runs_with_tables_in_global_memory(ctx):
     # 4096 sites x 96 walkers: the spins fit LDS bit-packed, the tables do not.
     J = gridded.gaussian_couplings(inputs.CUBIC3D, 16, inputs.make_rng(75, 0))
