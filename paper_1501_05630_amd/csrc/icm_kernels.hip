@@ -1082,9 +1082,11 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
             uint32_t xw[DEG];
 #pragma unroll
             for (int d = 0; d < DEG; ++d) {
-              Ji[d] = JK ? cf[i * DEG + d] : (int)cj[i * DEG + d];
-              Jsum += Ji[d];
               xw[d] = nw[d] ^ own;
+              if constexpr (JK) {
+                Ji[d] = cf[i * DEG + d];
+                Jsum += Ji[d];
+              }
             }
             uint32_t flip = 0;
             if constexpr (JK) {
@@ -1119,13 +1121,31 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
                 exq[3 + 2 * pos] = flip;
               }
             } else {
+              // int8 couplings: the site's couplings packed one per byte (slots
+              // 0-3, then 4-5), and per neighbour slot d the task's four walker
+              // bits of x_d in byte d; walker b's sum over d of J_d x_d is then
+              // two four-byte dot products (v_dot4c_i32_i8) of its bit bytes
+              // with the coupling bytes
+              uint32_t Jp, Jp2 = 0u, T = 0u, T2 = 0u;
+              if constexpr (DEG == 4) {
+                Jp = *(const uint32_t*)(cj + i * 4);
+              } else {
+                const uint16_t* c16 = (const uint16_t*)(cj + i * DEG);
+                Jp = (uint32_t)c16[0] | ((uint32_t)c16[1] << 16);
+                Jp2 = (uint32_t)c16[2];
+              }
+#pragma unroll
+              for (int d = 0; d < DEG; ++d) {
+                const uint32_t nib = (xw[d] >> sh) & 0xFu;
+                if (d < 4) T |= nib << (8 * d);
+                else T2 |= nib << (8 * (d - 4));
+              }
+              Jsum = __builtin_amdgcn_sdot4((int)0x01010101, (int)Jp, __builtin_amdgcn_sdot4((int)0x01010101, (int)Jp2, 0, false), false);
 #pragma unroll
               for (int b = 0; b < WPT; ++b) {
-                int mn = 0;
-#pragma unroll
-                for (int d = 0; d < DEG; ++d)
-                  mn = mad_i24(__builtin_amdgcn_sbfe((int)xw[d], (unsigned)(sh + b), 1u), Ji[d], mn);
-                const int e = Jsum + 2 * mn;  // dE = 2e
+                const uint32_t y = (T >> b) & 0x01010101u, y2 = (T2 >> b) & 0x01010101u;
+                const int sx = __builtin_amdgcn_sdot4((int)y2, (int)Jp2, __builtin_amdgcn_sdot4((int)y, (int)Jp, 0, false), false);
+                const int e = Jsum - 2 * sx;  // dE = 2e
                 // e <= 0 is always accepted; else u below the threshold of (T, e)
                 const uint32_t th = thr[rowb[b] + (e > 0 ? e : 0)];
                 const bool ok = ((vmask >> b) & 1u) && (e <= 0 || u[b >> 2].w[b & 3] < th);
