@@ -110,11 +110,11 @@ def launch_tag(cfg):
 # the kernel source (digest) and launch shape they were measured on; the line
 # reports null otherwise.
 PROFILED = {
-    "3d_L8_gauss_1024inst": {"kernel": "003f79b45ca92a3b", "launch": "t256_s16_spl256",
-                             "hbm_bytes_per_launch": 141092165, "valu_insts_per_launch": 1.0528e10,
+    "3d_L8_gauss_1024inst": {"kernel": "7b055d645cd8f143", "launch": "t256_s16_spl256",
+                             "hbm_bytes_per_launch": 141110243, "valu_insts_per_launch": 1.0528e10,
                              "profile": "profiles/sweep_block_kernel_3d_L8_gauss_1024inst.md"},
-    "chimera_C12_int3_512inst": {"kernel": "003f79b45ca92a3b", "launch": "t512_s16_spl256",
-                                 "hbm_bytes_per_launch": 1716481108, "valu_insts_per_launch": 1.0347e10,
+    "chimera_C12_int3_512inst": {"kernel": "7b055d645cd8f143", "launch": "t512_s16_spl256",
+                                 "hbm_bytes_per_launch": 1715107950, "valu_insts_per_launch": 9.9223e9,
                                  "profile": "profiles/sweep_block_kernel_chimera_C12_int3_512inst.md"},
 }
 
