@@ -736,6 +736,23 @@ __device__ __noinline__ void measure_step(uint32_t t_end, int N, int K, int R, i
 // task; empties the wave's queue.  Out of line, so that the sweep loop keeps
 // no registers for it.
 // ----------------------------------------------------------------------------
+// The PT swap rule between the walker carried up to rung k (energy ex) and
+// the walker at rung k + 1 (energy ey), with the draw u of (k, chain): float
+// couplings u 2^-32 < exp(-(beta_k - beta_k+1) D) in double after the float
+// pre-filter that settles all but a thin band (as for Metropolis); integer
+// couplings the threshold table of the gap D = ey - ex.
+template <int JK>
+__device__ __forceinline__ bool pt_swap(uint32_t u, typename EnergyT<JK>::T ex, typename EnergyT<JK>::T ey, int k,
+                                        const double* beta, const float* dbl2e, const uint32_t* ptthr, int ptlen) {
+  if constexpr (JK) {
+    const double D = (double)ey - (double)ex;
+    return accept_float(u, D, beta[k] - beta[k + 1], dbl2e[k]);
+  } else {
+    const int D = (int)ey - (int)ex;
+    return D <= 0 || (D <= ptlen && u < ptthr[k * ptlen + (D - 1)]);
+  }
+}
+
 // PT decisions of a step, up front (at most kPtTable temperatures): every
 // pair (k, c), c <= k, of every chain r -- the walker that sat at rung c,
 // carried up to rung k, against the walker at rung k + 1 -- decided with the
@@ -762,16 +779,7 @@ __device__ __noinline__ void pt_decide(uint32_t at_off, uint32_t energy_off, uin
     if (k * (k + 1) / 2 > idx) --k;
     const int c = idx - k * (k + 1) / 2;
     const E_t ex = energy[at[c * R + r]], ey = energy[at[(k + 1) * R + r]];
-    const uint32_t u = ptu[k * R + r];
-    bool accept;
-    if constexpr (JK) {
-      const double D = (double)ey - (double)ex;
-      accept = accept_float(u, D, beta[k] - beta[k + 1], dbl2e[k]);
-    } else {
-      const int D = (int)ey - (int)ex;
-      accept = D <= 0 || (D <= ptlen && u < ptthr[k * ptlen + (D - 1)]);
-    }
-    if (accept) atomicOr(&ptacc[k * R + r], 1u << c);
+    if (pt_swap<JK>(ptu[k * R + r], ex, ey, k, beta, dbl2e, ptthr, ptlen)) atomicOr(&ptacc[k * R + r], 1u << c);
   }
 }
 
@@ -1646,20 +1654,6 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
 
     // ---------------- step 3: parallel tempering ---------------------------------
     if (flags & kFlagPt) {
-      // the swap rule between the walker carried up to rung k (energy ex) and
-      // the walker at rung k + 1 (energy ey), with the draw u of (k, chain):
-      // u 2^-32 < exp(-(beta_k - beta_k+1) D) in double after the float
-      // pre-filter that settles all but a thin band (as for Metropolis), or
-      // the threshold table for integer couplings
-      auto pt_accept = [&](uint32_t u, E_t ex, E_t ey, int k) -> bool {
-        if constexpr (JK) {
-          const double D = (double)ey - (double)ex;
-          return accept_float(u, D, beta[k] - beta[k + 1], dbl2e[k]);
-        } else {
-          const int D = (int)ey - (int)ex;
-          return D <= 0 || (D <= U.ptlen && u < U.ptthr[k * U.ptlen + (D - 1)]);
-        }
-      };
       if (K >= kPtTableMin && K <= kPtTable) {
         // Every decision a chain's scan can meet is known up front: at rung k
         // the carried walker is one that sat at some rung c <= k before the
@@ -1737,7 +1731,7 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
                 un = ptu[(k + 1) * R + r];
                 if (k + 3 < K) ynn = at[(k + 3) * R + r];
               }
-              const bool accept = pt_accept(u, ex, ey, k);
+              const bool accept = pt_swap<JK>(u, ex, ey, k, beta, dbl2e, U.ptthr, U.ptlen);
               // rung k keeps y on a swap (x climbs on), else x (and y is carried)
               const int stay = accept ? y : x;
               at[k * R + r] = stay;
