@@ -158,6 +158,22 @@ def test_edge_cases_bit_exact(ctx, case):
     ctx.icm_remove_instance(h)
 
 
+@pytest.mark.parametrize("K,R,kind", [(21, 2, "pmJ"), (22, 2, "pmJ"), (22, 4, "gauss"), (33, 2, "gauss"),
+                                      (33, 16, "pmJ"), (34, 2, "gauss")])
+def test_pt_ladder_lengths_bit_exact(ctx, K, R, kind):
+    # ladders just below, at and above the range whose swaps are decided up
+    # front (22 to 33 temperatures), with up to 16 chains; PT at every sweep
+    rng = inputs.make_rng(73, K * 100 + R)
+    J = gridded.make_couplings(kind, inputs.SQUARE2D, 8, rng)
+    temps = inputs.geometric_temps(0.3, 2.5, K)
+    h, o = make_pair(ctx, inputs.SQUARE2D, 8, J, temps, R, 3, icm.FLAG_2A | icm.FLAG_PT, key=13)
+    ctx.icm_init_states(h)
+    o.init_hot()
+    run_both(ctx, h, o, [1, 30], f"K={K} R={R} {kind}")
+    assert ctx.icm_read_stats(h)["pt_accepts"] > 0
+    ctx.icm_remove_instance(h)
+
+
 @pytest.mark.parametrize("top,L,kind,K,R", [
     (inputs.CHIMERA, 16, "int3", 6, 2),     # 64 words: one word per lane, full wave
     (inputs.CHIMERA, 17, "gauss", 4, 2),    # 73 words: LDS shift program, chimera terms
