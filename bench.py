@@ -110,11 +110,11 @@ def launch_tag(cfg):
 # the kernel source (digest) and launch shape they were measured on; the line
 # reports null otherwise.
 PROFILED = {
-    "3d_L8_gauss_1024inst": {"kernel": "2f8788a0764a45d8", "launch": "t256_s16_spl256",
-                             "hbm_bytes_per_launch": 141098010, "valu_insts_per_launch": 1.0528e10,
+    "3d_L8_gauss_1024inst": {"kernel": "96f5acb89aab3c80", "launch": "t256_s16_spl256",
+                             "hbm_bytes_per_launch": 141144314, "valu_insts_per_launch": 1.0422e10,
                              "profile": "profiles/sweep_block_kernel_3d_L8_gauss_1024inst.md"},
-    "chimera_C12_int3_512inst": {"kernel": "2f8788a0764a45d8", "launch": "t512_s16_spl256",
-                                 "hbm_bytes_per_launch": 1714702671, "valu_insts_per_launch": 9.8817e9,
+    "chimera_C12_int3_512inst": {"kernel": "96f5acb89aab3c80", "launch": "t512_s16_spl256",
+                                 "hbm_bytes_per_launch": 1714659011, "valu_insts_per_launch": 9.8817e9,
                                  "profile": "profiles/sweep_block_kernel_chimera_C12_int3_512inst.md"},
 }
 

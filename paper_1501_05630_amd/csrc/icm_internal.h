@@ -114,6 +114,9 @@ ICM_HD int coupling_planes(int jkind, int Kc, int N, int jmin, int jmax) {
 // made exactly at the end of the colour; a wave's queue holds kExactQ tasks
 // and is emptied early when a task could fill it.
 constexpr int kExactQ = 96;
+// a float Metropolis call this close (units in the last place of float(u)
+// against the float estimate) is made again exactly
+constexpr uint32_t kCloseUlps = 512;
 
 // PT ladders of kPtTableMin to kPtTable temperatures decide every swap a
 // chain's scan could meet up front, in parallel: word (k, r) bit c = whether

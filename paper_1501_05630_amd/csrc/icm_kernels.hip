@@ -839,7 +839,7 @@ __device__ __noinline__ void exact_pass(uint32_t q_off, uint32_t sp_off, int Np,
       const int k = tau[w];
       const float lqb = ldexpf(bl2e[k], 1 - jexp);
       const float P = __builtin_amdgcn_exp2f(__builtin_fmaf(-(float)e, lqb, 32.0f));
-      if (absdiff(__float_as_uint((float)uu), __float_as_uint(P)) >= 4096u) continue;
+      if (absdiff(__float_as_uint((float)uu), __float_as_uint(P)) >= kCloseUlps) continue;
       const bool ex = e <= 0 || accept_exact(uu, (double)e * jq2, beta[k]);
       if (ex != (((guess >> b) & 1u) != 0u)) {
         corr |= 1u << b;
@@ -1101,12 +1101,16 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
               // every walker decided by the float estimate P of 2^32 exp(-beta dE)
               // (accept iff float(u) < P), no branch; `close` keeps the nearest
               // call of the task in float bit patterns (units in the last
-              // place).  4096 of them are a relative gap above 2^-12, far wider
-              // than the estimate's error (below 2^-17), so any call that close
-              // is made again exactly, in double, as the oracle does: the task
-              // is queued (rare) and exact_pass redoes those calls before the
-              // colour ends (same-colour sites do not interact, so a decision
-              // may wait until then).
+              // place).  Where the decision is open (1 <= P <= 2^32) the
+              // exponent argument 32 - e lq lies in [0, 32] and carries at most
+              // three roundings of 2^-24 relative (e and lq to float, the fma),
+              // so P is within 96 ln2 2^-24 < 2^-17.8 (plus exp2's last place)
+              // of the exact value: under 80 units in the last place with
+              // float(u)'s own rounding.  kCloseUlps = 512 of them leave a
+              // margin of six; any call that close is made again exactly, in
+              // double, as the oracle does: the task is queued (rare) and
+              // exact_pass redoes those calls before the colour ends
+              // (same-colour sites do not interact, so a decision may wait).
               uint32_t close = 0xFFFFFFFFu;
 #pragma unroll
               for (int b = 0; b < WPT; ++b) {
@@ -1122,7 +1126,7 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
                 flip |= ok ? (1u << b) : 0u;
                 acc[b] += ok ? e : 0;
               }
-              if (close < 4096u) {
+              if (close < kCloseUlps) {
                 // queue the task for the exact pass at the end of the colour
                 const uint32_t pos = atomicAdd(&exq[0], 1u);
                 exq[2 + 2 * pos] = (uint32_t)i | ((uint32_t)qt << 16);
