@@ -42,6 +42,65 @@ __device__ __forceinline__ Words4 philox4x32_10(uint32_t x0, uint32_t x1, uint32
   return r;
 }
 
+__device__ __forceinline__ uint64_t philox_m0(uint32_t x0) { return (uint64_t)0xD2511F53u * x0; }
+
+// The same function of (x0, x1, x2, x3, key) when x1, x2, x3 and the key are
+// the same in every lane of the wave and only x0 differs: the parts of the
+// first three rounds that depend on the uniform words alone go to the scalar
+// unit (readfirstlane keeps them there), leaving 73 vector operations for two
+// blocks with the same x0 instead of 81.  m0 = x0 times the first multiplier
+// (64-bit, philox_m0), which a caller drawing several blocks for one x0 forms
+// once.
+__device__ __forceinline__ Words4 philox4x32_10_lane(uint64_t m0, uint32_t x1, uint32_t x2, uint32_t x3,
+                                                     uint32_t key0, uint32_t key1) {
+  asm volatile("" : "+s"(key0), "+s"(key1));
+  // round 1: y0 = hi(M1 x2) ^ x1 ^ k0 is uniform, y2 = hi(m0) ^ x3 ^ k1 is not
+  const uint64_t p1 = (uint64_t)0xCD9E8D57u * x2;
+  const uint32_t u0 = __builtin_amdgcn_readfirstlane((uint32_t)(p1 >> 32) ^ x1 ^ key0);
+  const uint32_t u1 = (uint32_t)p1;
+  uint32_t v2 = (uint32_t)(m0 >> 32) ^ __builtin_amdgcn_readfirstlane(x3 ^ key1);
+  const uint32_t v3 = (uint32_t)m0;
+  key0 += 0x9E3779B9u;
+  key1 += 0xBB67AE85u;
+  // round 2: M0 u0 is uniform
+  const uint64_t p0 = (uint64_t)0xD2511F53u * u0;
+  const uint64_t q1 = (uint64_t)0xCD9E8D57u * v2;
+  uint32_t x0 = (uint32_t)(q1 >> 32) ^ __builtin_amdgcn_readfirstlane(u1 ^ key0);
+  v2 = v3 ^ __builtin_amdgcn_readfirstlane((uint32_t)(p0 >> 32) ^ key1);
+  x1 = (uint32_t)q1;
+  const uint32_t u3 = (uint32_t)p0;
+  key0 += 0x9E3779B9u;
+  key1 += 0xBB67AE85u;
+  // round 3: the word carried in position 3 is still uniform
+  {
+    const uint64_t a = (uint64_t)0xD2511F53u * x0;
+    const uint64_t b = (uint64_t)0xCD9E8D57u * v2;
+    x0 = __builtin_amdgcn_bitop3_b32((uint32_t)(b >> 32), x1, key0, 0x96);
+    v2 = (uint32_t)(a >> 32) ^ __builtin_amdgcn_readfirstlane(u3 ^ key1);
+    x1 = (uint32_t)b;
+    x3 = (uint32_t)a;
+    key0 += 0x9E3779B9u;
+    key1 += 0xBB67AE85u;
+  }
+  x2 = v2;
+#pragma unroll
+  for (int round = 3; round < 10; ++round) {
+    const uint64_t a = (uint64_t)0xD2511F53u * x0;
+    const uint64_t b = (uint64_t)0xCD9E8D57u * x2;
+    const uint32_t y0 = __builtin_amdgcn_bitop3_b32((uint32_t)(b >> 32), x1, key0, 0x96);
+    const uint32_t y2 = __builtin_amdgcn_bitop3_b32((uint32_t)(a >> 32), x3, key1, 0x96);
+    x1 = (uint32_t)b;
+    x3 = (uint32_t)a;
+    x0 = y0;
+    x2 = y2;
+    key0 += 0x9E3779B9u;
+    key1 += 0xBB67AE85u;
+  }
+  Words4 r;
+  r.w[0] = x0; r.w[1] = x1; r.w[2] = x2; r.w[3] = x3;
+  return r;
+}
+
 enum : uint32_t { kStreamMetro = 0, kStreamInit = 1, kStreamIcm = 2, kStreamPt = 3, kStreamPerc = 4 };
 
 // ----------------------------------------------------------------------------

@@ -4,18 +4,24 @@
 // instance with all its temperatures and replicas), n simulation steps of the
 // paper's isoenergetic cluster algorithm (steps 1, 2a, 2b, 3) with the unit
 // resident in LDS (spins bit-packed, 32 walkers per word):
-//   step 1   checkerboard Metropolis: each thread updates the four walkers of
-//            one Philox quad at one site with one Philox block;
+//   step 1   checkerboard Metropolis: a lane's task is one site and the
+//            walkers of one or two Philox quads; the field of each walker from
+//            the xor of the site's word with its neighbour words (24-bit
+//            integer multiply-adds for float couplings, byte dot products for
+//            int8 couplings); float couplings decide by a float estimate, and
+//            the rare calls it cannot make are redone exactly in double;
 //   step 2a  spin reversal recorded as a per-walker gauge bit;
-//   step 2b  one wavefront per cluster move: q-mask by bit compare, n_minus by
-//            popcount + DPP wave reduction, seed by ballot counts, the seed's
-//            cluster grown breadth-first with the frontier compacted by ballot +
-//            mbcnt, flipped in both replicas, the energy updated exactly from the
-//            bonds that leave the cluster; for the label readout the full
-//            component labelling by union-find (LDS atomicMin hooking, pointer
-//            jumping);
+//   step 2b  on the walker-major view of the spins (in-place 32x32 bit
+//            transposes), a lane group per move: q-mask words by xor,
+//            n_minus by popcounts, the seed by a scan, the seed's cluster grown
+//            as a bitset flood fill (a whole frontier per level), flipped in
+//            both replicas by word xor, the energy change from the bonds that
+//            leave the cluster; union-find labelling only for the label
+//            readout;
 //   step 3   parallel tempering: one lane per chain scans the neighbouring
-//            temperature pairs in ascending order.
+//            temperature pairs in ascending order (long ladders decide every
+//            pair the scan can meet up front, in parallel).
+
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -120,6 +126,53 @@ __device__ __forceinline__ T transpose_sum(T (&v)[NV]) {
   return wave_rest<NV>(transpose_stages<NV>(v));
 }
 
+// The transposed stages for integers by DPP inside 16-lane rows, no LDS
+// permute: partners at lane distance 1 and 2 (quad permutes), then 8 (row
+// rotate by 8).  Stage s pairs lanes that differ in bit m_s = 1, 2, 8 of the
+// lane id; after the stages NV = 2, 4, 8 needs, lane l holds the sum over its
+// NV-lane group (the lanes that differ from l in those bits) of index
+// dpp_index<NV>(l): bit 0, bit 1 and bit 3 of l as the index's bits 0, 1, 2.
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+
+template <int NV>
+__device__ __forceinline__ int dpp_index(int lane) {
+  return (lane & (NV > 2 ? 3 : 1)) | (NV > 4 ? (lane >> 1) & 4 : 0);
+}
+
+template <int NV>
+__device__ __forceinline__ int dpp_transpose_stages(int (&v)[NV]) {
+  static_assert(NV == 2 || NV == 4 || NV == 8, "two, four or eight values per lane");
+  const int lane = lane_id();
+  {
+    const bool hi = (lane & 1) != 0;
+#pragma unroll
+    for (int j = 0; j < NV / 2; ++j) {
+      const int a = v[2 * j] + dpp_i<0xB1>(v[2 * j]);              // quad_perm [1,0,3,2]
+      const int b = v[2 * j + 1] + dpp_i<0xB1>(v[2 * j + 1]);
+      v[j] = hi ? b : a;
+    }
+  }
+  if constexpr (NV >= 4) {
+    const bool hi = (lane & 2) != 0;
+#pragma unroll
+    for (int j = 0; j < NV / 4; ++j) {
+      const int a = v[2 * j] + dpp_i<0x4E>(v[2 * j]);              // quad_perm [2,3,0,1]
+      const int b = v[2 * j + 1] + dpp_i<0x4E>(v[2 * j + 1]);
+      v[j] = hi ? b : a;
+    }
+  }
+  if constexpr (NV == 8) {
+    const bool hi = (lane & 8) != 0;
+    const int a = v[0] + dpp_i<0x128>(v[0]);                       // row_ror:8
+    const int b = v[1] + dpp_i<0x128>(v[1]);
+    v[0] = hi ? b : a;
+  }
+  return v[0];
+}
+
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
@@ -198,29 +251,38 @@ struct EnergyT<1> { using T = double; };
 // lane takes at most 32 sites of a colour).  Integer sums throughout.  narrow
 // (float couplings): a lane took at most nchunk sites with nchunk DEG WPT <
 // 256, so |acc| < 2^31 / WPT (|e| < DEG 2^23) and the WPT-lane group sums of
-// the butterfly stages still fit an int; only the rest of the wave is summed
-// in double.
+// the butterfly stages still fit an int; the groups are then added into the
+// double energies one by one (LDS atomics, exact in any order).
 template <int JK, int WPT>
 __device__ __forceinline__ void flush_energy(int (&acc)[WPT], typename EnergyT<JK>::T* en, int jexp,
                                              bool narrow) {
   const int lane = lane_id();
   if constexpr (JK) {
-    double tot;  // integers below 2^53: exact in any order
     if (narrow) {
-      tot = wave_rest<WPT>((double)transpose_stages<WPT>(acc));
+      // the WPT-lane group sums by DPP, then every lane adds its group's sum
+      // (WPT = 8: eight lanes per walker); each addition is exact (integer
+      // multiples of 2^(1 - jexp) below 2^53 ulps), so their order is free
+      const int g = dpp_transpose_stages<WPT>(acc);
+      if (g != 0) atomicAdd(&en[dpp_index<WPT>(lane)], ldexp((double)g, 1 - jexp));
     } else {
-      double v[WPT];
+      double v[WPT];  // integers below 2^53: exact in any order
 #pragma unroll
       for (int b = 0; b < WPT; ++b) v[b] = (double)acc[b];
-      tot = transpose_sum<WPT>(v);
+      const double tot = transpose_sum<WPT>(v);
+      if (lane < WPT && tot != 0.0) atomicAdd(&en[lane], ldexp(tot, 1 - jexp));
     }
-    if (lane < WPT && tot != 0.0) atomicAdd(&en[lane], ldexp(tot, 1 - jexp));
   } else {
-    int v[WPT];
-#pragma unroll
-    for (int b = 0; b < WPT; ++b) v[b] = acc[b];
-    const int tot = transpose_sum<WPT>(v);
-    if (lane < WPT && tot != 0) atomicAdd(&en[lane], 2 * tot);
+    // four-lane group sums by DPP, then the four groups of each 16-lane row
+    // (rotations by 4 and 8 keep a lane's index), and one lane per row and
+    // walker adds the row's sum
+    int v = dpp_transpose_stages<WPT>(acc);
+    if constexpr (WPT == 4) {
+      v += dpp_i<0x124>(v);  // row_ror:4
+      v += dpp_i<0x128>(v);  // row_ror:8
+      if ((lane & 12) == 0 && v != 0) atomicAdd(&en[lane & 3], 2 * v);
+    } else {
+      if (v != 0) atomicAdd(&en[dpp_index<WPT>(lane)], 2 * v);
+    }
   }
 }
 
@@ -980,7 +1042,7 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
   }
   __syncthreads();
 
-  const uint32_t t0 = *U.sweep;
+  const uint32_t t0 = (uint32_t)uniform((int)*U.sweep);
   const uint32_t flags = U.flags, seed = U.seed, key = U.key;
   const int lane = lane_id(), wave = wave_id(), nwaves = nthr >> 6;
   uint32_t metro_cnt = 0;  // accepted flips of this lane, flushed once per sweep
@@ -1013,6 +1075,7 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
         const int tb = (int)(((long long)ntasks * wave) / nwaves);
         const int te = (int)(((long long)ntasks * (wave + 1)) / nwaves);
         int cur_q = -1;
+        int qn = 0;  // tasks this wave has queued for the exact pass (uniform)
         int acc[WPT];  // per lane: sum of e over its accepted flips (dE = 2 e in field units)
         // per walker of the current task's quads (uniform): float couplings
         // the acceptance exponent's scale, integer couplings the threshold row;
@@ -1030,10 +1093,12 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
           if (task == tb + (((te - tb) * 3) >> 3)) __builtin_amdgcn_s_setprio(1);
           // the queue holds room for every lane of the next task
           if constexpr (JK) {
-            if (uniform((int)__hip_atomic_load(&exq[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT)) > kExactQ - 64)
+            if (qn > kExactQ - 64) {
               exact_pass<DEG, QPT>(lay.exq + 4u * (uint32_t)wave * (2 + 2 * kExactQ), lay.sp, Np, lay.nbr,
                                 TL ? nullptr : U.nbr, lay.coup, TL ? nullptr : (const int32_t*)U.coup, lay.tau,
                                 lay.beta, lay.bl2e, lay.energy, lay.stats, W, Wq, U.jexp, t, seed, key);
+              qn = 0;
+            }
           }
           if (qt != cur_q) {
             if (cur_q >= 0) {
@@ -1065,6 +1130,7 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
             }
           }
           const int j = chunk * 64 + lane;
+          bool queued = false;
           if (j < Nc) {
             const int q0 = QPT * qt;
             const int g = q0 >> 3, sh = 4 * (q0 & 7);
@@ -1076,9 +1142,10 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
 #pragma unroll
             for (int d = 0; d < DEG; ++d) nw[d] = row[nbr[i * DEG + d]];
             Words4 u[QPT];
+            const uint64_t m0 = philox_m0((uint32_t)i);
 #pragma unroll
             for (int h = 0; h < QPT; ++h)
-              if (h == 0 || q0 + h < Wq) u[h] = philox4x32_10((uint32_t)i, t, (uint32_t)(q0 + h), kStreamMetro, seed, key);
+              if (h == 0 || q0 + h < Wq) u[h] = philox4x32_10_lane(m0, t, (uint32_t)(q0 + h), kStreamMetro, seed, key);
               else u[h] = u[0];
             // e = s_i h = sum_d J_d s_i s_d = sum J - 2 sum_d J_d x_d, x_d = 1 where
             // the spin and its d-neighbour differ (own word xor neighbour word,
@@ -1126,7 +1193,8 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
                 flip |= ok ? (1u << b) : 0u;
                 acc[b] += ok ? e : 0;
               }
-              if (close < kCloseUlps) {
+              queued = close < kCloseUlps;
+              if (queued) {
                 // queue the task for the exact pass at the end of the colour
                 const uint32_t pos = atomicAdd(&exq[0], 1u);
                 exq[2 + 2 * pos] = (uint32_t)i | ((uint32_t)qt << 16);
@@ -1168,10 +1236,11 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
             if (flip) atomicXor(&row[i], flip << sh);
             metro_cnt += __popc(flip);
           }
+          if constexpr (JK) qn += (int)__popcll(__builtin_amdgcn_ballot_w64(queued));
         }
         if (cur_q >= 0) flush_energy<JK, WPT>(acc, energy + WPT * cur_q, U.jexp, narrow);
         if constexpr (JK) {
-          if (uniform((int)__hip_atomic_load(&exq[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT)) > 0)
+          if (qn > 0)
             exact_pass<DEG, QPT>(lay.exq + 4u * (uint32_t)wave * (2 + 2 * kExactQ), lay.sp, Np, lay.nbr,
                                 TL ? nullptr : U.nbr, lay.coup, TL ? nullptr : (const int32_t*)U.coup, lay.tau,
                                 lay.beta, lay.bl2e, lay.energy, lay.stats, W, Wq, U.jexp, t, seed, key);
