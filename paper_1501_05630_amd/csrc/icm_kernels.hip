@@ -303,6 +303,20 @@ __device__ __forceinline__ uint32_t absdiff(uint32_t a, uint32_t b) {
   return r;
 }
 
+// flip |= bit and acc += e in the lanes of the lane mask m only (m a subset of
+// the active lanes; the others keep both values): exec is narrowed to m around
+// one OR and one add, where selects would cost two more operations.
+__device__ __forceinline__ void accept_where(uint64_t m, uint32_t bit, uint32_t& flip, int e, int& acc) {
+  uint64_t saved;
+  asm volatile(
+      "s_and_saveexec_b64 %0, %3\n\t"
+      "v_or_b32 %1, %4, %1\n\t"
+      "v_add_u32 %2, %5, %2\n\t"
+      "s_mov_b64 exec, %0"
+      : "=&s"(saved), "+v"(flip), "+v"(acc)
+      : "s"(m), "s"(bit), "v"(e));
+}
+
 // Index of the lowest set bit, all ones for 0 (one v_ffbl_b32).
 __device__ __forceinline__ uint32_t lowest_bit(uint32_t x) {
   uint32_t r;
@@ -761,7 +775,7 @@ __device__ __noinline__ void measure_step(uint32_t t_end, int N, int K, int R, i
       const uint32_t qi = (qw[i >> 5] >> (i & 31)) & 1u;
 #pragma unroll
       for (int d = 0; d < DEG; ++d) {
-        const int j = nbr[i * DEG + d];
+        const int j = nbr_global ? nbr[i * DEG + d] : nbr[i * DEG + d] >> 2;  // LDS copy: byte offsets
         // each bond once: lattices from the +axis slots; chimera in-cell bonds
         // from u < 4, inter-cell bonds from the "next" slot if present
         const bool bond = topo == 2 ? (((i & 7) < 4 && d < 4) || (d == 5 && j != i)) : (d & 1) == 0;
@@ -878,7 +892,7 @@ __device__ __noinline__ void exact_pass(uint32_t q_off, uint32_t sp_off, int Np,
     int Ji[DEG], Jsum = 0;
 #pragma unroll
     for (int d = 0; d < DEG; ++d) {
-      xw[d] = row[nbr[i * DEG + d]] ^ own;
+      xw[d] = row[nbr_global ? nbr[i * DEG + d] : nbr[i * DEG + d] >> 2] ^ own;  // LDS copy: byte offsets
       Ji[d] = cf[i * DEG + d];
       Jsum += Ji[d];
     }
@@ -935,7 +949,8 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
                                    JK ? 0 : U.jpl, (int)(blockDim.x >> 6));
 
   uint32_t* sp = (uint32_t*)(lds + lay.sp);
-  // TL: tables in LDS; otherwise read-only global memory (cached in L1/L2)
+  // TL: tables in LDS (neighbours as byte offsets 4 j); otherwise read-only
+  // global memory (cached in L1/L2, neighbours as site indices j)
   const uint16_t* nbr = TL ? (const uint16_t*)(lds + lay.nbr) : U.nbr;
   const uint16_t* clist = TL ? (const uint16_t*)(lds + lay.clist) : U.clist;
   const int8_t* cj = TL ? (const int8_t*)(lds + lay.coup) : (const int8_t*)U.coup;
@@ -972,7 +987,10 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
   if (TL) {
     uint16_t* nbr_w = (uint16_t*)(lds + lay.nbr);
     uint16_t* clist_w = (uint16_t*)(lds + lay.clist);
-    for (int x = tid; x < N * DEG; x += nthr) nbr_w[x] = U.nbr[x];
+    // the LDS copy holds byte offsets (4 j) within a row of the spin image, so
+    // the Metropolis task forms a neighbour word's address in one add (units
+    // have at most kMaxSites = 4096 sites: 4 j fits 16 bits)
+    for (int x = tid; x < N * DEG; x += nthr) nbr_w[x] = (uint16_t)(U.nbr[x] << 2);
     for (int x = tid; x < N; x += nthr) clist_w[x] = U.clist[x];
     if (JK) {
       int32_t* cf_w = (int32_t*)(lds + lay.coup);
@@ -1140,7 +1158,8 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
             const uint32_t own = row[i];
             uint32_t nw[DEG];
 #pragma unroll
-            for (int d = 0; d < DEG; ++d) nw[d] = row[nbr[i * DEG + d]];
+            for (int d = 0; d < DEG; ++d)
+              nw[d] = TL ? *(const uint32_t*)((const unsigned char*)row + nbr[i * DEG + d]) : row[nbr[i * DEG + d]];
             Words4 u[QPT];
             const uint64_t m0 = philox_m0((uint32_t)i);
 #pragma unroll
@@ -1188,10 +1207,10 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
                 const int e = Jsum + 2 * mn;  // dE = e 2^(1 - jexp)
                 const float P = __builtin_amdgcn_exp2f(__builtin_fmaf(-(float)e, lq[b], 32.0f));
                 const float uf = (float)u[b >> 2].w[b & 3];
-                const bool ok = ((vmask >> b) & 1u) && uf < P;
+                // the lanes that accept, as a lane mask straight from the compare
+                const uint64_t ok = __builtin_amdgcn_ballot_w64(uf < P) & (0ull - (uint64_t)((vmask >> b) & 1u));
                 close = min(close, absdiff(__float_as_uint(uf), __float_as_uint(P)));
-                flip |= ok ? (1u << b) : 0u;
-                acc[b] += ok ? e : 0;
+                accept_where(ok, 1u << b, flip, e, acc[b]);
               }
               queued = close < kCloseUlps;
               if (queued) {
@@ -1228,9 +1247,10 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
                 const int e = Jsum - 2 * sx;  // dE = 2e
                 // e <= 0 is always accepted; else u below the threshold of (T, e)
                 const uint32_t th = thr[rowb[b] + (e > 0 ? e : 0)];
-                const bool ok = ((vmask >> b) & 1u) && (e <= 0 || u[b >> 2].w[b & 3] < th);
-                flip |= ok ? (1u << b) : 0u;
-                acc[b] += ok ? e : 0;
+                const uint64_t ok = (__builtin_amdgcn_ballot_w64(e <= 0) |
+                                     __builtin_amdgcn_ballot_w64(u[b >> 2].w[b & 3] < th)) &
+                                    (0ull - (uint64_t)((vmask >> b) & 1u));
+                accept_where(ok, 1u << b, flip, e, acc[b]);
               }
             }
             if (flip) atomicXor(&row[i], flip << sh);
@@ -1426,7 +1446,7 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
                 if (!inmask(i)) continue;
 #pragma unroll
                 for (int d = 0; d < DEG; ++d) {
-                  const int jn = nbr[i * DEG + d];
+                  const int jn = TL ? nbr[i * DEG + d] >> 2 : nbr[i * DEG + d];
                   if (jn > i && inmask(jn)) uf_union(parent, i, jn);
                 }
               }
