@@ -39,10 +39,10 @@ namespace icm {
 // DPP: butterfly inside each quad, then half-row and row mirrors give every
 // lane its 16-lane row sum; the four row sums are read back with readlane.
 __device__ __forceinline__ int dpp_row_sum(int v) {
-  v += __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
-  v += __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
-  v += __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false);  // row_half_mirror
-  v += __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, false);  // row_mirror
+  v += __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true);   // quad_perm [1,0,3,2]
+  v += __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true);   // quad_perm [2,3,0,1]
+  v += __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, true);  // row_half_mirror
+  v += __builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, true);  // row_mirror
   return v;
 }
 
@@ -55,8 +55,8 @@ __device__ __forceinline__ int wave_sum(int v) {
 template <int CTRL>
 __device__ __forceinline__ double dpp_d(double v) {
   const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
@@ -81,10 +81,10 @@ __device__ __forceinline__ double wave_sum(double v) {
 // lane is broadcast into the rows after it (row_bcast 15 and 31).
 __device__ __forceinline__ int wave_exclusive_scan(int v) {
   int x = v;
-  x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xF, 0xF, false);  // row_shr:1
-  x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xF, 0xF, false);  // row_shr:2
-  x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xF, 0xF, false);  // row_shr:4
-  x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xF, 0xF, false);  // row_shr:8
+  x += __builtin_amdgcn_mov_dpp(x, 0x111, 0xF, 0xF, true);  // row_shr:1
+  x += __builtin_amdgcn_mov_dpp(x, 0x112, 0xF, 0xF, true);  // row_shr:2
+  x += __builtin_amdgcn_mov_dpp(x, 0x114, 0xF, 0xF, true);  // row_shr:4
+  x += __builtin_amdgcn_mov_dpp(x, 0x118, 0xF, 0xF, true);  // row_shr:8
   x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xA, 0xF, false);  // row_bcast:15 into rows 1, 3
   x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xC, 0xF, false);  // row_bcast:31 into rows 2, 3
   return x - v;
@@ -134,7 +134,7 @@ __device__ __forceinline__ T transpose_sum(T (&v)[NV]) {
 // dpp_index<NV>(l): bit 0, bit 1 and bit 3 of l as the index's bits 0, 1, 2.
 template <int CTRL>
 __device__ __forceinline__ int dpp_i(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, true);
 }
 
 template <int NV>
@@ -338,14 +338,24 @@ __device__ __forceinline__ int boundary_sum(uint32_t bb, uint32_t anti, int w, i
   const int base = 32 * w * DEG + d;
   int s = 0, slots = 0;
   while (bb) {
+    // the round's four positions and signs (-1 where anti-aligned) first, then
+    // its four loads together, and only then the sums (the scheduling barrier
+    // keeps the loads from being spread between the multiply-adds)
+    int pos[4], sg[4], v[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int pos = max((int)lowest_bit(bb), 0);
+      pos[u] = max((int)lowest_bit(bb), 0);
       bb &= bb - 1u;
-      const int x = base + pos * DEG;
-      const int v = JK ? cf[x] : (int)cj[x];
-      s = mad_i24(v, mad_i24((int)bit_of(anti, pos), -2, 1), s);  // sign -1 where anti-aligned
+      sg[u] = mad_i24((int)bit_of(anti, pos[u]), -2, 1);
     }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int x = base + pos[u] * DEG;
+      v[u] = JK ? cf[x] : (int)cj[x];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s = mad_i24(v[u], sg[u], s);
     slots += 4;
   }
   const int v0 = JK ? cf[base] : (int)cj[base];
@@ -423,9 +433,9 @@ __device__ __forceinline__ uint32_t chimera_in_cell(uint32_t f) {
 // at 16 words = 8 planes).  Both directions of every axis are taken, so the
 // result is the full neighbourhood of the frontier.
 __device__ __forceinline__ uint32_t cube8_expand(uint32_t f) {
-  const uint32_t fp = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)f, 0xB1, 0xF, 0xF, false);  // w ^ 1
-  const uint32_t zp = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)f, 0x12E, 0xF, 0xF, false); // row_ror:14
-  const uint32_t zm = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)f, 0x122, 0xF, 0xF, false); // row_ror:2
+  const uint32_t fp = (uint32_t)__builtin_amdgcn_mov_dpp((int)f, 0xB1, 0xF, 0xF, true);  // w ^ 1
+  const uint32_t zp = (uint32_t)__builtin_amdgcn_mov_dpp((int)f, 0x12E, 0xF, 0xF, true); // row_ror:14
+  const uint32_t zm = (uint32_t)__builtin_amdgcn_mov_dpp((int)f, 0x122, 0xF, 0xF, true); // row_ror:2
   const uint32_t xp = ((f >> 1) & 0x7F7F7F7Fu) | ((f << 7) & 0x80808080u);
   const uint32_t xm = ((f << 1) & 0xFEFEFEFEu) | ((f >> 7) & 0x01010101u);
   const uint32_t yp = (f >> 8) | (fp << 24);
@@ -437,13 +447,13 @@ __device__ __forceinline__ uint32_t cube8_expand(uint32_t f) {
 // The six neighbour words of the 8^3 layout above, in neighbour-table order
 // (+x, -x, +y, -y, +z, -z): out[d] bit b = F at the d-neighbour of site 32 w + b.
 __device__ __forceinline__ void cube8_dirs(uint32_t f, uint32_t out[6]) {
-  const uint32_t fp = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)f, 0xB1, 0xF, 0xF, false);
+  const uint32_t fp = (uint32_t)__builtin_amdgcn_mov_dpp((int)f, 0xB1, 0xF, 0xF, true);
   out[0] = ((f >> 1) & 0x7F7F7F7Fu) | ((f << 7) & 0x80808080u);
   out[1] = ((f << 1) & 0xFEFEFEFEu) | ((f >> 7) & 0x01010101u);
   out[2] = (f >> 8) | (fp << 24);
   out[3] = (f << 8) | (fp >> 24);
-  out[4] = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)f, 0x12E, 0xF, 0xF, false);  // word w + 2
-  out[5] = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)f, 0x122, 0xF, 0xF, false);  // word w - 2
+  out[4] = (uint32_t)__builtin_amdgcn_mov_dpp((int)f, 0x12E, 0xF, 0xF, true);  // word w + 2
+  out[5] = (uint32_t)__builtin_amdgcn_mov_dpp((int)f, 0x122, 0xF, 0xF, true);  // word w - 2
 }
 
 
@@ -469,8 +479,8 @@ __device__ __forceinline__ void chimera_inter(uint32_t f, int lane, const Chimer
   const int qd = -cs.qv - (cs.rv ? 1 : 0), rd = (32 - cs.rv) & 31;
   const uint32_t dn_lo = lane_fetch(f, lane + qd);
   const uint32_t dn_hi = cs.rv ? lane_fetch(f, lane + qd + 1) : 0u;
-  const uint32_t fr = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)f, 0x130, 0xF, 0xF, false);  // lane + 1
-  const uint32_t fl = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)f, 0x138, 0xF, 0xF, false);  // lane - 1
+  const uint32_t fr = (uint32_t)__builtin_amdgcn_mov_dpp((int)f, 0x130, 0xF, 0xF, true);  // lane + 1
+  const uint32_t fl = (uint32_t)__builtin_amdgcn_mov_dpp((int)f, 0x138, 0xF, 0xF, true);  // lane - 1
   out[0] = (cs.rv ? __builtin_amdgcn_alignbit(up_hi, up_lo, (uint32_t)cs.rv) : up_lo) & cs.m[0];
   out[1] = (cs.rv ? __builtin_amdgcn_alignbit(dn_hi, dn_lo, (uint32_t)rd) : dn_lo) & cs.m[1];
   out[2] = __builtin_amdgcn_alignbit(fr, f, 8u) & cs.m[2];
@@ -512,12 +522,12 @@ __device__ __forceinline__ void pair_dir(bool sq, uint32_t lo, uint32_t hi, int 
       case 0: olo = __builtin_amdgcn_alignbit(hi, lo, 1u); ohi = __builtin_amdgcn_alignbit(lo, hi, 1u); break;
       case 1: olo = __builtin_amdgcn_alignbit(lo, hi, 31u); ohi = __builtin_amdgcn_alignbit(hi, lo, 31u); break;
       case 2:
-        olo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lo, 0x134, 0xF, 0xF, false);
-        ohi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)hi, 0x134, 0xF, 0xF, false);
+        olo = (uint32_t)__builtin_amdgcn_mov_dpp((int)lo, 0x134, 0xF, 0xF, true);
+        ohi = (uint32_t)__builtin_amdgcn_mov_dpp((int)hi, 0x134, 0xF, 0xF, true);
         break;
       default:
-        olo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lo, 0x13C, 0xF, 0xF, false);
-        ohi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)hi, 0x13C, 0xF, 0xF, false);
+        olo = (uint32_t)__builtin_amdgcn_mov_dpp((int)lo, 0x13C, 0xF, 0xF, true);
+        ohi = (uint32_t)__builtin_amdgcn_mov_dpp((int)hi, 0x13C, 0xF, 0xF, true);
         break;
     }
     return;
@@ -532,13 +542,13 @@ __device__ __forceinline__ void pair_dir(bool sq, uint32_t lo, uint32_t hi, int 
       ohi = ((hi << 1) & 0xFFFEFFFEu) | ((hi >> 15) & 0x00010001u);
       break;
     case 2: {
-      const uint32_t nlo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lo, 0x39, 0xF, 0xF, false);
+      const uint32_t nlo = (uint32_t)__builtin_amdgcn_mov_dpp((int)lo, 0x39, 0xF, 0xF, true);
       olo = (lo >> 16) | (hi << 16);
       ohi = (hi >> 16) | (nlo << 16);
       break;
     }
     case 3: {
-      const uint32_t phi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)hi, 0x93, 0xF, 0xF, false);
+      const uint32_t phi = (uint32_t)__builtin_amdgcn_mov_dpp((int)hi, 0x93, 0xF, 0xF, true);
       olo = (lo << 16) | (phi >> 16);
       ohi = (hi << 16) | (lo >> 16);
       break;
@@ -575,14 +585,14 @@ __device__ __forceinline__ int wt_index(int w, int j, int Np) { return (w >> 5) 
 template <int S>
 __device__ __forceinline__ uint32_t partner_row(uint32_t x) {
   if constexpr (S == 16) return (uint32_t)__builtin_amdgcn_ds_swizzle((int)x, 0x401F);  // xor 16 in 32 lanes
-  if constexpr (S == 8) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x128, 0xF, 0xF, false);  // row_ror:8
+  if constexpr (S == 8) return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x128, 0xF, 0xF, true);  // row_ror:8
   if constexpr (S == 4) {
     // lanes with bit 2 clear (banks 0, 2 of a row) read lane + 4, the others lane - 4
     const int up = __builtin_amdgcn_update_dpp(0, (int)x, 0x104, 0xF, 0x5, false);   // row_shl:4
     return (uint32_t)__builtin_amdgcn_update_dpp(up, (int)x, 0x114, 0xF, 0xA, false);  // row_shr:4
   }
-  if constexpr (S == 2) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x4E, 0xF, 0xF, false);  // quad [2,3,0,1]
-  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0xB1, 0xF, 0xF, false);                     // quad [1,0,3,2]
+  if constexpr (S == 2) return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x4E, 0xF, 0xF, true);  // quad [2,3,0,1]
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, true);                     // quad [1,0,3,2]
 }
 
 // One stage of the 32 x 32 bit transpose (lane r holds row r of the block):
@@ -641,10 +651,10 @@ __device__ __forceinline__ int group_sum(int v, int lpm) {
 // 64: the whole wave).
 __device__ __forceinline__ int group_exclusive_scan(int v, int lpm) {
   int x = v;
-  x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xF, 0xF, false);  // row_shr:1
-  x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xF, 0xF, false);  // row_shr:2
-  x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xF, 0xF, false);  // row_shr:4
-  x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xF, 0xF, false);  // row_shr:8
+  x += __builtin_amdgcn_mov_dpp(x, 0x111, 0xF, 0xF, true);  // row_shr:1
+  x += __builtin_amdgcn_mov_dpp(x, 0x112, 0xF, 0xF, true);  // row_shr:2
+  x += __builtin_amdgcn_mov_dpp(x, 0x114, 0xF, 0xF, true);  // row_shr:4
+  x += __builtin_amdgcn_mov_dpp(x, 0x118, 0xF, 0xF, true);  // row_shr:8
   if (lpm >= 32) x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xA, 0xF, false);  // row_bcast:15 into rows 1, 3
   if (lpm == 64) x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xC, 0xF, false);  // row_bcast:31 into rows 2, 3
   return x - v;
