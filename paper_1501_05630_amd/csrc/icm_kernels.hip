@@ -327,11 +327,14 @@ __device__ __forceinline__ uint32_t lowest_bit(uint32_t x) {
 // Sum over the set bits b of bb of +-J for the bond in slot d of site
 // 32 w + b (J in the coupling table's integer units): -J where replica a is
 // anti-aligned across the bond (bit b of anti set).  Four bits per round, their
-// coupling loads in flight together; a round's slot without a bit left reads
-// the bond of site 32 w (bit 0: the lowest-bit index of 0 is -1, clamped to 0),
-// a valid entry, and those reads are taken out at the end.  At most 32 bits of
-// 24-bit values, plus the same number taken out: the sum stays within an int.
-template <int JK, int DEG>
+// coupling loads in flight together; a round's slot without a bit left reads a
+// fixed entry, and those reads are taken out at the end.  The lowest-bit index
+// of 0 is -1: with the table in LDS (TL) that slot reads entry base - DEG,
+// which lies inside LDS even at the start of the table (whatever it holds is
+// read, weighed with bit 31 of anti, and taken out the same way); a table in
+// global memory clamps the index to 0 instead.  At most 32 bits of 24-bit
+// values, plus the same number taken out: the sum stays within an int.
+template <int JK, int DEG, int TL>
 __device__ __forceinline__ int boundary_sum(uint32_t bb, uint32_t anti, int w, int d, const int32_t* cf,
                                             const int8_t* cj) {
   const int cnt = (int)__popc(bb);
@@ -344,9 +347,10 @@ __device__ __forceinline__ int boundary_sum(uint32_t bb, uint32_t anti, int w, i
     int pos[4], sg[4], v[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      pos[u] = max((int)lowest_bit(bb), 0);
+      pos[u] = TL ? (int)lowest_bit(bb) : max((int)lowest_bit(bb), 0);
       bb &= bb - 1u;
-      sg[u] = mad_i24((int)bit_of(anti, pos[u]), -2, 1);
+      // the bit-field extract takes the offset mod 32 (-1: bit 31)
+      sg[u] = mad_i24((int)__builtin_amdgcn_ubfe(anti, (uint32_t)pos[u], 1u), -2, 1);
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -358,8 +362,9 @@ __device__ __forceinline__ int boundary_sum(uint32_t bb, uint32_t anti, int w, i
     for (int u = 0; u < 4; ++u) s = mad_i24(v[u], sg[u], s);
     slots += 4;
   }
-  const int v0 = JK ? cf[base] : (int)cj[base];
-  return s - (slots - cnt) * mad_i24((int)(anti & 1u), -2, 1) * v0;
+  const int e0 = TL ? base - DEG : base;  // the entry an empty slot reads
+  const int v0 = JK ? cf[e0] : (int)cj[e0];
+  return s - (slots - cnt) * mad_i24(v0, mad_i24((int)(TL ? anti >> 31 : anti & 1u), -2, 1), 0);
 }
 
 // Spin (+1/-1) of byte b of an int8 quad word.
@@ -923,7 +928,7 @@ __device__ __noinline__ void exact_pass(uint32_t q_off, uint32_t sp_off, int Np,
       const int e = Jsum + 2 * mn;
       const uint32_t uu = u[b >> 2].w[b & 3];
       const int k = tau[w];
-      const float lqb = ldexpf(bl2e[k], 1 - jexp);
+      const float lqb = bl2e[k];
       const float P = __builtin_amdgcn_exp2f(__builtin_fmaf(-(float)e, lqb, 32.0f));
       if (absdiff(__float_as_uint((float)uu), __float_as_uint(P)) >= kCloseUlps) continue;
       const bool ex = e <= 0 || accept_exact(uu, (double)e * jq2, beta[k]);
@@ -1021,7 +1026,9 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
   for (int x = tid; x < K * R; x += nthr) at[x] = U.at[x];
   for (int x = tid; x < K; x += nthr) {
     beta[x] = U.beta[x];
-    bl2e[x] = U.bl2e[x];
+    // float couplings: beta log2 e times 2^(1 - jexp), the factor of e (the
+    // field in units of 2^-jexp) in the acceptance exponent; exact (a power of 2)
+    bl2e[x] = JK ? ldexpf(U.bl2e[x], 1 - U.jexp) : U.bl2e[x];
     // PT pre-filter factor: the gap of neighbouring betas times log2 e, rounded once
     dbl2e[x] = x + 1 < K ? (float)((U.beta[x] - U.beta[x + 1]) * 1.4426950408889634) : 0.0f;
   }
@@ -1136,13 +1143,12 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
             }
             cur_q = qt;
             if constexpr (JK) {
-              // lane b (mod WPT) looks up walker WPT qt + b and its scale; the
-              // wave then takes the values as uniforms
+              // lane b (mod WPT) looks up walker WPT qt + b's scale; the wave
+              // then takes the values as uniforms.  Walkers from W on are padding.
               const int wb = WPT * qt + (lane & (WPT - 1));
-              const int tl = wb < W ? tau[wb] : K;
-              const bool real = tl < K;
-              vmask = (uint32_t)__builtin_amdgcn_ballot_w64(real) & ((1u << WPT) - 1u);
-              const float lql = real ? ldexpf(bl2e[real ? tl : 0], 1 - U.jexp) : 0.0f;
+              const int nreal = W - WPT * qt;
+              vmask = nreal >= WPT ? (1u << WPT) - 1u : (1u << nreal) - 1u;
+              const float lql = wb < W ? bl2e[tau[wb]] : 0.0f;
 #pragma unroll
               for (int b = 0; b < WPT; ++b) lq[b] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lql), b));
             } else {
@@ -1586,7 +1592,7 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
               }
 #pragma unroll
               for (int d = 0; d < 6; ++d)
-                ib += JK ? boundary_sum<1, DEG>(bb[d], an[d], jw, d, cf, cj)
+                ib += JK ? boundary_sum<1, DEG, TL>(bb[d], an[d], jw, d, cf, cj)
                    : boundary_sum_planes(bb[d], an[d], jplw + (jw * DEG + d) * jpl, jpl);
             }
             if (chimreg) {
@@ -1621,7 +1627,7 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
               }
 #pragma unroll
               for (int d = 0; d < 6; ++d)
-                ib += JK ? boundary_sum<1, DEG>(bbs[d], ans[d], jw, d, cf, cj)
+                ib += JK ? boundary_sum<1, DEG, TL>(bbs[d], ans[d], jw, d, cf, cj)
                    : boundary_sum_planes(bbs[d], ans[d], jplw + (jw * DEG + d) * jpl, jpl);
             }
             if (latreg) {
@@ -1642,7 +1648,7 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
               }
 #pragma unroll
               for (int d = 0; d < DEG; ++d)
-                ib += JK ? boundary_sum<1, DEG>(bbs[d], ans[d], jw, d, cf, cj)
+                ib += JK ? boundary_sum<1, DEG, TL>(bbs[d], ans[d], jw, d, cf, cj)
                    : boundary_sum_planes(bbs[d], ans[d], jplw + (jw * DEG + d) * jpl, jpl);
             }
             if (pair) {
