@@ -176,6 +176,17 @@ __device__ __forceinline__ int dpp_transpose_stages(int (&v)[NV]) {
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// The lane index as a value the optimiser cannot see through: per-lane
+// constants derived from it inside one phase of the sweep (the PT scan's
+// addresses) are then formed in that phase instead of being hoisted out of
+// the sweep loop, where they would hold registers for the whole kernel and be
+// spilled (their reloads sat on the scan's serial chain).
+__device__ __forceinline__ int phase_lane() {
+  int l = (int)(threadIdx.x & 63u);
+  asm volatile("" : "+v"(l));
+  return l;
+}
+
 __device__ __forceinline__ double uniform_d(double v) {
   const long long b = __double_as_longlong(v);
   const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll));
@@ -1331,7 +1342,7 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
       transpose_image(sp, G, nw, true);
       __syncthreads();
       if (wave < iwaves) {
-        const int grp = lane / lpm, li = lane - grp * lpm;
+        const int grp = lane >> (31 - __builtin_clz(lpm)), li = lane & (lpm - 1);  // lpm: 16, 32 or 64
         uint32_t* gsl = (uint32_t*)(lds + lay.slots) + (wave * P + grp) * sw;  // my group's slot
         uint32_t* gmc = gsl + 2 * (nw + 2);
         uint32_t* gaw = gmc + 2 * nw;
@@ -1346,7 +1357,8 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
           int a = 0, b = 0;
           uint32_t gx = 0u, um = 0u;
           if (live) {
-            const int k = mv / half, p2 = mv - k * half;
+            // (half is almost always 1 or 2: a shift instead of a division)
+            const int k = half == 1 ? mv : (half == 2 ? mv >> 1 : mv / half), p2 = mv - k * half;
             a = at[k * R + 2 * p2];
             b = at[k * R + 2 * p2 + 1];
             gx = (uint32_t)(gauge[a] ^ gauge[b]);
@@ -1774,7 +1786,7 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
                       lay.ptacc, lay.beta, lay.dbl2e, U.ptthr, U.ptlen, K, R);
         __syncthreads();
         if (wave == 0) {
-          const int r = lane;
+          const int r = phase_lane();
           int acc_pt = 0;
           __builtin_amdgcn_s_setprio(3);
           if (r < R) {
@@ -1818,7 +1830,7 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
         // its energy stay in registers, rung k is final once decided, and the
         // next rung's walker, energy and draw are read ahead.
         if (wave == 0) {
-          const int r = lane;
+          const int r = phase_lane();
           int acc_pt = 0;
           __builtin_amdgcn_s_setprio(3);  // one serial chain: first in line on its SIMD
           if (r < R && K > 1) {
