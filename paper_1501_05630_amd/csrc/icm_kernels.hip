@@ -959,10 +959,11 @@ __device__ __noinline__ void exact_pass(uint32_t q_off, uint32_t sp_off, int Np,
 
 // ----------------------------------------------------------------------------
 // The fused sweep-block kernel.  JK: 0 = int8 couplings, 1 = float couplings.
-// DEG: neighbour slots (4 for square2d, 6 otherwise).  One workgroup runs one
-// unit; its spins live bit-packed in LDS for the whole block of sweeps.
+// DEG: neighbour slots (4 for square2d, 6 otherwise).  TL: tables in LDS.
+// LAY: the cluster-move layout (kLayAny: chosen per unit).  One workgroup runs
+// one unit; its spins live bit-packed in LDS for the whole block of sweeps.
 // ----------------------------------------------------------------------------
-template <int JK, int DEG, int TL>
+template <int JK, int DEG, int TL, int LAY>
 __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __restrict__ units,
                                                           uint32_t n_sweeps, int icm_slots) {
   using E_t = typename EnergyT<JK>::T;
@@ -1328,12 +1329,14 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
       const int nterm = lattice_terms(U.topo);
       const int* tshift = (const int*)(lds + lay.terms);
       const uint32_t* tmask = (const uint32_t*)(lds + lay.terms) + kMaxTerms;
-      const bool chim = U.topo == 2;
-      const bool cube8 = DEG == 6 && U.topo == 1 && U.L == 8;  // lpm = 16: one word per lane
-      const bool chimreg = DEG == 6 && chim && nw <= 64;        // one word per lane
-      const bool latreg = !chim && !cube8 && nw <= 64;  // periodic lattice, one word per lane
-      const bool sq64 = DEG == 4 && U.topo == 0 && U.L == 64;    // two words per lane
-      const bool cube16 = DEG == 6 && U.topo == 1 && U.L == 16;
+      // a build for one layout knows it at compile time and drops the others
+      const bool chim = LAY == kLayChimReg || (LAY == kLayAny && U.topo == 2);
+      const bool cube8 = LAY == kLayCube8 ||
+                         (LAY == kLayAny && DEG == 6 && U.topo == 1 && U.L == 8);  // lpm = 16: one word per lane
+      const bool chimreg = LAY == kLayChimReg || (LAY == kLayAny && DEG == 6 && chim && nw <= 64);  // one word per lane
+      const bool latreg = LAY == kLayAny && !chim && !cube8 && nw <= 64;  // periodic lattice, one word per lane
+      const bool sq64 = LAY == kLayAny && DEG == 4 && U.topo == 0 && U.L == 64;  // two words per lane
+      const bool cube16 = LAY == kLayAny && DEG == 6 && U.topo == 1 && U.L == 16;
       const bool pair = sq64 || cube16;
       const bool record = (flags & kFlagRecord) && s + 1 == n_sweeps;
       // the cluster moves are short dependent chains (growth levels, set-up
@@ -2036,25 +2039,35 @@ __global__ void __launch_bounds__(256) overlap_kernel(const uint32_t* __restrict
 // ----------------------------------------------------------------------------
 extern "C" {
 
-int icmk_launch_sweep(const icm::UnitDesc* d_units, int n_units, int jkind, int deg, int tables,
+int icmk_launch_sweep(const icm::UnitDesc* d_units, int n_units, int jkind, int deg, int tables, int layout,
                       uint32_t n_sweeps, int threads, int icm_slots, size_t lds_bytes,
                       hipStream_t stream) {
   if (n_units <= 0) return 0;
   dim3 grid(n_units), block(threads);
-#define ICM_LAUNCH(JK, DEG, TL)                                                            \
-  hipLaunchKernelGGL((icm::sweep_block_kernel<JK, DEG, TL>), grid, block, lds_bytes, stream, \
+#define ICM_LAUNCH(JK, DEG, TL, LAY)                                                            \
+  hipLaunchKernelGGL((icm::sweep_block_kernel<JK, DEG, TL, LAY>), grid, block, lds_bytes, stream, \
                      d_units, n_sweeps, icm_slots)
+  // the layout builds exist for 6 slots with tables in LDS (what those units use)
+  const int lay = (deg == 6 && tables) ? layout : icm::kLayAny;
   const int sel = (jkind ? 4 : 0) + (deg == 6 ? 2 : 0) + (tables ? 1 : 0);
-  switch (sel) {
-    case 0: ICM_LAUNCH(0, 4, 0); break;
-    case 1: ICM_LAUNCH(0, 4, 1); break;
-    case 2: ICM_LAUNCH(0, 6, 0); break;
-    case 3: ICM_LAUNCH(0, 6, 1); break;
-    case 4: ICM_LAUNCH(1, 4, 0); break;
-    case 5: ICM_LAUNCH(1, 4, 1); break;
-    case 6: ICM_LAUNCH(1, 6, 0); break;
-    case 7: ICM_LAUNCH(1, 6, 1); break;
-    default: return (int)hipErrorInvalidValue;
+  if (lay == icm::kLayCube8) {
+    if (jkind) ICM_LAUNCH(1, 6, 1, icm::kLayCube8);
+    else ICM_LAUNCH(0, 6, 1, icm::kLayCube8);
+  } else if (lay == icm::kLayChimReg) {
+    if (jkind) ICM_LAUNCH(1, 6, 1, icm::kLayChimReg);
+    else ICM_LAUNCH(0, 6, 1, icm::kLayChimReg);
+  } else {
+    switch (sel) {
+      case 0: ICM_LAUNCH(0, 4, 0, icm::kLayAny); break;
+      case 1: ICM_LAUNCH(0, 4, 1, icm::kLayAny); break;
+      case 2: ICM_LAUNCH(0, 6, 0, icm::kLayAny); break;
+      case 3: ICM_LAUNCH(0, 6, 1, icm::kLayAny); break;
+      case 4: ICM_LAUNCH(1, 4, 0, icm::kLayAny); break;
+      case 5: ICM_LAUNCH(1, 4, 1, icm::kLayAny); break;
+      case 6: ICM_LAUNCH(1, 6, 0, icm::kLayAny); break;
+      case 7: ICM_LAUNCH(1, 6, 1, icm::kLayAny); break;
+      default: return (int)hipErrorInvalidValue;
+    }
   }
 #undef ICM_LAUNCH
   if (deg != 4 && deg != 6) return (int)hipErrorInvalidValue;
@@ -2063,12 +2076,15 @@ int icmk_launch_sweep(const icm::UnitDesc* d_units, int n_units, int jkind, int 
 
 int icmk_set_lds_limit(size_t bytes) {
   hipError_t e = hipSuccess;
-  const void* fns[8] = {
-      (const void*)icm::sweep_block_kernel<0, 4, 0>, (const void*)icm::sweep_block_kernel<0, 4, 1>,
-      (const void*)icm::sweep_block_kernel<0, 6, 0>, (const void*)icm::sweep_block_kernel<0, 6, 1>,
-      (const void*)icm::sweep_block_kernel<1, 4, 0>, (const void*)icm::sweep_block_kernel<1, 4, 1>,
-      (const void*)icm::sweep_block_kernel<1, 6, 0>, (const void*)icm::sweep_block_kernel<1, 6, 1>};
-  for (int x = 0; x < 8; ++x) {
+  using namespace icm;
+  const void* fns[12] = {
+      (const void*)sweep_block_kernel<0, 4, 0, kLayAny>, (const void*)sweep_block_kernel<0, 4, 1, kLayAny>,
+      (const void*)sweep_block_kernel<0, 6, 0, kLayAny>, (const void*)sweep_block_kernel<0, 6, 1, kLayAny>,
+      (const void*)sweep_block_kernel<1, 4, 0, kLayAny>, (const void*)sweep_block_kernel<1, 4, 1, kLayAny>,
+      (const void*)sweep_block_kernel<1, 6, 0, kLayAny>, (const void*)sweep_block_kernel<1, 6, 1, kLayAny>,
+      (const void*)sweep_block_kernel<0, 6, 1, kLayCube8>, (const void*)sweep_block_kernel<1, 6, 1, kLayCube8>,
+      (const void*)sweep_block_kernel<0, 6, 1, kLayChimReg>, (const void*)sweep_block_kernel<1, 6, 1, kLayChimReg>};
+  for (int x = 0; x < 12; ++x) {
     hipError_t r = hipFuncSetAttribute(fns[x], hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (r != hipSuccess) e = r;
   }

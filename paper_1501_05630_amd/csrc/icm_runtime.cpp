@@ -24,7 +24,7 @@
 #include "icm_internal.h"
 
 extern "C" {
-int icmk_launch_sweep(const icm::UnitDesc* d_units, int n_units, int jkind, int deg, int tables,
+int icmk_launch_sweep(const icm::UnitDesc* d_units, int n_units, int jkind, int deg, int tables, int layout,
                       uint32_t n_sweeps, int threads, int icm_slots, size_t lds_bytes,
                       hipStream_t stream);
 int icmk_set_lds_limit(size_t bytes);
@@ -765,8 +765,22 @@ int unit_table(icm_ctx* c, const std::vector<int32_t>& hs, UnitDesc** out) {
   return ICM_OK;
 }
 
+// The cluster-move layout all of the units share (a kernel built for it alone
+// runs them), else kLayAny.
+int group_layout(icm_ctx* c, const std::vector<int32_t>& hs) {
+  int lay = -1;
+  for (int32_t h : hs) {
+    const UnitDesc& u = find(c, h)->unit;
+    const int l = icm::unit_layout(u.topo, u.L, u.deg, u.N);
+    if (lay >= 0 && l != lay) return icm::kLayAny;
+    lay = l;
+  }
+  return lay < 0 ? icm::kLayAny : lay;
+}
+
 int launch_group(icm_ctx* c, const Group& g, uint32_t n_sweeps, bool per_instance, hipStream_t strm) {
   const int threads = class_threads(c->cfg, g.cls);
+  const int layout = group_layout(c, g.handles);
   size_t lds = 0;
   int tables = 1;
   const int slots = effective_slots(c, g.handles, threads, c->cfg.icm_slots, lds, tables);
@@ -781,7 +795,8 @@ int launch_group(icm_ctx* c, const Group& g, uint32_t n_sweeps, bool per_instanc
       if (rc) return rc;
       for (uint32_t done = 0; done < n_sweeps; done += spl) {
         const uint32_t n = std::min(spl, n_sweeps - done);
-        KERNEL_OK(c, icmk_launch_sweep(d, 1, g.jkind, g.deg, tables, n, threads, slots, lds, strm));
+        KERNEL_OK(c, icmk_launch_sweep(d, 1, g.jkind, g.deg, tables, group_layout(c, one), n, threads, slots,
+                                       lds, strm));
       }
     }
     return ICM_OK;
@@ -802,7 +817,7 @@ int launch_group(icm_ctx* c, const Group& g, uint32_t n_sweeps, bool per_instanc
       hipGraph_t graph;
       HIP_OK(c, hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
       for (uint32_t x = 0; x < full; ++x) {
-        int e = icmk_launch_sweep(d, (int)g.handles.size(), g.jkind, g.deg, tables, spl, threads,
+        int e = icmk_launch_sweep(d, (int)g.handles.size(), g.jkind, g.deg, tables, layout, spl, threads,
                                   slots, lds, c->capture_stream);
         if (e) {
           hipGraph_t dummy;
@@ -819,10 +834,12 @@ int launch_group(icm_ctx* c, const Group& g, uint32_t n_sweeps, bool per_instanc
     HIP_OK(c, hipGraphLaunch(it->second, strm));
   } else {
     for (uint32_t x = 0; x < full; ++x)
-      KERNEL_OK(c, icmk_launch_sweep(d, (int)g.handles.size(), g.jkind, g.deg, tables, spl, threads, slots, lds, strm));
+      KERNEL_OK(c, icmk_launch_sweep(d, (int)g.handles.size(), g.jkind, g.deg, tables, layout, spl, threads, slots,
+                                     lds, strm));
   }
   if (rest)
-    KERNEL_OK(c, icmk_launch_sweep(d, (int)g.handles.size(), g.jkind, g.deg, tables, rest, threads, slots, lds, strm));
+    KERNEL_OK(c, icmk_launch_sweep(d, (int)g.handles.size(), g.jkind, g.deg, tables, layout, rest, threads, slots,
+                                   lds, strm));
   return ICM_OK;
 }
 
