@@ -969,7 +969,9 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
   using E_t = typename EnergyT<JK>::T;
   extern __shared__ __align__(16) unsigned char lds[];
   const UnitDesc U = units[blockIdx.x];
-  const int N = U.N, Nc = U.Nc, W = U.W, Wq = U.Wq, K = U.K, R = U.R, Kc = U.Kc, HM = U.HM;
+  // the 8^3 build knows its unit size: 512 sites, 256 of each colour
+  const int N = LAY == kLayCube8 ? 512 : U.N, Nc = LAY == kLayCube8 ? 256 : U.Nc;
+  const int W = U.W, Wq = U.Wq, K = U.K, R = U.R, Kc = U.Kc, HM = U.HM;
   const int Wp = 4 * Wq, G = bit_words(Wq);
   const LdsLayout lay = lds_layout(N, DEG, Wq, K, R, HM, JK, icm_slots, TL,
                                    ((U.flags & kFlagRecord) ? 1 : 0) | ((U.flags & kFlagMeasure) ? 2 : 0), Kc,
