@@ -1121,8 +1121,12 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
         const int nchunk = (Nc + 63) >> 6;
         const bool narrow = nchunk * DEG * WPT < 256;
         const int ntasks = Wqt * nchunk;
-        const int tb = (int)(((long long)ntasks * wave) / nwaves);
-        const int te = (int)(((long long)ntasks * (wave + 1)) / nwaves);
+        // workgroups have 1, 2, 4, 8 or 16 waves: in the 8^3 build the split is
+        // a shift (the other builds measured faster with the division)
+        const int lgw = 31 - __builtin_clz(nwaves);
+        const int tb = LAY == kLayCube8 ? (ntasks * wave) >> lgw : (int)(((long long)ntasks * wave) / nwaves);
+        const int te = LAY == kLayCube8 ? (ntasks * (wave + 1)) >> lgw
+                                        : (int)(((long long)ntasks * (wave + 1)) / nwaves);
         int cur_q = -1;
         int qn = 0;  // tasks this wave has queued for the exact pass (uniform)
         int acc[WPT];  // per lane: sum of e over its accepted flips (dE = 2 e in field units)
