@@ -885,6 +885,62 @@ __device__ __noinline__ void pt_decide(uint32_t at_off, uint32_t energy_off, uin
   }
 }
 
+// Full labelling of a wave's moves for the label readout (rare: only when
+// labels are recorded), one move at a time with the whole wave: union-find
+// over the q = -1 subgraph, roots hooked towards the smaller index, path
+// compression.  Out of line, so that the cluster-move loop does not carry its
+// registers.
+template <int DEG, int TL>
+__device__ __noinline__ void record_labels(uint32_t slots_off, uint32_t parent_off, uint32_t nbr_off,
+                                           const uint16_t* nbr_global, int* labels, int* seeds, int wave, int P,
+                                           int sw, int nw, int N, int nmoves) {
+  wave = uniform(wave); P = uniform(P); sw = uniform(sw); nw = uniform(nw); N = uniform(N);
+  nmoves = uniform(nmoves);
+  const int lane = lane_id();
+  const uint16_t* nbr = TL ? (const uint16_t*)(lds + uniform((int)nbr_off)) : nbr_global;
+  for (int g = 0; g < P; ++g) {
+    const int slot = wave * P + g;
+    uint32_t* mc = (uint32_t*)(lds + uniform((int)slots_off)) + slot * sw + 2 * (nw + 2);
+    const int* info = (const int*)(mc + 3 * nw);
+    const int mvr = info[kInMv];
+    if (mvr < 0) continue;
+    int* parent = (int*)(lds + uniform((int)parent_off)) + slot * N;
+    int* lab = labels + (size_t)mvr * N;
+    const int nown = N > lane ? (N - lane + 63) >> 6 : 0;
+    auto inmask = [&](int j) { return (mc[2 * (j >> 5)] >> (j & 31)) & 1u; };
+    for (int s2 = 0; s2 < nown; ++s2) {
+      const int i = s2 * 64 + lane;
+      if (inmask(i)) parent[i] = i;
+    }
+    wave_sync();
+    for (int s2 = 0; s2 < nown; ++s2) {
+      const int i = s2 * 64 + lane;
+      if (!inmask(i)) continue;
+#pragma unroll
+      for (int d = 0; d < DEG; ++d) {
+        const int jn = TL ? nbr[i * DEG + d] >> 2 : nbr[i * DEG + d];  // LDS copy: byte offsets
+        if (jn > i && inmask(jn)) uf_union(parent, i, jn);
+      }
+    }
+    wave_sync();
+    for (int s2 = 0; s2 < nown; ++s2) {
+      const int i = s2 * 64 + lane;
+      if (inmask(i))
+        __hip_atomic_store(&parent[i], uf_find(parent, i), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    }
+    wave_sync();
+    for (int s2 = 0; s2 < nown; ++s2) {
+      const int i = s2 * 64 + lane;
+      lab[i] = inmask(i) ? uf_load(parent, i) : -1;
+    }
+    if (lane == 0) {
+      seeds[mvr] = info[kInSeed];
+      seeds[nmoves + mvr] = info[kInN];
+    }
+    wave_sync();
+  }
+}
+
 template <int DEG, int QPT>
 __device__ __noinline__ void exact_pass(uint32_t q_off, uint32_t sp_off, int Np, uint32_t nbr_off,
                                         const uint16_t* nbr_global, uint32_t coup_off, const int32_t* coup_global,
@@ -1459,53 +1515,8 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
             }
           }
           wave_sync();
-          if (record) {
-            // full labelling for the readout, one move at a time with the full
-            // wave: union-find over the q = -1 subgraph, roots hooked towards
-            // the smaller index, path compression
-            for (int g = 0; g < P; ++g) {
-              const int slot = wave * P + g;
-              uint32_t* mc = (uint32_t*)(lds + lay.slots) + slot * sw + 2 * (nw + 2);
-              const int* info = (const int*)(mc + 3 * nw);
-              const int mvr = info[kInMv];
-              if (mvr < 0) continue;
-              int* parent = (int*)(lds + lay.parent) + slot * N;
-              int* lab = U.labels + (size_t)mvr * N;
-              const int nown = N > lane ? (N - lane + 63) >> 6 : 0;
-              auto inmask = [&](int j) { return (mc[2 * (j >> 5)] >> (j & 31)) & 1u; };
-              for (int s2 = 0; s2 < nown; ++s2) {
-                const int i = s2 * 64 + lane;
-                if (inmask(i)) parent[i] = i;
-              }
-              wave_sync();
-              for (int s2 = 0; s2 < nown; ++s2) {
-                const int i = s2 * 64 + lane;
-                if (!inmask(i)) continue;
-#pragma unroll
-                for (int d = 0; d < DEG; ++d) {
-                  const int jn = TL ? nbr[i * DEG + d] >> 2 : nbr[i * DEG + d];
-                  if (jn > i && inmask(jn)) uf_union(parent, i, jn);
-                }
-              }
-              wave_sync();
-              for (int s2 = 0; s2 < nown; ++s2) {
-                const int i = s2 * 64 + lane;
-                if (inmask(i))
-                  __hip_atomic_store(&parent[i], uf_find(parent, i), __ATOMIC_RELAXED,
-                                     __HIP_MEMORY_SCOPE_WAVEFRONT);
-              }
-              wave_sync();
-              for (int s2 = 0; s2 < nown; ++s2) {
-                const int i = s2 * 64 + lane;
-                lab[i] = inmask(i) ? uf_load(parent, i) : -1;
-              }
-              if (lane == 0) {
-                U.seeds[mvr] = info[kInSeed];
-                U.seeds[nmoves + mvr] = info[kInN];
-              }
-              wave_sync();
-            }
-          }
+          if (record)
+            record_labels<DEG, TL>(lay.slots, lay.parent, lay.nbr, TL ? nullptr : U.nbr, U.labels, U.seeds, wave, P, sw, nw, N, nmoves);
           // ---- the P clusters grow together, a whole frontier per level ----
           if (cube8) {
             // one word per lane, frontier, mask and cluster kept in registers
