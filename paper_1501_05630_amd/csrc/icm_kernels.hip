@@ -1300,14 +1300,14 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
                 // the lanes that accept, as a lane mask straight from the compare
                 const uint64_t ok = __builtin_amdgcn_ballot_w64(uf < P) & (0ull - (uint64_t)((vmask >> b) & 1u));
                 close = min(close, absdiff(__float_as_uint(uf), __float_as_uint(P)));
-                accept_where(ok, 1u << b, flip, e, acc[b]);
+                accept_where(ok, 1u << (sh + b), flip, e, acc[b]);
               }
               queued = close < kCloseUlps;
               if (queued) {
                 // queue the task for the exact pass at the end of the colour
                 const uint32_t pos = atomicAdd(&exq[0], 1u);
                 exq[2 + 2 * pos] = (uint32_t)i | ((uint32_t)qt << 16);
-                exq[3 + 2 * pos] = flip;
+                exq[3 + 2 * pos] = flip >> sh;
               }
             } else {
               // int8 couplings: the site's couplings packed one per byte (slots
@@ -1340,10 +1340,10 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
                 const uint64_t ok = (__builtin_amdgcn_ballot_w64(e <= 0) |
                                      __builtin_amdgcn_ballot_w64(u[b >> 2].w[b & 3] < th)) &
                                     (0ull - (uint64_t)((vmask >> b) & 1u));
-                accept_where(ok, 1u << b, flip, e, acc[b]);
+                accept_where(ok, 1u << (sh + b), flip, e, acc[b]);
               }
             }
-            if (flip) atomicXor(&row[i], flip << sh);
+            if (flip) atomicXor(&row[i], flip);  // the bits at their places sh + b
             metro_cnt += __popc(flip);
           }
           if constexpr (JK) qn += (int)__popcll(__builtin_amdgcn_ballot_w64(queued));
