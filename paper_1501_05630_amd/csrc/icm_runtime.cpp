@@ -697,7 +697,7 @@ void drop_cached_tables(icm_ctx* c, int32_t h) {
 
 // Groups of instances that share a kernel instantiation (coupling kind, degree).
 struct Group {
-  int jkind, deg, cls;
+  int jkind, deg, cls, layout;  // layout: icm::unit_layout of every unit, or kLayAny for a mix
   std::vector<int32_t> handles;
 };
 
@@ -714,15 +714,19 @@ int class_threads(const icm_run_config& cfg, int cls) {
   return cls == 0 ? 256 : (cls == 1 ? 512 : 1024);
 }
 
+// Units of one size class and coupling kind share a launch; those with a
+// cluster-move layout that has its own kernel build (8^3, chimera register
+// layout) get a launch of their own, so that they run in that build.
 std::vector<Group> group_handles(icm_ctx* c, const int32_t* handles, int n) {
   std::vector<Group> g;
   for (int x = 0; x < n; ++x) {
     Instance* in = find(c, handles[x]);
     const int cls = size_class(in->N);
+    const int lay = icm::unit_layout(in->unit.topo, in->unit.L, in->unit.deg, in->unit.N);
     auto it = std::find_if(g.begin(), g.end(), [&](const Group& q) {
-      return q.jkind == in->jkind && q.deg == in->deg && q.cls == cls;
+      return q.jkind == in->jkind && q.deg == in->deg && q.cls == cls && q.layout == lay;
     });
-    if (it == g.end()) g.push_back({in->jkind, in->deg, cls, {handles[x]}});
+    if (it == g.end()) g.push_back({in->jkind, in->deg, cls, lay, {handles[x]}});
     else it->handles.push_back(handles[x]);
   }
   return g;
@@ -1488,7 +1492,7 @@ void serve_loop(icm_ctx* c) {
     for (auto& g : groups) {
       if (g.running || g.members.empty()) continue;
       uint32_t b = (uint32_t)c->serve_block;
-      Group lg{g.jkind, g.deg, g.cls, {}};
+      Group lg{g.jkind, g.deg, g.cls, icm::kLayAny, {}};
       for (auto& r : g.members) {
         b = std::min(b, r->n_sweeps - r->done_sweeps);
         lg.handles.push_back(r->handle);
