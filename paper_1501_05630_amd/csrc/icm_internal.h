@@ -120,16 +120,18 @@ constexpr uint32_t kCloseUlps = 512;
 
 // Cluster-move layouts a sweep kernel can be built for: kLayAny picks the
 // layout per unit at run time; kLayCube8 (periodic 8^3 lattice, one bitset
-// word per lane), kLayChimReg (chimera of at most 64 words, one word per lane)
-// and kLayLatReg (any other periodic lattice of at most 64 words, one word per
-// lane, grown through the shift program) carry only that layout's code, which
-// frees the registers the other layouts' code would hold.  A launch takes a
-// specialised build when every unit in it has that layout.
-enum : int { kLayAny = 0, kLayCube8 = 1, kLayChimReg = 2, kLayLatReg = 3 };
+// word per lane), kLayChimReg (chimera of at most 64 words, one word per lane),
+// kLayLatReg (any other periodic lattice of at most 64 words, one word per
+// lane, grown through the shift program) and kLayPair (2D L=64 and 3D L=16,
+// two words per lane) carry only that layout's code, which frees the
+// registers the other layouts' code would hold.  A launch takes a specialised
+// build when every unit in it has that layout.
+enum : int { kLayAny = 0, kLayCube8 = 1, kLayChimReg = 2, kLayLatReg = 3, kLayPair = 4 };
 ICM_HD int unit_layout(int topo, int L, int deg, int N) {
   if (deg == 6 && topo == 1 && L == 8) return kLayCube8;
   if (deg == 6 && topo == 2 && site_words(N) <= 64) return kLayChimReg;
   if (topo != 2 && site_words(N) <= 64) return kLayLatReg;
+  if ((deg == 4 && topo == 0 && L == 64) || (deg == 6 && topo == 1 && L == 16)) return kLayPair;
   return kLayAny;
 }
 

@@ -1397,8 +1397,9 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
                          (LAY == kLayAny && DEG == 6 && U.topo == 1 && U.L == 8);  // lpm = 16: one word per lane
       const bool chimreg = LAY == kLayChimReg || (LAY == kLayAny && DEG == 6 && chim && nw <= 64);  // one word per lane
       const bool latreg = LAY == kLayLatReg || (LAY == kLayAny && !chim && !cube8 && nw <= 64);  // periodic lattice, one word per lane
-      const bool sq64 = LAY == kLayAny && DEG == 4 && U.topo == 0 && U.L == 64;  // two words per lane
-      const bool cube16 = LAY == kLayAny && DEG == 6 && U.topo == 1 && U.L == 16;
+      // (a kLayPair build: chim, cube8, chimreg and latreg are all false)
+      const bool sq64 = (LAY == kLayPair && DEG == 4) || (LAY == kLayAny && DEG == 4 && U.topo == 0 && U.L == 64);  // two words per lane
+      const bool cube16 = (LAY == kLayPair && DEG == 6) || (LAY == kLayAny && DEG == 6 && U.topo == 1 && U.L == 16);
       const bool pair = sq64 || cube16;
       const bool record = (flags & kFlagRecord) && s + 1 == n_sweeps;
       // the cluster moves are short dependent chains (growth levels, set-up
@@ -2064,8 +2065,9 @@ int icmk_launch_sweep(const icm::UnitDesc* d_units, int n_units, int jkind, int 
 #define ICM_LAUNCH(JK, DEG, TL, LAY)                                                            \
   hipLaunchKernelGGL((icm::sweep_block_kernel<JK, DEG, TL, LAY>), grid, block, lds_bytes, stream, \
                      d_units, n_sweeps, icm_slots)
-  // the layout builds exist with tables in LDS (what those units use)
-  const int lay = tables ? layout : icm::kLayAny;
+  // the one-word layout builds exist with tables in LDS (what those units
+  // use); the two-word one with the tables in either place
+  const int lay = (tables || layout == icm::kLayPair) ? layout : icm::kLayAny;
   const int sel = (jkind ? 4 : 0) + (deg == 6 ? 2 : 0) + (tables ? 1 : 0);
   if (lay == icm::kLayCube8 && deg == 6) {
     if (jkind) ICM_LAUNCH(1, 6, 1, icm::kLayCube8);
@@ -2073,6 +2075,18 @@ int icmk_launch_sweep(const icm::UnitDesc* d_units, int n_units, int jkind, int 
   } else if (lay == icm::kLayChimReg && deg == 6) {
     if (jkind) ICM_LAUNCH(1, 6, 1, icm::kLayChimReg);
     else ICM_LAUNCH(0, 6, 1, icm::kLayChimReg);
+  } else if (lay == icm::kLayPair && (deg == 4 || deg == 6)) {
+    const int ps = (jkind ? 4 : 0) + (deg == 6 ? 2 : 0) + (tables ? 1 : 0);
+    switch (ps) {
+      case 0: ICM_LAUNCH(0, 4, 0, icm::kLayPair); break;
+      case 1: ICM_LAUNCH(0, 4, 1, icm::kLayPair); break;
+      case 2: ICM_LAUNCH(0, 6, 0, icm::kLayPair); break;
+      case 3: ICM_LAUNCH(0, 6, 1, icm::kLayPair); break;
+      case 4: ICM_LAUNCH(1, 4, 0, icm::kLayPair); break;
+      case 5: ICM_LAUNCH(1, 4, 1, icm::kLayPair); break;
+      case 6: ICM_LAUNCH(1, 6, 0, icm::kLayPair); break;
+      default: ICM_LAUNCH(1, 6, 1, icm::kLayPair); break;
+    }
   } else if (lay == icm::kLayLatReg && (deg == 4 || deg == 6)) {
     if (jkind && deg == 6) ICM_LAUNCH(1, 6, 1, icm::kLayLatReg);
     else if (jkind) ICM_LAUNCH(1, 4, 1, icm::kLayLatReg);
@@ -2099,7 +2113,7 @@ int icmk_launch_sweep(const icm::UnitDesc* d_units, int n_units, int jkind, int 
 int icmk_set_lds_limit(size_t bytes) {
   hipError_t e = hipSuccess;
   using namespace icm;
-  const void* fns[16] = {
+  const void* fns[24] = {
       (const void*)sweep_block_kernel<0, 4, 0, kLayAny>, (const void*)sweep_block_kernel<0, 4, 1, kLayAny>,
       (const void*)sweep_block_kernel<0, 6, 0, kLayAny>, (const void*)sweep_block_kernel<0, 6, 1, kLayAny>,
       (const void*)sweep_block_kernel<1, 4, 0, kLayAny>, (const void*)sweep_block_kernel<1, 4, 1, kLayAny>,
@@ -2107,8 +2121,12 @@ int icmk_set_lds_limit(size_t bytes) {
       (const void*)sweep_block_kernel<0, 6, 1, kLayCube8>, (const void*)sweep_block_kernel<1, 6, 1, kLayCube8>,
       (const void*)sweep_block_kernel<0, 6, 1, kLayChimReg>, (const void*)sweep_block_kernel<1, 6, 1, kLayChimReg>,
       (const void*)sweep_block_kernel<0, 4, 1, kLayLatReg>, (const void*)sweep_block_kernel<1, 4, 1, kLayLatReg>,
-      (const void*)sweep_block_kernel<0, 6, 1, kLayLatReg>, (const void*)sweep_block_kernel<1, 6, 1, kLayLatReg>};
-  for (int x = 0; x < 16; ++x) {
+      (const void*)sweep_block_kernel<0, 6, 1, kLayLatReg>, (const void*)sweep_block_kernel<1, 6, 1, kLayLatReg>,
+      (const void*)sweep_block_kernel<0, 4, 0, kLayPair>, (const void*)sweep_block_kernel<0, 4, 1, kLayPair>,
+      (const void*)sweep_block_kernel<0, 6, 0, kLayPair>, (const void*)sweep_block_kernel<0, 6, 1, kLayPair>,
+      (const void*)sweep_block_kernel<1, 4, 0, kLayPair>, (const void*)sweep_block_kernel<1, 4, 1, kLayPair>,
+      (const void*)sweep_block_kernel<1, 6, 0, kLayPair>, (const void*)sweep_block_kernel<1, 6, 1, kLayPair>};
+  for (int x = 0; x < 24; ++x) {
     hipError_t r = hipFuncSetAttribute(fns[x], hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (r != hipSuccess) e = r;
   }
