@@ -126,6 +126,27 @@ def profiled(name, cfg):
     return None
 
 
+def copy_bandwidth_gbs(nbytes=1 << 30, reps=8):
+    """Measured device-to-device copy bandwidth (read + write bytes / time) of
+    one GiB, timed with HIP events: the practical HBM ceiling beside the
+    vendor peak."""
+    import torch
+    a = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * nbytes * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def cpu_baseline(name, spec, seconds):
     """The CPU oracle on the host cores, over a bounded sample of the workload."""
     import concurrent.futures as cf
@@ -141,9 +162,9 @@ def cpu_baseline(name, spec, seconds):
     # uneven batch is represented)
     picks = [b * spec["n_instances"] // n_inst for b in range(n_inst)]
 
-    def sim(b):
+    def sim(b, flags=oracle.FLAG_2A | oracle.FLAG_PT):
         J, temps, kc, sp = inputs.workload_instance(name, b)
-        o = oracle.Sim(sp["topology"], sp["L"], J, temps, spec["n_replicas"], kc,
+        o = oracle.Sim(sp["topology"], sp["L"], J, temps, spec["n_replicas"], kc, flags=flags,
                        seed=inputs.MASTER_SEED, instance_key=b, j_scale=spec["j_scale"])
         o.init_hot()
         return o, inputs.n_sites(sp["topology"], sp["L"])
@@ -170,6 +191,16 @@ def cpu_baseline(name, spec, seconds):
     t1 = time.perf_counter()
     o.run(s1)
     dt1 = time.perf_counter() - t1
+    # the cluster moves alone, on the states the single-thread run left:
+    # Metropolis and PT switched off (steps 2a and 2b only), one thread
+    ic, _ = sim(picks[0], flags=oracle.FLAG_2A | oracle.FLAG_SKIP_METRO)
+    ic.set_states(o.states())
+    m0 = ic.stats()["icm_moves"]
+    s_icm = max(8, 4 * s1)
+    t2 = time.perf_counter()
+    ic.run(s_icm)
+    dt2 = time.perf_counter() - t2
+    icm_only = (ic.stats()["icm_moves"] - m0) / dt2
     model = ""
     try:
         with open("/proc/cpuinfo") as f:
@@ -179,8 +210,10 @@ def cpu_baseline(name, spec, seconds):
     return {"value": sum(r[1] for r in res) / dt, "unit": "spin-flip attempts/s", "cores": cores,
             "kind": "oracle", "icm_moves_per_s": sum(r[0] for r in res) / dt,
             "single_thread_value": S * N1 * s1 / dt1, "cpu_model": model, "host_cpus": os.cpu_count(),
+            "icm_only_moves_per_s": icm_only,
             "sample": f"{n_inst} instances x {sweeps} sweeps of {name}, one oracle per thread; "
-                      f"single thread: {s1} sweeps of one instance"}
+                      f"single thread: {s1} sweeps of one instance; cluster moves alone (no Metropolis, "
+                      f"no PT) on that instance's states: {s_icm} steps, one thread"}
 
 
 def serve_request(x, rng):
@@ -741,6 +774,10 @@ def main():
                      "algorithmic_bytes_per_launch": per_launch_bytes, "launch_ms": launch_ms,
                      "alu": alu},
     }
+    # the practical HBM ceiling beside the vendor peak (outside the timed region)
+    copy_gbs = copy_bandwidth_gbs()
+    out["roofline"]["measured_copy_gbs"] = copy_gbs
+    out["roofline"]["frac_of_measured_copy"] = achieved_gbs / copy_gbs
     # the cluster moves' own accounting: a move reads both replicas' N spins and
     # writes the |C| flipped sites in both (2 N + 2 <|C|> bytes as int8)
     st = [ctx.icm_read_stats(h) for h in hs]
