@@ -697,7 +697,7 @@ void drop_cached_tables(icm_ctx* c, int32_t h) {
 
 // Groups of instances that share a kernel instantiation (coupling kind, degree).
 struct Group {
-  int jkind, deg, cls, layout;  // layout: icm::unit_layout of every unit, or kLayAny for a mix
+  int jkind, deg, cls, layout;  // layout: icm::unit_layout of its units (kLayAny: mixed, as in serving)
   std::vector<int32_t> handles;
 };
 
@@ -714,9 +714,10 @@ int class_threads(const icm_run_config& cfg, int cls) {
   return cls == 0 ? 256 : (cls == 1 ? 512 : 1024);
 }
 
-// Units of one size class and coupling kind share a launch; those with a
-// cluster-move layout that has its own kernel build (8^3, chimera register
-// layout) get a launch of their own, so that they run in that build.
+// Units of one size class and coupling kind share a launch, split by their
+// cluster-move layout (8^3, chimera of up to 64 words, other one-word
+// lattices, two-word lattices, anything else), so that each layout runs in
+// the kernel build made for it.
 std::vector<Group> group_handles(icm_ctx* c, const int32_t* handles, int n) {
   std::vector<Group> g;
   for (int x = 0; x < n; ++x) {
