@@ -1167,11 +1167,11 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
     if (flags & kFlagSkipMetro) __syncthreads();
     // ---------------- step 1: Metropolis sweep, colour 0 then colour 1 ----------
     if (!(flags & kFlagSkipMetro)) {
-      // A task is one site of one colour for the walkers of QPT Philox quads
-      // (4 QPT walkers in one bit-word): the neighbour words and couplings are
-      // read once for all of them.  Two quads pay off for float couplings (the
-      // per-site part is the larger there), one for integer couplings.
-      constexpr int QPT = JK ? 2 : 1, WPT = 4 * QPT;
+      // A task is one site of one colour for the walkers of QPT = 2 Philox
+      // quads (8 walkers in one byte of a bit-word): the neighbour words and
+      // couplings are read once for all of them, and the two Philox blocks
+      // share their first round's per-lane product.
+      constexpr int QPT = 2, WPT = 4 * QPT;
       const int Wqt = (Wq + QPT - 1) / QPT;
       for (int c = 0; c < 2; ++c) {
         const int nchunk = (Nc + 63) >> 6;
@@ -1325,7 +1325,7 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(const UnitDesc* __res
               }
 #pragma unroll
               for (int d = 0; d < DEG; ++d) {
-                const uint32_t nib = (xw[d] >> sh) & 0xFu;
+                const uint32_t nib = (xw[d] >> sh) & ((1u << WPT) - 1u);
                 if (d < 4) T |= nib << (8 * d);
                 else T2 |= nib << (8 * (d - 4));
               }
