@@ -110,11 +110,11 @@ def launch_tag(cfg):
 # the kernel source (digest) and launch shape they were measured on; the line
 # reports null otherwise.
 PROFILED = {
-    "3d_L8_gauss_1024inst": {"kernel": "db93d609612913a2", "launch": "t256_s16_spl256",
-                             "hbm_bytes_per_launch": 102604382, "valu_insts_per_launch": 8.9388e9,
+    "3d_L8_gauss_1024inst": {"kernel": "deabc0ef5d7c9f14", "launch": "t256_s16_spl256",
+                             "hbm_bytes_per_launch": 102604222, "valu_insts_per_launch": 8.9388e9,
                              "profile": "profiles/sweep_block_kernel_3d_L8_gauss_1024inst.md"},
-    "chimera_C12_int3_512inst": {"kernel": "db93d609612913a2", "launch": "t512_s16_spl256",
-                                 "hbm_bytes_per_launch": 1477820771, "valu_insts_per_launch": 8.5440e9,
+    "chimera_C12_int3_512inst": {"kernel": "deabc0ef5d7c9f14", "launch": "t512_s16_spl256",
+                                 "hbm_bytes_per_launch": 1467544054, "valu_insts_per_launch": 8.0294e9,
                                  "profile": "profiles/sweep_block_kernel_chimera_C12_int3_512inst.md"},
 }
 
